@@ -1,0 +1,180 @@
+/*
+ * wsconv -- FFT-based convolution with radially symmetric weakly singular
+ * kernels on the unit square, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tiwari, Pandey, Paul, Anand, "Fast accurate approximation of
+ * convolutions with weakly singular kernel and its applications".
+ *
+ *   (A u)(x)   = int_D g(x - y) u(y) dy,  D = [0,1]^2            (Section 1, eq. conv)
+ *   (A_n u)(x) = sum_{k in F_n} ghat(k) uhat_{e,n}(k) e^{2 pi i k.x/b}    (Section 2.1, eq. An)
+ *
+ * evaluated at the grid points x_j = j/n, j in [0,n)^2.  The density is
+ * zero-extended to the b-periodic square [0,b]^2 (eq. fc_discrete), its
+ * trapezoidal Fourier coefficients are taken on the nb x nb grid, multiplied
+ * by the kernel moments ghat(k) (Section 2.2, eq. ghat) and transformed back.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays of grid samples are row-major [n][n] with the FIRST index the x1
+ *    coordinate (sample [j1][j2] = u(j1/n, j2/n)); batches are [batch][n][n].
+ *  - Real arrays are float64 (WS_FP64 plans) or float32 (WS_FP32 plans);
+ *    complex arrays are interleaved (re, im) pairs of the same width.
+ *  - Every device pointer must be device memory of the current HIP device,
+ *    aligned to 16 bytes, and is owned by the caller.  The library never
+ *    allocates device memory; the caller sizes buffers with the *_query calls.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued asynchronously on it; calls return without waiting unless the
+ *    description says otherwise.
+ *  - Return value: 0 (WS_OK) on success, a negative WS_E* code on failure;
+ *    nothing is enqueued when a call fails its argument checks.
+ *    conv_last_error() then returns a message (per host thread).
+ *  - A plan may be used from one host thread at a time.
+ */
+#ifndef WSCONV_H
+#define WSCONV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define WS_OK            0
+#define WS_EINVAL       -1   /* invalid argument (sizes, kernel parameters, NULL pointers) */
+#define WS_EUNSUPPORTED -2   /* valid but not supported (FFT length, plan/precision combination) */
+#define WS_EDEVICE      -3   /* a HIP runtime call failed */
+
+/* Kernel families (Section 2.2). */
+#define WS_LOG       0   /* g(x) = scale * log|x|                               */
+#define WS_POWER     1   /* g(x) = scale * |x|^gamma,  -2 < gamma < 0           */
+#define WS_HELMHOLTZ 2   /* g(x) = scale * (i/4) H0^(1)(kappa |x|), kappa > 0   */
+
+/* Arithmetic of the apply. */
+#define WS_FP64 0
+#define WS_FP32 1        /* FFT passes and spectral multiply in float32, twiddles as float32 hi/lo pairs */
+
+/* Fourier-smoothing shapes (Section 2.4). */
+#define WS_FS_NONE   0
+#define WS_FS_DISC   1   /* indicator of the disc |x - c| < size                 */
+#define WS_FS_SQUARE 2   /* indicator of the square |x - c|_inf < size           */
+
+/* Lippmann-Schwinger solver status (ws_ls_info.status). */
+#define WS_LS_CONVERGED 0
+#define WS_LS_MAXIT     1
+#define WS_LS_BREAKDOWN 2
+
+typedef struct {
+    int    family;   /* WS_LOG, WS_POWER or WS_HELMHOLTZ */
+    double scale;    /* multiplies g */
+    double gamma;    /* WS_POWER: exponent, -2 < gamma < 0 */
+    double kappa;    /* WS_HELMHOLTZ: wavenumber > 0 */
+} ws_kernel;
+
+typedef struct {
+    int    n;               /* grid points per side on D; power of two, 16 <= n <= 2048 */
+    int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1); must be 2 */
+    double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
+                               the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the window
+                               [rho + sqrt(2)/2, b - 1/2 - rho] for a density supported in a disc of
+                               radius rho about (1/2, 1/2); an explicit a must satisfy 0 < a < b */
+    double support_radius;  /* informational: radius rho of the density's support about the centre */
+} ws_grid;
+
+/* Fourier smoothing descriptor for one density (Section 2.4, eqs. ls1, tfs).
+ * The density passed to conv_apply is then u_tilde, a smooth extension, and
+ * the operator is applied to u_tilde * chi^n * psi, where chi^n is the
+ * truncated b-periodic Fourier series of the shape's indicator on F_n and
+ * psi(r) = 1 for r <= psi_r1, step((r - psi_r1)/(psi_r2 - psi_r1)) between,
+ * 0 for r >= psi_r2, with r = |x - c| and step(t) = exp(2 e^{-1/t}/(t - 1)).
+ * The centre must be a grid point (n*c1 and n*c2 integers) so chi^n is real. */
+typedef struct {
+    int    shape;          /* WS_FS_NONE, WS_FS_DISC or WS_FS_SQUARE */
+    double c1, c2;         /* centre */
+    double size;           /* disc radius or square half-width */
+    double psi_r1, psi_r2; /* window radii, 0 < psi_r1 < psi_r2 */
+} ws_fs_desc;
+
+typedef struct {
+    int    status;        /* WS_LS_CONVERGED, WS_LS_MAXIT or WS_LS_BREAKDOWN */
+    int    iterations;    /* Arnoldi steps taken (all cycles, all refinements) */
+    int    matvecs;       /* operator applications, including true-residual checks */
+    int    refinements;   /* outer refinement steps (mixed precision), else 0 */
+    double rel_residual;  /* final true relative residual ||u_inc - K u|| / ||u_inc||, in FP64 */
+} ws_ls_info;
+
+typedef struct ws_plan* ws_plan_t;
+
+/* Sizes of the caller-owned buffers for a plan.
+ * plan_bytes: device buffer holding the kernel moments ghat(k) (Section 2.2)
+ *   and the twiddle tables; work_bytes_per_density: device scratch for one
+ *   density in conv_apply (the half-spectrum intermediate).
+ * Returns WS_EINVAL / WS_EUNSUPPORTED for parameters conv_plan would reject. */
+int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
+                    size_t* plan_bytes, size_t* work_bytes_per_density);
+
+/* Build a plan (Section 2.1 discretisation + Section 2.2 moments).
+ * Computes, on the device and in FP64, the moments ghat(k) for every k in
+ * F_n scaled by (nb)^-2, in the layout the apply kernels read, plus the
+ * twiddle tables; all of it is written into plan_buf (plan_bytes, device).
+ * The host-side plan object keeps raw pointers into plan_buf: the caller must
+ * keep plan_buf alive until conv_destroy.  Enqueued on `stream`. */
+int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision,
+              void* plan_buf, void* stream, ws_plan_t* out_plan);
+
+/* Effective truncation radius a of a plan (after defaulting). */
+double conv_plan_radius(ws_plan_t plan);
+
+/* Apply A_n (Section 2.1, eq. An) to `batch` densities.
+ *  density: [batch][n][n] samples u_j; real for WS_LOG / WS_POWER plans,
+ *           complex for WS_HELMHOLTZ plans; element type per the plan precision.
+ *  out:     [batch][n][n] results (A_n u)(x_j), same type as density.  May equal
+ *           density (in place).
+ *  work:    batch * work_bytes_per_density bytes of device scratch.
+ *  fs:      NULL, or a host array of `batch` descriptors; entries with shape
+ *           WS_FS_NONE are applied plainly (Section 2.4 otherwise).
+ * batch = 0 is a no-op. */
+int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work,
+               const ws_fs_desc* fs, void* stream);
+
+/* Device scratch needed by ls_solve for a given restart length. */
+int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* work_bytes);
+
+/* Solve the Nystrom discretisation of the Lippmann-Schwinger equation
+ * (Section 3.3, eq. descretls):  u_j + kappa^2 (A_n(m u))_j = u_inc_j,  j in G_n,
+ * by restarted GMRES(restart) from u = 0 with classical Gram-Schmidt applied
+ * twice and Givens rotations, all in FP64 on the device; the stop test is the
+ * true relative residual ||u_inc - K u||_2 / ||u_inc||_2 <= tol (K = I + kappa^2 A_n M).
+ *  plan:      a WS_HELMHOLTZ plan (kappa from the kernel).
+ *  contrast:  [n][n] float64, m = 1 - mu (device).
+ *  u_inc:     [n][n] complex128 incident field (device).
+ *  u_out:     [n][n] complex128 solution (device).
+ *  mixed_precision: 0 -> FP64 operator throughout; 1 -> iterative refinement: FP64 residual
+ *             and correction, inner GMRES with the FP32 operator (plan precision WS_FP32).
+ *  max_matvecs: bound on operator applications (all cycles).
+ *  work:      ls_solve_query bytes of device scratch.
+ *  info:      host struct, filled on return.
+ * Synchronises `stream` once per restart cycle to read the convergence state.
+ * Returns WS_OK when it converged, 1 (positive) when it stopped at max_matvecs
+ * (u_out holds the last iterate) and WS_LS_BREAKDOWN status with return 2 on a
+ * non-finite residual. */
+int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol,
+             int restart, int max_matvecs, int mixed_precision, void* u_out, void* work,
+             ws_ls_info* info, void* stream);
+
+/* Read back `count` moments ghat(k) (Section 2.2, eq. ghat) of a built plan,
+ * for the integer frequencies (k1[i], k2[i]) in F_n, as computed on the device
+ * (FP64, without the (nb)^-2 factor).  out: host array of 2*count doubles
+ * (real, imaginary).  Synchronises `stream`. */
+int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, double* out, void* stream);
+
+/* Release the host-side plan object (the caller frees plan_buf). */
+void conv_destroy(ws_plan_t plan);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* conv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WSCONV_H */

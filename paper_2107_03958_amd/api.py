@@ -1,0 +1,170 @@
+"""Python binding of libwsconv: argument marshalling around the C-ABI.
+
+PyTorch supplies device memory and the stream; every step of the method runs
+in the HIP kernels of libwsconv.so.
+
+    plan = ConvPlan("log", n=256, scale=1.0)          # moments built on the GPU
+    out = plan.apply(u)                               # u: [batch, n, n] float64 on cuda
+    u, info = ConvPlan("helmholtz", n=256, kappa=20).ls_solve(m, u_inc, tol=1e-8)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_FAMILIES = {"log": L.WS_LOG, "power": L.WS_POWER, "helmholtz": L.WS_HELMHOLTZ}
+_PRECISIONS = {"fp64": L.WS_FP64, "fp32": L.WS_FP32}
+
+
+@dataclass
+class FsDesc:
+    """Fourier smoothing of one density (Section 2.4): shape 'disc' or 'square'."""
+    shape: str
+    c1: float
+    c2: float
+    size: float
+    psi_r1: float
+    psi_r2: float
+
+    def to_c(self) -> L.WsFsDesc:
+        code = {"none": L.WS_FS_NONE, "disc": L.WS_FS_DISC, "square": L.WS_FS_SQUARE}[self.shape]
+        return L.WsFsDesc(code, self.c1, self.c2, self.size, self.psi_r1, self.psi_r2)
+
+
+@dataclass
+class LsInfo:
+    status: int
+    iterations: int
+    matvecs: int
+    refinements: int
+    rel_residual: float
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class ConvPlan:
+    """A plan for A_n with one kernel, grid and precision (conv_plan)."""
+
+    def __init__(self, family: str, n: int, b: int = 2, a: float = 0.0, scale: float = 1.0,
+                 gamma: float = 0.0, kappa: float = 0.0, precision: str = "fp64",
+                 support_radius: float = 0.0, device="cuda", stream=None):
+        self.lib = L.load()
+        self.family = family
+        self.n = n
+        self.b = b
+        self.precision = precision
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.kernel = L.WsKernel(_FAMILIES[family], scale, gamma, kappa)
+        self.grid = L.WsGrid(n, b, a, support_radius)
+        prec = _PRECISIONS[precision]
+        pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        L.check(self.lib.conv_plan_query(ctypes.byref(self.kernel), ctypes.byref(self.grid), prec,
+                                         ctypes.byref(pb), ctypes.byref(wb)))
+        self.plan_bytes = pb.value
+        self.work_bytes = wb.value
+        self.buf = torch.empty(self.plan_bytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.conv_plan(ctypes.byref(self.kernel), ctypes.byref(self.grid), prec,
+                                       _dev_ptr(self.buf), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.a = self.lib.conv_plan_radius(h)
+        self._work = None
+
+    # ------------------------------------------------------------------
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    @property
+    def dtype(self):
+        if self.family == "helmholtz":
+            return torch.complex128 if self.precision == "fp64" else torch.complex64
+        return self.real_dtype
+
+    def workspace(self, batch: int) -> torch.Tensor:
+        need = max(1, batch) * self.work_bytes
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def apply(self, density: torch.Tensor, out: torch.Tensor | None = None, fs=None, work=None,
+              stream=None) -> torch.Tensor:
+        """(A_n u)(x_j) for a [batch, n, n] (or [n, n]) tensor of samples (conv_apply)."""
+        squeeze = density.dim() == 2
+        u = density.unsqueeze(0) if squeeze else density
+        if u.dtype != self.dtype or u.device != self.device or not u.is_contiguous():
+            raise ValueError(f"density must be a contiguous {self.dtype} tensor on {self.device}")
+        if u.shape[-2:] != (self.n, self.n):
+            raise ValueError(f"density must have trailing shape ({self.n}, {self.n})")
+        batch = u.shape[0]
+        if out is None:
+            out = torch.empty_like(u)
+        elif squeeze:
+            out = out.unsqueeze(0)
+        w = work if work is not None else self.workspace(batch)
+        fs_arr = None
+        if fs is not None:
+            if len(fs) != batch:
+                raise ValueError("one smoothing descriptor per density")
+            fs_arr = (L.WsFsDesc * batch)(*[(f.to_c() if f is not None else L.WsFsDesc(0, 0, 0, 0, 0, 0))
+                                            for f in fs])
+        with torch.cuda.device(self.device):
+            L.check(self.lib.conv_apply(self.handle, batch, _dev_ptr(u), _dev_ptr(out), _dev_ptr(w),
+                                        fs_arr, _stream_ptr(stream)))
+        return out[0] if squeeze else out
+
+    def ls_workspace(self, restart: int, mixed: bool) -> torch.Tensor:
+        nbytes = ctypes.c_size_t()
+        L.check(self.lib.ls_solve_query(self.handle, restart, int(mixed), ctypes.byref(nbytes)))
+        return torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+
+    def ls_solve(self, contrast: torch.Tensor, u_inc: torch.Tensor, tol: float = 1e-8, restart: int = 50,
+                 max_matvecs: int = 5000, mixed: bool = False, out: torch.Tensor | None = None,
+                 work: torch.Tensor | None = None, stream=None):
+        """Solve u + kappa^2 A_n(m u) = u_inc (ls_solve); returns (u, LsInfo)."""
+        if contrast.dtype != torch.float64 or u_inc.dtype != torch.complex128:
+            raise ValueError("contrast must be float64 and u_inc complex128")
+        for t in (contrast, u_inc):
+            if t.device != self.device or not t.is_contiguous() or t.shape != (self.n, self.n):
+                raise ValueError(f"inputs must be contiguous ({self.n}, {self.n}) tensors on {self.device}")
+        u = out if out is not None else torch.empty_like(u_inc)
+        w = work if work is not None else self.ls_workspace(restart, mixed)
+        info = L.WsLsInfo()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.ls_solve(self.handle, _dev_ptr(contrast), _dev_ptr(u_inc), tol, restart,
+                                      max_matvecs, int(mixed), _dev_ptr(u), _dev_ptr(w), ctypes.byref(info),
+                                      _stream_ptr(stream)))
+        return u, LsInfo(info.status, info.iterations, info.matvecs, info.refinements, info.rel_residual)
+
+    def moments(self, k1, k2):
+        """Moments ghat(k) at integer frequencies (conv_plan_moments); complex numpy array."""
+        import numpy as np
+        k1 = np.asarray(k1, dtype=np.int32).ravel()
+        k2 = np.asarray(k2, dtype=np.int32).ravel()
+        out = np.zeros(2 * len(k1), dtype=np.float64)
+        L.check(self.lib.conv_plan_moments(
+            self.handle, len(k1), k1.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            k2.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(None)))
+        return out[0::2] + 1j * out[1::2]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.conv_destroy(h)
+            self.handle = None

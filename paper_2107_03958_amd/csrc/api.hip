@@ -1,0 +1,300 @@
+// C-ABI of libwsconv: argument checks, plan-buffer carving and dispatch.
+// The operations are defined in include/wsconv.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "ls.hpp"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return WS_EDEVICE;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_kernel(const ws_kernel* k) {
+  if (!k) return fail(WS_EINVAL, "kernel descriptor is NULL");
+  if (!std::isfinite(k->scale)) return fail(WS_EINVAL, "kernel scale is not finite");
+  switch (k->family) {
+    case WS_LOG: return WS_OK;
+    case WS_POWER:
+      if (!(k->gamma > -2.0 && k->gamma < 0.0)) return fail(WS_EINVAL, "power kernel needs -2 < gamma < 0");
+      return WS_OK;
+    case WS_HELMHOLTZ:
+      if (!(k->kappa > 0.0) || !std::isfinite(k->kappa)) return fail(WS_EINVAL, "Helmholtz kernel needs kappa > 0");
+      return WS_OK;
+    default: return fail(WS_EINVAL, "unknown kernel family");
+  }
+}
+
+int check_grid(const ws_grid* g, double* a_out, int* logn) {
+  if (!g) return fail(WS_EINVAL, "grid descriptor is NULL");
+  if (g->n <= 0 || (g->n & (g->n - 1))) return fail(WS_EUNSUPPORTED, "n must be a power of two");
+  if (g->n < 16 || g->n > 2048) return fail(WS_EUNSUPPORTED, "n must lie in [16, 2048]");
+  if (g->b < 1) return fail(WS_EINVAL, "period b must be a positive integer");
+  if (g->b != 2) return fail(WS_EUNSUPPORTED, "only period b = 2 (FFT length 2n) is implemented");
+  double a = g->a;
+  if (!(a > 0.0)) a = (g->b + std::sqrt(2.0) / 2.0 - 0.5) / 2.0;
+  if (!(a < g->b) || !std::isfinite(a)) return fail(WS_EINVAL, "truncation radius must satisfy 0 < a < b");
+  *a_out = a;
+  int l = 0;
+  while ((1 << l) < g->n) ++l;
+  *logn = l;
+  return WS_OK;
+}
+
+struct Sizes {
+  size_t tw64, tw32, g64, nyq64, g32, nyq32, total, work;
+};
+
+Sizes sizes_for(int n, bool cplx, int precision) {
+  Sizes s{};
+  const size_t nb = 2 * (size_t)n;
+  const size_t te = ws::table_elems(n, cplx);
+  s.tw64 = align_up(nb * 16);
+  s.tw32 = precision == WS_FP32 ? align_up(nb * 8) : 0;   // each of hi and lo
+  s.g64 = align_up(te * (cplx ? 16 : 8));
+  s.nyq64 = cplx ? 0 : align_up((size_t)(n + 1) * 8);
+  s.g32 = precision == WS_FP32 ? align_up(te * (cplx ? 8 : 4)) : 0;
+  s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((size_t)(n + 1) * 4) : 0;
+  s.total = s.tw64 + 2 * s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
+  const size_t elem = precision == WS_FP32 ? 8 : 16;
+  s.work = (size_t)n * (cplx ? 2 * n : n) * elem;
+  return s;
+}
+
+int check_fs(const ws_fs_desc& d, int n) {
+  if (d.shape == WS_FS_NONE) return WS_OK;
+  if (d.shape != WS_FS_DISC && d.shape != WS_FS_SQUARE) return fail(WS_EINVAL, "unknown smoothing shape");
+  if (!(d.size > 0.0)) return fail(WS_EINVAL, "smoothing shape size must be positive");
+  if (!(d.psi_r1 > 0.0 && d.psi_r2 > d.psi_r1)) return fail(WS_EINVAL, "window radii need 0 < psi_r1 < psi_r2");
+  const double e1 = d.c1 * n - std::nearbyint(d.c1 * n), e2 = d.c2 * n - std::nearbyint(d.c2 * n);
+  if (std::fabs(e1) > 1e-9 || std::fabs(e2) > 1e-9)
+    return fail(WS_EUNSUPPORTED, "smoothing centre must be a grid point (n*c integer)");
+  return WS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* conv_last_error(void) { return g_err.c_str(); }
+
+int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision, size_t* plan_bytes,
+                    size_t* work_bytes_per_density) {
+  g_err.clear();
+  int rc = check_kernel(kernel);
+  if (rc) return rc;
+  double a;
+  int logn;
+  if ((rc = check_grid(grid, &a, &logn))) return rc;
+  if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
+  const Sizes s = sizes_for(grid->n, kernel->family == WS_HELMHOLTZ, precision);
+  if (plan_bytes) *plan_bytes = s.total;
+  if (work_bytes_per_density) *work_bytes_per_density = s.work;
+  return WS_OK;
+}
+
+int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void* plan_buf, void* stream,
+              ws_plan_t* out_plan) {
+  g_err.clear();
+  if (!out_plan) return fail(WS_EINVAL, "out_plan is NULL");
+  *out_plan = nullptr;
+  int rc = check_kernel(kernel);
+  if (rc) return rc;
+  double a;
+  int logn;
+  if ((rc = check_grid(grid, &a, &logn))) return rc;
+  if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
+  if (!plan_buf) return fail(WS_EINVAL, "plan buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(plan_buf) % 256) return fail(WS_EINVAL, "plan buffer must be 256-byte aligned");
+  const bool cplx = kernel->family == WS_HELMHOLTZ;
+  const Sizes s = sizes_for(grid->n, cplx, precision);
+  auto* p = new ws_plan();
+  p->kern = *kernel;
+  p->n = grid->n;
+  p->b = grid->b;
+  p->nb = grid->n * grid->b;
+  p->logn = logn;
+  p->a = a;
+  p->precision = precision;
+  p->cplx = cplx;
+  char* base = static_cast<char*>(plan_buf);
+  size_t off = 0;
+  p->tw64 = reinterpret_cast<ws::cx<double>*>(base + off);
+  off += s.tw64;
+  if (precision == WS_FP32) {
+    p->tw32hi = reinterpret_cast<ws::cx<float>*>(base + off);
+    off += s.tw32;
+    p->tw32lo = reinterpret_cast<ws::cx<float>*>(base + off);
+    off += s.tw32;
+  }
+  p->g64 = base + off;
+  off += s.g64;
+  if (!cplx) {
+    p->gnyq64 = reinterpret_cast<double*>(base + off);
+    off += s.nyq64;
+  }
+  if (precision == WS_FP32) {
+    p->g32 = base + off;
+    off += s.g32;
+    if (!cplx) {
+      p->gnyq32 = reinterpret_cast<float*>(base + off);
+      off += s.nyq32;
+    }
+  }
+  p->plan_bytes = s.total;
+  p->work_bytes = s.work;
+  hipError_t e = ws::launch_build_tables(*p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "conv_plan: table kernels");
+  }
+  *out_plan = p;
+  return WS_OK;
+}
+
+double conv_plan_radius(ws_plan_t plan) { return plan ? plan->a : 0.0; }
+
+int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work, const ws_fs_desc* fs,
+               void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(WS_EINVAL, "batch must be >= 0");
+  if (batch == 0) return WS_OK;
+  if (batch > 65535) return fail(WS_EUNSUPPORTED, "batch must be at most 65535 per call");
+  if (!density || !out || !work) return fail(WS_EINVAL, "density, out and work must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(density) | reinterpret_cast<uintptr_t>(out) |
+       reinterpret_cast<uintptr_t>(work)) % 16)
+    return fail(WS_EINVAL, "device buffers must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ws::Plan& p = *plan;
+  const size_t nn = (size_t)p.n * p.n;
+  bool any_fs = false;
+  if (fs) {
+    for (int i = 0; i < batch; ++i) {
+      int rc = check_fs(fs[i], p.n);
+      if (rc) return rc;
+      any_fs = any_fs || fs[i].shape != WS_FS_NONE;
+    }
+  }
+  if (any_fs && p.cplx) return fail(WS_EUNSUPPORTED, "Fourier smoothing is implemented for real kernels only");
+  hipError_t e = hipSuccess;
+  if (!p.cplx) {
+    const size_t esz = p.precision == WS_FP64 ? 8 : 4;
+    const void* src = density;
+    if (any_fs) {
+      // Pre-pass: out_i = u_tilde_i * chi^n_i * psi_i (or a copy of u_i), then apply in place.
+      for (int i = 0; i < batch && e == hipSuccess; ++i) {
+        const char* ui = static_cast<const char*>(density) + i * nn * esz;
+        char* oi = static_cast<char*>(out) + i * nn * esz;
+        if (fs[i].shape != WS_FS_NONE) {
+          if (p.precision == WS_FP64)
+            e = ws::launch_fs_real<double>(p, (const double*)ui, (double*)oi, (ws::cx<double>*)work, fs[i], s);
+          else
+            e = ws::launch_fs_real<float>(p, (const float*)ui, (float*)oi, (ws::cx<float>*)work, fs[i], s);
+        } else if (ui != oi) {
+          e = hipMemcpyAsync(oi, ui, nn * esz, hipMemcpyDeviceToDevice, s);
+        }
+      }
+      src = out;
+    }
+    if (e == hipSuccess) {
+      if (p.precision == WS_FP64)
+        e = ws::launch_apply_real<double>(p, batch, (const double*)src, (double*)out, (ws::cx<double>*)work, s);
+      else
+        e = ws::launch_apply_real<float>(p, batch, (const float*)src, (float*)out, (ws::cx<float>*)work, s);
+    }
+  } else {
+    if (p.precision == WS_FP64)
+      e = ws::launch_apply_cplx<double>(p, batch, (const ws::cx<double>*)density, nullptr, 1.0, false,
+                                        (ws::cx<double>*)out, (ws::cx<double>*)work, s);
+    else
+      e = ws::launch_apply_cplx<float>(p, batch, (const ws::cx<float>*)density, nullptr, 1.0f, false,
+                                       (ws::cx<float>*)out, (ws::cx<float>*)work, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "conv_apply");
+  return WS_OK;
+}
+
+int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* work_bytes) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (!plan->cplx) return fail(WS_EUNSUPPORTED, "ls_solve needs a Helmholtz plan");
+  if (restart < 1 || restart > 200) return fail(WS_EINVAL, "restart must lie in [1, 200]");
+  if (mixed_precision && plan->precision != WS_FP32)
+    return fail(WS_EINVAL, "mixed precision needs a WS_FP32 plan");
+  if (work_bytes) *work_bytes = ws::ls_work_bytes(*plan, restart, mixed_precision != 0);
+  return WS_OK;
+}
+
+int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol, int restart, int max_matvecs,
+             int mixed_precision, void* u_out, void* work, ws_ls_info* info, void* stream) {
+  g_err.clear();
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (!plan->cplx) return fail(WS_EUNSUPPORTED, "ls_solve needs a Helmholtz plan");
+  if (!contrast || !u_inc || !u_out || !work || !info) return fail(WS_EINVAL, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WS_EINVAL, "tol must be positive");
+  if (restart < 1 || restart > 200) return fail(WS_EINVAL, "restart must lie in [1, 200]");
+  if (max_matvecs < 1) return fail(WS_EINVAL, "max_matvecs must be >= 1");
+  if (mixed_precision && plan->precision != WS_FP32)
+    return fail(WS_EINVAL, "mixed precision needs a WS_FP32 plan");
+  std::string err;
+  const int rc = ws::ls_run(*plan, static_cast<const double*>(contrast),
+                            static_cast<const ws::cx<double>*>(u_inc), tol, restart, max_matvecs,
+                            mixed_precision != 0, static_cast<ws::cx<double>*>(u_out), work, info,
+                            static_cast<hipStream_t>(stream), &err);
+  if (rc < 0) return fail(rc, err);
+  return rc;
+}
+
+int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, double* out, void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (count < 0 || (count > 0 && (!k1 || !k2 || !out))) return fail(WS_EINVAL, "bad moment request");
+  const ws::Plan& p = *plan;
+  const int n = p.n, nb = p.nb, CB = ws::Layout<double>::CB;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "conv_plan_moments");
+  const double scale = (double)nb * nb;
+  for (int i = 0; i < count; ++i) {
+    if (k1[i] < -nb / 2 || k1[i] >= nb / 2 || k2[i] < -nb / 2 || k2[i] >= nb / 2)
+      return fail(WS_EINVAL, "frequency outside F_n");
+    const int a1 = std::abs(k1[i]), a2 = std::abs(k2[i]);   // the moments are radial
+    double v[2] = {0.0, 0.0};
+    if (p.cplx) {
+      const size_t idx = ((size_t)(a2 / CB) * (n + 1) + a1) * CB + a2 % CB;
+      e = hipMemcpy(v, static_cast<const char*>(p.g64) + idx * 16, 16, hipMemcpyDeviceToHost);
+    } else if (a2 == n) {
+      e = hipMemcpy(v, p.gnyq64 + a1, 8, hipMemcpyDeviceToHost);
+    } else {
+      const size_t idx = ((size_t)(a2 / CB) * (n + 1) + a1) * CB + a2 % CB;
+      e = hipMemcpy(v, static_cast<const char*>(p.g64) + idx * 8, 8, hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) return hip_fail(e, "conv_plan_moments");
+    out[2 * i] = v[0] * scale;
+    out[2 * i + 1] = v[1] * scale;
+  }
+  return WS_OK;
+}
+
+void conv_destroy(ws_plan_t plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+// Register/LDS Stockham FFT building blocks for gfx950 (64-wide wavefronts).
+//
+// A "line" is one 1D transform of power-of-two length L.  The P = L/E
+// threads that own a line each hold E of its elements in registers; thread p
+// holds elements p + P*s, s in [0, E), both before the first stage and after
+// the last one, so loads from and stores to global memory are coalesced
+// across p.  Radix-R stages (R <= 16) run in registers; between stages the
+// elements are exchanged through LDS (one write, one barrier, one read, one
+// barrier).  Stage (span NS, radix R) is the Stockham autosort step:
+//   butterfly j reads x[j + r L/R], scales by w_{NS R}^{(j mod NS) r},
+//   takes an R-point DFT and writes y[(j/NS) NS R + j mod NS + r NS].
+// A thread may drive NL lines at once (all exchanged with one barrier pair).
+//
+// Twiddles come from a table of exp(-2 pi i m / TWN); the FP32 path keeps
+// each twiddle as a float pair (hi, lo) rounded from FP64 and multiplies by
+// both, so the twiddle itself carries FP64 accuracy.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+namespace ws {
+
+template <typename T> struct cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// LDS index padding: one slot every 16 elements breaks power-of-two strides.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
+
+// ---------------------------------------------------------------------------
+// Twiddle tables.  w(m) = exp(-2 pi i m / TWN); SGN = -1 forward, +1 inverse.
+struct TwD {
+  const cx<double>* t;
+  template <int SGN>
+  __device__ __forceinline__ cx<double> mul(cx<double> x, int m) const {
+    cx<double> w = t[m];
+    return SGN < 0 ? cmul(x, w) : cmulc(x, w);
+  }
+  template <int SGN>
+  __device__ __forceinline__ cx<double> get(int m) const {
+    cx<double> w = t[m];
+    return SGN < 0 ? w : cconj(w);
+  }
+};
+
+struct TwF {
+  const cx<float>* hi;
+  const cx<float>* lo;
+  template <int SGN>
+  __device__ __forceinline__ cx<float> mul(cx<float> x, int m) const {
+    cx<float> h = hi[m], l = lo[m];
+    return SGN < 0 ? cmul(x, h) + cmul(x, l) : cmulc(x, h) + cmulc(x, l);
+  }
+};
+
+template <typename T> struct TwOf;
+template <> struct TwOf<double> { using type = TwD; };
+template <> struct TwOf<float> { using type = TwF; };
+
+// ---------------------------------------------------------------------------
+// Constant twiddles inside the R-point butterflies: w_R^k, R <= 16.
+// cos(2 pi k / 16) for k = 0..4 (exact FP64 roundings).
+constexpr double kC16[5] = {1.0, 0.92387953251128673848, 0.70710678118654752440,
+                            0.38268343236508977173, 0.0};
+
+template <int R, int K>
+struct ConstW {
+  static_assert(16 % R == 0, "radix must divide 16");
+  static constexpr int k16 = (K * (16 / R)) % 16;  // angle in units of 2 pi / 16
+  static constexpr int q = k16 / 4, rr = k16 % 4;   // quadrant and remainder
+  // cos/sin of 2 pi k16/16 built from the first quadrant table.
+  static constexpr double c0 = kC16[rr], s0 = kC16[4 - rr];
+  static constexpr double c = q == 0 ? c0 : q == 1 ? -s0 : q == 2 ? -c0 : s0;
+  static constexpr double s = q == 0 ? s0 : q == 1 ? c0 : q == 2 ? -s0 : -c0;
+};
+
+template <typename T> struct CMul;
+template <> struct CMul<double> {
+  template <int R, int K, int SGN>
+  __device__ __forceinline__ static cx<double> mul(cx<double> x) {
+    using W = ConstW<R, K>;
+    if constexpr (W::k16 == 0) return x;
+    else if constexpr (W::k16 == 4) return SGN < 0 ? cx<double>{x.y, -x.x} : cx<double>{-x.y, x.x};
+    else if constexpr (W::k16 == 8) return {-x.x, -x.y};
+    else if constexpr (W::k16 == 12) return SGN < 0 ? cx<double>{-x.y, x.x} : cx<double>{x.y, -x.x};
+    else {
+      constexpr double c = W::c, s = SGN < 0 ? -W::s : W::s;   // exp(SGN 2 pi i k/R)
+      return {x.x * c - x.y * s, x.x * s + x.y * c};
+    }
+  }
+};
+template <> struct CMul<float> {
+  template <int R, int K, int SGN>
+  __device__ __forceinline__ static cx<float> mul(cx<float> x) {
+    using W = ConstW<R, K>;
+    if constexpr (W::k16 == 0) return x;
+    else if constexpr (W::k16 == 4) return SGN < 0 ? cx<float>{x.y, -x.x} : cx<float>{-x.y, x.x};
+    else if constexpr (W::k16 == 8) return {-x.x, -x.y};
+    else if constexpr (W::k16 == 12) return SGN < 0 ? cx<float>{-x.y, x.x} : cx<float>{x.y, -x.x};
+    else {
+      constexpr double cd = W::c, sd = SGN < 0 ? -W::s : W::s;
+      constexpr float ch = (float)cd, sh = (float)sd;
+      constexpr float cl = (float)(cd - (double)ch), sl = (float)(sd - (double)sh);
+      cx<float> a = {x.x * ch - x.y * sh, x.x * sh + x.y * ch};
+      cx<float> b = {x.x * cl - x.y * sl, x.x * sl + x.y * cl};
+      return a + b;
+    }
+  }
+};
+
+// Last radix-2 step of an R-point DFT: v[k] = e[k] + w^k o[k], v[k+R/2] = e[k] - w^k o[k].
+template <int R, int SGN, typename T>
+struct Combine {
+  template <int... K>
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>* e, const cx<T>* o,
+                                             std::integer_sequence<int, K...>) {
+    ((one<K>(v, e, o)), ...);
+  }
+  template <int K>
+  __device__ __forceinline__ static void one(cx<T>* v, const cx<T>* e, const cx<T>* o) {
+    const cx<T> t = CMul<T>::template mul<R, K, SGN>(o[K]);
+    v[K] = e[K] + t;
+    v[K + R / 2] = e[K] - t;
+  }
+};
+
+// In-register R-point DFT (radix-2 decimation in time), SGN = -1 forward.
+template <int R, int SGN, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else {
+    cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) { e[i] = v[2 * i]; o[i] = v[2 * i + 1]; }
+    dft<R / 2, SGN>(e);
+    dft<R / 2, SGN>(o);
+    Combine<R, SGN, T>::run(v, e, o, std::make_integer_sequence<int, R / 2>{});
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix plan for a line of length L with E elements per thread.
+template <int L, int E, int NS>
+struct Radix {
+  static constexpr int RMAX = E < 16 ? E : 16;
+  static constexpr int REM = L / NS;
+  static constexpr int R = REM < RMAX ? REM : RMAX;   // radix of stage with span NS
+};
+
+// Position s (element p + P*s) of register slot `reg` for a stage of radix R.
+template <int E, int R>
+__host__ __device__ constexpr int slot_elem(int reg) { return reg / R + (reg % R) * (E / R); }
+
+// Radix of the first and the last stage.
+template <int L, int E> struct FirstLast {
+  static constexpr int R0 = Radix<L, E, 1>::R;
+  static constexpr int last_ns() {
+    int ns = 1;
+    while (ns * Radix<L, E, 1>::RMAX < L) ns *= Radix<L, E, 1>::RMAX;
+    return ns;
+  }
+  static constexpr int RL = L / last_ns();
+};
+
+// Butterflies of one stage on every line a thread holds.
+template <int L, int E, int NL, int R, int NS, int SGN, typename T, typename TW>
+__device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW& tw, int twstep) {
+  constexpr int P = L / E;
+#pragma unroll
+  for (int q = 0; q < E / R; ++q) {
+    const int j = p + q * P;
+    if constexpr (NS > 1) {
+      const int jm = j % NS;
+      const int unit = (L / (NS * R)) * twstep;   // w_{NS R} in table units
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int m = jm * r * unit;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) v[l][q * R + r] = tw.template mul<SGN>(v[l][q * R + r], m);
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) dft<R, SGN>(&v[l][q * R]);
+  }
+}
+
+// Exchange through LDS between stage (R, NS) and the next stage of radix R2.
+template <int L, int E, int NL, int R, int NS, int R2, typename T>
+__device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], cx<T>* const* lds, int p) {
+  constexpr int P = L / E;
+#pragma unroll
+  for (int q = 0; q < E / R; ++q) {
+    const int j = p + q * P;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int l = 0; l < NL; ++l) lds[l][pad(base + r * NS)] = v[l][q * R + r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E / R2; ++q) {
+    const int j = p + q * P;
+#pragma unroll
+    for (int r = 0; r < R2; ++r)
+#pragma unroll
+      for (int l = 0; l < NL; ++l) v[l][q * R2 + r] = lds[l][pad(j + r * (L / R2))];
+  }
+  __syncthreads();
+}
+
+template <int L, int E, int NL, int SGN, int NS, typename T, typename TW>
+__device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,
+                                           int twstep) {
+  constexpr int R = Radix<L, E, NS>::R;
+  stage_compute<L, E, NL, R, NS, SGN>(v, p, tw, twstep);
+  if constexpr (NS * R < L) {
+    constexpr int R2 = Radix<L, E, NS * R>::R;
+    exchange<L, E, NL, R, NS, R2>(v, lds, p);
+    run_stages<L, E, NL, SGN, NS * R>(v, lds, p, tw, twstep);
+  }
+}
+
+// Full transform of NL lines of length L.  On entry register slot `reg` holds
+// element p + P*slot_elem<E,R0>(reg); on exit element p + P*slot_elem<E,RL>(reg).
+// twstep = TWN / L.  Uses the LDS line buffers lds[l] (padded(L) elements each)
+// and contains __syncthreads(): every thread of the block must call it.
+template <int L, int E, int NL, int SGN, typename T, typename TW>
+__device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,
+                                          int twstep) {
+  run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep);
+}
+
+// Re-order registers from the last-stage layout (radix RA) to the first-stage
+// layout (radix RB) without moving data between threads.
+template <int E, int RA, int RB, int NL, typename T>
+__device__ __forceinline__ void relayout(cx<T> (&v)[NL][E]) {
+  if constexpr (RA != RB) {
+    cx<T> tmp[NL][E];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int r = 0; r < E; ++r) tmp[l][r] = v[l][r];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int rb = 0; rb < E; ++rb) {
+        // slot rb (layout RB) holds element s; find its slot in layout RA.
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int s = slot_elem<E, RB>(rb);
+        const int ra = (s % (E / RA)) * RA + s / (E / RA);
+        v[l][rb] = tmp[l][ra];
+      }
+  }
+}
+
+}  // namespace ws

@@ -1,0 +1,18 @@
+// Lippmann-Schwinger Nystrom solver (Section 3.3, eq. descretls) on the device.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "plan.hpp"
+
+namespace ws {
+
+size_t ls_work_bytes(const Plan& p, int restart, bool mixed);
+
+// Solve (I + kappa^2 A_n M) u = u_inc.  Returns WS_OK, 1 (max_matvecs reached),
+// 2 (breakdown: non-finite values) or a negative WS_E* code with *err set.
+int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart, int max_matvecs,
+           bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s, std::string* err);
+
+}  // namespace ws

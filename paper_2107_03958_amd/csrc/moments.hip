@@ -1,0 +1,247 @@
+// Plan construction on the device, in FP64: the kernel moments ghat(k)
+// (Section 2.2, eq. ghat) for every k in F_n, scaled by the trapezoid factor
+// (nb)^-2 and written in the blocked layout the column pass reads, and the
+// twiddle table exp(-2 pi i m / nb).
+//
+//   ghat(k) = 2 pi int_0^a g(rho) J0(xi rho) rho d rho,  xi = 2 pi |k| / b
+//
+// log |x|:        closed form of Section 2.2 (stated for -(1/2pi) log|x|).
+// Helmholtz:      closed form of Section 2.2 (stated for (i/4) H0^(1)); the
+//                 |k| = 0 line uses -2/(kappa pi): the printed +2/(kappa pi) is
+//                 not the k -> 0 limit of the generic line.  The resonance line
+//                 is used when |xi - kappa| <= 1e-9 kappa.
+// |x|^gamma:      for z = xi a < 48 the numerical moment of Section 2.2: the
+//                 substitution rho = tau^p (p chosen so tau^(p(2+gamma)-1) is a
+//                 polynomial when gamma is rational with a small denominator)
+//                 and Fejer's first rule (the paper's "Clenshaw-Curtis" nodes
+//                 x_j = alpha/2 (1 + cos((j - 1/2) pi / n_pc)) with its weights),
+//                 on panels graded away from rho = 0 and no longer than half a
+//                 period of J0.  For z >= 48 the closed form of Section 2.2,
+//                 written as Gamma-ratio term minus the tail
+//                 int_a^inf rho^(1+gamma) J0(xi rho) d rho, whose Lommel-function
+//                 factors are evaluated by their asymptotic series (optimally
+//                 truncated; below 1e-17 relative for z >= 48).
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace ws {
+
+struct KernelArgs {
+  int family;
+  double scale, gamma, kappa, a, b;
+  // Helmholtz constants at kappa a.
+  double j0ka, j1ka, y0ka, y1ka;
+  // power kernels
+  int p;              // substitution exponent
+  double ginf_coef;   // 2^(1+gamma) Gamma(1+gamma/2) / Gamma(-gamma/2)
+};
+
+__device__ inline double log_moment(double kabs, const KernelArgs& K) {
+  // moments of -(1/2pi) log|x|
+  const double a = K.a;
+  if (kabs == 0.0) return a * a / 4.0 * (1.0 - 2.0 * log(a));
+  const double xi = 2.0 * M_PI * kabs / K.b;
+  const double z = xi * a;
+  return -a * log(a) * j1(z) / xi + (1.0 - j0(z)) / (xi * xi);
+}
+
+__device__ inline cx<double> helmholtz_moment(double kabs, const KernelArgs& K) {
+  const double a = K.a, kap = K.kappa, ka = kap * a;
+  const cx<double> h0 = {K.j0ka, K.y0ka}, h1 = {K.j1ka, K.y1ka};
+  if (kabs == 0.0) {
+    const double f = M_PI / (2.0 * kap);
+    return {f * (-a * K.y1ka - 2.0 / (kap * M_PI)), f * (a * K.j1ka)};
+  }
+  const double xi = 2.0 * M_PI * kabs / K.b;
+  if (fabs(xi - kap) <= 1e-9 * kap) {
+    // (i/4) pi a^2 (J0 H0 + J1 H1)(kappa a)
+    const cx<double> s = {K.j0ka * h0.x + K.j1ka * h1.x, K.j0ka * h0.y + K.j1ka * h1.y};
+    const double f = 0.25 * M_PI * a * a;
+    return {-f * s.y, f * s.x};
+  }
+  const double z = xi * a;
+  const double jz0 = j0(z), jz1 = j1(z);
+  // num = z J1(z) H0 - ka J0(z) H1 - 2i/pi
+  const cx<double> num = {z * jz1 * h0.x - ka * jz0 * h1.x, z * jz1 * h0.y - ka * jz0 * h1.y - 2.0 / M_PI};
+  const double den = xi * xi - kap * kap;
+  // (i pi / 2) num / den
+  const double f = 0.5 * M_PI / den;
+  return {-f * num.y, f * num.x};
+}
+
+// Fejer's first rule on [0, 1]: node j (1-based) and weight.
+__device__ inline void fejer_node(int j, int npc, double* x, double* w) {
+  const double th = (j - 0.5) * M_PI / npc;
+  *x = 0.5 * (1.0 + cos(th));
+  double s = 1.0;                                    // k = 0 term, halved: (1/2) * 2
+  for (int k = 2; k <= npc; k += 2) s += -2.0 / ((double)k * k - 1.0) * cos(k * th);
+  *w = s / npc;                                       // alpha / n_pc with alpha = 1
+}
+
+// int_0^a rho^mu J0(xi rho) d rho by the substitution + Fejer rule (z < 48).
+__device__ double power_moment_quad(double xi, double mu, const KernelArgs& K) {
+  const double a = K.a;
+  const int p = K.p;
+  const int npc1 = 48, npc = 24;
+  const double rho1 = xi > 0.0 ? fmin(a, 0.5 / xi) : a;
+  // First panel in tau = rho^(1/p): p tau^(p(mu+1)-1) J0(xi tau^p) d tau.
+  const double al = pow(rho1, 1.0 / p);
+  const double ex = p * (mu + 1.0) - 1.0;
+  double tot = 0.0;
+  for (int j = 1; j <= npc1; ++j) {
+    double x, w;
+    fejer_node(j, npc1, &x, &w);
+    const double tau = al * x;
+    const double tp = pow(tau, (double)p);
+    tot += w * (ex == 0.0 ? 1.0 : pow(tau, ex)) * j0(xi * tp);
+  }
+  tot *= p * al;
+  double lo = rho1;
+  const double hp = xi > 0.0 ? M_PI / xi : a;
+  while (lo < a * (1.0 - 1e-15)) {
+    const double hi = fmin(a, fmin(2.0 * lo, lo + hp));
+    double part = 0.0;
+    for (int j = 1; j <= npc; ++j) {
+      double x, w;
+      fejer_node(j, npc, &x, &w);
+      const double r = lo + (hi - lo) * x;
+      part += w * pow(r, mu) * j0(xi * r);
+    }
+    tot += (hi - lo) * part;
+    lo = hi;
+  }
+  return tot;
+}
+
+// int_0^a rho^mu J0(xi rho) d rho = G_inf - tail for z = xi a >= 48.
+__device__ double power_moment_asym(double xi, double mu, const KernelArgs& K) {
+  const double a = K.a, z = xi * a, zz = z * z;
+  const double jz0 = j0(z), jz1 = j1(z);
+  // term m: (-1)^m P_m / z^(2m) [J1/z + (mu - 2m - 1) J0 / z^2],  P_m = prod_{l<m} (mu - 2l - 1)^2
+  double s = 0.0, f = 1.0;
+  for (int m = 0; m < 400; ++m) {
+    const double c = mu - 2.0 * m - 1.0;
+    const double t = f * (jz1 / z + c * jz0 / zz);
+    s += (m & 1) ? -t : t;
+    const double bound = f * (fabs(jz1) / z + fabs(c) * fabs(jz0) / zz + 1.0 / zz);
+    if (bound <= 1e-18 * fabs(s)) break;
+    const double ratio = c * c / zz;
+    if (ratio >= 1.0) break;                        // smallest term reached: optimal truncation
+    f *= ratio;
+  }
+  const double tail = -pow(a, mu + 1.0) * s;
+  const double ginf = K.ginf_coef * pow(xi, -(1.0 + mu));
+  return ginf - tail;
+}
+
+__device__ inline double power_moment(double kabs, const KernelArgs& K) {
+  // 2 pi int_0^a rho^gamma J0 rho d rho for g = |x|^gamma
+  const double mu = 1.0 + K.gamma;
+  if (kabs == 0.0) return 2.0 * M_PI * pow(K.a, mu + 1.0) / (mu + 1.0);
+  const double xi = 2.0 * M_PI * kabs / K.b;
+  const double z = xi * K.a;
+  return 2.0 * M_PI * (z < 48.0 ? power_moment_quad(xi, mu, K) : power_moment_asym(xi, mu, K));
+}
+
+// Moment of scale * g at |k|, times inv = nb^-2.
+__device__ inline cx<double> moment(double kabs, const KernelArgs& K, double inv) {
+  if (K.family == WS_LOG) return {-2.0 * M_PI * K.scale * log_moment(kabs, K) * inv, 0.0};
+  if (K.family == WS_POWER) return {K.scale * power_moment(kabs, K) * inv, 0.0};
+  const cx<double> h = helmholtz_moment(kabs, K);
+  return {K.scale * h.x * inv, K.scale * h.y * inv};
+}
+
+// Blocked table: entry (cb, k1f, c) <-> column bin k2 = cb*CB + c, folded row k1f in [0, n].
+template <int CB>
+__global__ void k_table(int n, int ncols, KernelArgs K, double inv, int cplx, double* g64, float* g32,
+                        double* nyq64, float* nyq32) {
+  const size_t total = (size_t)ncols * (n + 1);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % CB);
+    const size_t rest = e / CB;
+    const int k1f = (int)(rest % (n + 1));
+    const int cb = (int)(rest / (n + 1));
+    int k2 = cb * CB + c;
+    const int nb = 2 * n;
+    if (k2 > n) k2 = nb - k2;                        // |k2| of bin k2
+    const double kabs = sqrt((double)k1f * k1f + (double)k2 * k2);
+    const cx<double> v = moment(kabs, K, inv);
+    if (cplx) {
+      if (g64) reinterpret_cast<cx<double>*>(g64)[e] = v;
+      if (g32) reinterpret_cast<cx<float>*>(g32)[e] = {(float)v.x, (float)v.y};
+    } else {
+      if (g64) g64[e] = v.x;
+      if (g32) g32[e] = (float)v.x;
+    }
+  }
+  // Nyquist column k2 = n of the real path.
+  if (nyq64 || nyq32) {
+    for (int k1f = blockIdx.x * blockDim.x + threadIdx.x; k1f <= n; k1f += gridDim.x * blockDim.x) {
+      const double kabs = sqrt((double)k1f * k1f + (double)n * n);
+      const double v = moment(kabs, K, inv).x;
+      if (nyq64) nyq64[k1f] = v;
+      if (nyq32) nyq32[k1f] = (float)v;
+    }
+  }
+}
+
+__global__ void k_twiddles(int nb, cx<double>* t64, cx<float>* hi, cx<float>* lo) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nb; m += gridDim.x * blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)m / nb, &s, &c);         // exp(-2 pi i m / nb)
+    t64[m] = {c, s};
+    if (hi) {
+      const float ch = (float)c, sh = (float)s;
+      hi[m] = {ch, sh};
+      lo[m] = {(float)(c - (double)ch), (float)(s - (double)sh)};
+    }
+  }
+}
+
+static int choose_p(double gamma) {
+  // smallest p in [1, 16] with p (2 + gamma) an integer >= 1, else 16
+  for (int p = 1; p <= 16; ++p) {
+    const double v = p * (2.0 + gamma);
+    if (v >= 1.0 - 1e-12 && fabs(v - nearbyint(v)) < 1e-9) return p;
+  }
+  return 16;
+}
+
+hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
+  KernelArgs K{};
+  K.family = pl.kern.family;
+  K.scale = pl.kern.scale;
+  K.gamma = pl.kern.gamma;
+  K.kappa = pl.kern.kappa;
+  K.a = pl.a;
+  K.b = pl.b;
+  if (K.family == WS_HELMHOLTZ) {
+    const double ka = K.kappa * K.a;
+    K.j0ka = ::j0(ka);
+    K.j1ka = ::j1(ka);
+    K.y0ka = ::y0(ka);
+    K.y1ka = ::y1(ka);
+  }
+  if (K.family == WS_POWER) {
+    K.p = choose_p(K.gamma);
+    K.ginf_coef = std::pow(2.0, 1.0 + K.gamma) * std::tgamma(1.0 + K.gamma / 2.0) / std::tgamma(-K.gamma / 2.0);
+  }
+  const int n = pl.n, nb = pl.nb;
+  const double inv = 1.0 / ((double)nb * nb);
+  const int threads = 256;
+  k_twiddles<<<(nb + threads - 1) / threads, threads, 0, s>>>(nb, pl.tw64, pl.tw32hi, pl.tw32lo);
+  const int ncols = pl.cplx ? 2 * n : n;
+  const size_t total = (size_t)ncols * (n + 1);
+  const int blocks = (int)std::min<size_t>((total + threads - 1) / threads, 65536);
+  const int cp = pl.cplx ? 1 : 0;
+  // FP64 table (every plan: FP64 applies, the refinement residual of mixed solves).
+  k_table<Layout<double>::CB><<<blocks, threads, 0, s>>>(n, ncols, K, inv, cp, (double*)pl.g64, nullptr,
+                                                         pl.cplx ? nullptr : pl.gnyq64, nullptr);
+  if (pl.precision == WS_FP32)
+    k_table<Layout<float>::CB><<<blocks, threads, 0, s>>>(n, ncols, K, inv, cp, nullptr, (float*)pl.g32,
+                                                          nullptr, pl.cplx ? nullptr : pl.gnyq32);
+  return hipGetLastError();
+}
+
+}  // namespace ws

@@ -1,0 +1,62 @@
+// Host-side plan object and internal launch interfaces of libwsconv.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "../../include/wsconv.h"
+#include "fft_core.hpp"
+
+namespace ws {
+
+// Column-block width of the blocked half-spectrum layout T[cb][row][c]: a
+// column pass reads one contiguous block of n rows x CB columns, and a row
+// pass over RPB rows writes RPB*CB contiguous elements per block (128 bytes).
+template <typename T> struct Layout;
+template <> struct Layout<double> { static constexpr int CB = 2; static constexpr int RPB = 4; };
+template <> struct Layout<float> { static constexpr int CB = 4; static constexpr int RPB = 4; };
+
+struct Plan {
+  ws_kernel kern;
+  int n = 0, b = 2, nb = 0, logn = 0;
+  double a = 0;
+  int precision = WS_FP64;
+  bool cplx = false;          // Helmholtz: complex densities, c2c path
+  // Device pointers into the caller's plan buffer.
+  void* g64 = nullptr;        // moments / nb^2, FP64 (real or complex), blocked layout
+  double* gnyq64 = nullptr;   // real path: column k2 = nb/2 (Nyquist), rows k1' in [0, n]
+  void* g32 = nullptr;        // FP32 copy (WS_FP32 plans)
+  float* gnyq32 = nullptr;
+  cx<double>* tw64 = nullptr; // exp(-2 pi i m / nb), m in [0, nb)
+  cx<float>* tw32hi = nullptr;
+  cx<float>* tw32lo = nullptr;
+  size_t plan_bytes = 0;
+  size_t work_bytes = 0;      // per density
+};
+
+// Sizes (in elements) of the moment tables for a plan.
+inline size_t table_elems(int n, bool cplx) {
+  // real path: n columns + a Nyquist column stored apart; complex path: 2n columns.
+  return (size_t)(n + 1) * (cplx ? 2 * n : n);
+}
+
+// Launchers (apply.hip).  Each returns the hipError_t of its launches.
+// Real path (WS_LOG / WS_POWER): out = A_n u for `batch` real densities.
+template <typename T>
+hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s);
+// Fourier-smoothing pre-pass (real path): out = u_tilde * Re(chi^n) * psi for one density.
+template <typename T>
+hipError_t launch_fs_real(const Plan& p, const T* u_tilde, T* out, cx<T>* work, const ws_fs_desc& fs,
+                          hipStream_t s);
+// Complex path (WS_HELMHOLTZ): out = [add_input ? v : 0] + alpha * A_n(m .* v), m optional.
+// skip: optional device flag; when it reads nonzero the kernels return at entry.
+template <typename T>
+hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add_input,
+                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr);
+
+// Plan construction kernels (moments.hip).
+hipError_t launch_build_tables(Plan& p, hipStream_t s);
+
+}  // namespace ws
+
+// The opaque handle of the C-ABI is the plan itself.
+struct ws_plan : public ws::Plan {};

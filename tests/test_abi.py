@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad
+arguments on the host (no GPU needed: none of these calls reaches the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2107_03958_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2107_03958_amd import build
+        build.build(jobs=8)
+    return L.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "wsconv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|double|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"conv_plan", "conv_apply", "ls_solve", "conv_destroy", "conv_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS), "binding and header disagree"
+
+
+def _query(lib, family=L.WS_LOG, n=64, b=2, a=0.0, gamma=0.0, kappa=0.0, prec=L.WS_FP64):
+    k = L.WsKernel(family, 1.0, gamma, kappa)
+    g = L.WsGrid(n, b, a, 0.0)
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = lib.conv_plan_query(ctypes.byref(k), ctypes.byref(g), prec, ctypes.byref(pb), ctypes.byref(wb))
+    return rc, pb.value, wb.value
+
+
+def test_plan_query_sizes(lib):
+    rc, pb, wb = _query(lib, n=2048)
+    assert rc == L.WS_OK
+    assert wb == 2048 * 2048 * 16                    # half spectrum, complex128
+    assert pb >= 2048 * 2049 * 8                     # FP64 moment table
+    rc, pb32, wb32 = _query(lib, n=2048, prec=L.WS_FP32)
+    assert rc == 0 and wb32 == wb // 2 and pb32 > pb
+    rc, pbh, wbh = _query(lib, family=L.WS_HELMHOLTZ, kappa=20.0, n=1024)
+    assert rc == 0 and wbh == 1024 * 2048 * 16
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=100), L.WS_EUNSUPPORTED),
+    (dict(n=8), L.WS_EUNSUPPORTED),
+    (dict(n=4096), L.WS_EUNSUPPORTED),
+    (dict(b=3), L.WS_EUNSUPPORTED),
+    (dict(b=0), L.WS_EINVAL),
+    (dict(a=2.5), L.WS_EINVAL),
+    (dict(family=L.WS_POWER, gamma=0.5), L.WS_EINVAL),
+    (dict(family=L.WS_POWER, gamma=-2.0), L.WS_EINVAL),
+    (dict(family=L.WS_HELMHOLTZ, kappa=0.0), L.WS_EINVAL),
+    (dict(family=7), L.WS_EINVAL),
+    (dict(prec=5), L.WS_EINVAL),
+])
+def test_plan_query_rejects(lib, kw, code):
+    rc, _, _ = _query(lib, **kw)
+    assert rc == code
+    assert lib.conv_last_error().decode()
+
+
+def test_null_handles_rejected(lib):
+    assert lib.conv_apply(None, 1, None, None, None, None, None) == L.WS_EINVAL
+    assert b"plan" in lib.conv_last_error()
+    nb = ctypes.c_size_t()
+    assert lib.ls_solve_query(None, 50, 0, ctypes.byref(nb)) == L.WS_EINVAL
+    info = L.WsLsInfo()
+    assert lib.ls_solve(None, None, None, 1e-8, 50, 100, 0, None, None, ctypes.byref(info), None) == L.WS_EINVAL
+    h = ctypes.c_void_p()
+    k = L.WsKernel(L.WS_LOG, 1.0, 0.0, 0.0)
+    g = L.WsGrid(64, 2, 0.0, 0.0)
+    assert lib.conv_plan(ctypes.byref(k), ctypes.byref(g), L.WS_FP64, None, None, ctypes.byref(h)) == L.WS_EINVAL
+    assert lib.conv_plan_radius(None) == 0.0
+    lib.conv_destroy(None)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(ImportError):
+        L._lib_backup = L._lib
+        try:
+            L._lib = None
+            L.load(str(tmp_path / "missing.so"))
+        finally:
+            L._lib = L._lib_backup

@@ -1,0 +1,226 @@
+"""GPU path vs the CPU oracle, element by element, through the C-ABI.
+
+Bar: FP64 relative L-infinity (eq. rel-err form) <= 1e-12; FP32 relative
+L-infinity <= 2e-6 and relative L2 <= 5e-7 against the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ls as ols
+from oracle import metrics, moments, scheme, smoothing
+from tests.gpu_common import A_DEFAULT, B, oracle_table, plan_kwargs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2107_03958_amd import api as _api
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return _api
+
+
+def _gpu(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def test_config0_single_apply(api):
+    n = 64
+    u = synth.bump_density(n)
+    plan = api.ConvPlan(n=n, **plan_kwargs("laplace"))
+    assert abs(plan.a - A_DEFAULT) < 1e-15
+    got = plan.apply(_gpu(u, torch.float64)).cpu().numpy()
+    ref = np.real(scheme.apply(u, oracle_table("laplace", n), B))
+    assert metrics.rel_linf(got, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kname", ["log", "pow-1/2", "pow-1/3"])
+@pytest.mark.parametrize("n", [16, 32, 128, 256])
+def test_real_apply_batch(api, kname, n):
+    us = np.stack([synth.smooth_density(n, 1000 + i) for i in range(3)])
+    plan = api.ConvPlan(n=n, **plan_kwargs(kname))
+    got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    g = oracle_table(kname, n)
+    for i in range(3):
+        ref = np.real(scheme.apply(us[i], g, B))
+        assert metrics.rel_linf(got[i], ref) <= FP64_TOL, (kname, n, i)
+
+
+@pytest.mark.parametrize("n", [512])
+def test_real_apply_n512_log(api, n):
+    us = np.stack([synth.smooth_density(n, 1000 + i) for i in range(2)])
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    g = oracle_table("log", n)
+    for i in range(2):
+        assert metrics.rel_linf(got[i], np.real(scheme.apply(us[i], g, B))) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kname", ["helm20", "helm40"])
+@pytest.mark.parametrize("n", [16, 64, 128])
+def test_complex_apply(api, kname, n):
+    rng = np.random.default_rng(n)
+    v = (rng.normal(size=(2, n, n)) + 1j * rng.normal(size=(2, n, n))) * synth.cutoff(n)
+    plan = api.ConvPlan(n=n, **plan_kwargs(kname))
+    got = plan.apply(_gpu(v, torch.complex128)).cpu().numpy()
+    g = oracle_table(kname, n)
+    for i in range(2):
+        assert metrics.rel_linf(got[i], scheme.apply(v[i], g, B)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kname", ["log", "pow-1/2", "pow-1/3", "helm20"])
+def test_moments_sampled(api, kname):
+    n = 128
+    plan = api.ConvPlan(n=n, **plan_kwargs(kname))
+    rng = np.random.default_rng(5)
+    k1 = np.concatenate([[0, 1, 0, 3, -n, -n, n - 1], rng.integers(-n, n, 40)])
+    k2 = np.concatenate([[0, 0, 1, 4, 0, -n, n - 1], rng.integers(-n, n, 40)])
+    got = plan.moments(k1, k2)
+    full = oracle_table(kname, n)
+    nb = n * B
+    ref = np.array([full[a % nb, b % nb] for a, b in zip(k1, k2)])
+    scale = np.max(np.abs(full))
+    assert np.max(np.abs(got - ref)) <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("shape", ["disc", "square"])
+@pytest.mark.parametrize("n", [64, 128])
+def test_fourier_smoothing_apply(api, shape, n):
+    R = 0.25
+    plan = api.ConvPlan(n=n, **plan_kwargs("laplace"))
+    ut = np.ones((n, n))
+    if shape == "disc":
+        fs = api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)
+        dens = smoothing.smoothed_disc_density(n, B, R, r2=0.39)
+    else:
+        h = 0.15
+        fs = api.FsDesc("square", 0.5, 0.5, h, h * math.sqrt(2), 0.39)
+        dens = smoothing.smoothed_square_density(n, B, 0.5 - h, 0.5 + h, h * math.sqrt(2), 0.39)
+    got = plan.apply(_gpu(ut, torch.float64).unsqueeze(0), fs=[fs]).cpu().numpy()[0]
+    ref = np.real(scheme.apply(dens, oracle_table("laplace", n), B))
+    assert metrics.rel_linf(got, ref) <= FP64_TOL
+
+
+def test_mixed_fs_and_plain_batch(api):
+    n = 64
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    u0 = synth.smooth_density(n, 1003)
+    R = synth.disc_radius(1100)
+    us = np.stack([u0, np.ones((n, n))])
+    fs = [None, api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)]
+    got = plan.apply(_gpu(us, torch.float64), fs=fs).cpu().numpy()
+    g = oracle_table("log", n)
+    assert metrics.rel_linf(got[0], np.real(scheme.apply(u0, g, B))) <= FP64_TOL
+    dens = smoothing.smoothed_disc_density(n, B, R, r2=0.39)
+    assert metrics.rel_linf(got[1], np.real(scheme.apply(dens, g, B))) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kname", ["log", "pow-1/2"])
+@pytest.mark.parametrize("n", [64, 256])
+def test_fp32_apply_bound(api, kname, n):
+    us = np.stack([synth.smooth_density(n, 2000 + i) for i in range(2)])
+    plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs(kname))
+    got = plan.apply(_gpu(us, torch.float32)).cpu().numpy().astype(np.float64)
+    g = oracle_table(kname, n)
+    for i in range(2):
+        ref = np.real(scheme.apply(us[i], g, B))
+        assert metrics.rel_linf(got[i], ref) <= 2e-6
+        assert metrics.rel_l2(got[i], ref) <= 5e-7
+
+
+def test_fp32_complex_apply_bound(api):
+    n = 64
+    rng = np.random.default_rng(9)
+    v = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * synth.cutoff(n)
+    plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("helm20"))
+    got = plan.apply(_gpu(v, torch.complex64)).cpu().numpy().astype(np.complex128)
+    ref = scheme.apply(v, oracle_table("helm20", n), B)
+    assert metrics.rel_linf(got, ref) <= 2e-6
+
+
+def test_in_place_and_empty_batch_and_determinism(api):
+    n = 128
+    u = synth.smooth_density(n, 1010)
+    plan = api.ConvPlan(n=n, **plan_kwargs("pow-1/2"))
+    t = _gpu(u, torch.float64).unsqueeze(0).contiguous()
+    a = plan.apply(t.clone()).cpu().numpy()
+    b = plan.apply(t.clone()).cpu().numpy()
+    assert np.array_equal(a, b)                            # bitwise reproducible
+    tt = t.clone()
+    plan.apply(tt, out=tt)                                 # in place
+    assert np.array_equal(tt.cpu().numpy(), a)
+    empty = torch.empty((0, n, n), dtype=torch.float64, device="cuda")
+    assert plan.apply(empty).shape == (0, n, n)
+
+
+def test_batch_independence(api):
+    # Each density's result is the same alone and inside a batch (bitwise).
+    n = 64
+    us = np.stack([synth.smooth_density(n, 1020 + i) for i in range(5)])
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    allb = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    for i in (0, 3):
+        one = plan.apply(_gpu(us[i:i + 1], torch.float64)).cpu().numpy()[0]
+        assert np.array_equal(one, allb[i])
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_ls_solve_fp64_vs_dense(api, n):
+    kappa = 20.0
+    m = synth.contrast(n)
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(3020))
+    plan = api.ConvPlan(n=n, **plan_kwargs("helm20"))
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-12, restart=20)
+    assert info.status == 0, info
+    g = oracle_table("helm20", n)
+    ref = ols.dense_solve(m, ui, g, B, kappa)
+    got = u.cpu().numpy()
+    assert metrics.rel_linf(got, ref) <= 1e-10
+    res = ui - ols.matvec(got, m, g, B, kappa)
+    assert np.linalg.norm(res) / np.linalg.norm(ui) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_ls_solve_mixed_precision(api, n):
+    kappa = 40.0
+    m = synth.contrast(n)
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(3040))
+    plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("helm40"))
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-8, restart=30,
+                            mixed=True)
+    assert info.status == 0, info
+    assert info.refinements >= 1
+    g = oracle_table("helm40", n)
+    got = u.cpu().numpy()
+    res = ui - ols.matvec(got, m, g, B, kappa)
+    assert np.linalg.norm(res) / np.linalg.norm(ui) <= 1.2e-8
+    ref, oinfo = ols.gmres(m, ui, g, B, kappa, tol=1e-12, restart=50)
+    assert metrics.rel_linf(got, ref) <= 1e-6
+
+
+def test_ls_zero_contrast_and_zero_rhs(api):
+    n, kappa = 32, 20.0
+    plan = api.ConvPlan(n=n, **plan_kwargs("helm20"))
+    ui = synth.plane_wave(n, kappa, 0.3)
+    u, info = plan.ls_solve(_gpu(np.zeros((n, n)), torch.float64), _gpu(ui, torch.complex128), tol=1e-10)
+    assert info.status == 0 and np.max(np.abs(u.cpu().numpy() - ui)) < 1e-14
+    z, info = plan.ls_solve(_gpu(synth.contrast(n), torch.float64),
+                            torch.zeros((n, n), dtype=torch.complex128, device="cuda"), tol=1e-10)
+    assert info.status == 0 and info.matvecs == 0 and torch.all(z == 0)
+
+
+def test_ls_maxit_status(api):
+    n, kappa = 32, 40.0
+    plan = api.ConvPlan(n=n, **plan_kwargs("helm40"))
+    m = synth.contrast(n)
+    ui = synth.plane_wave(n, kappa, 0.3)
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-14, restart=5,
+                            max_matvecs=7)
+    assert info.status == 1 and info.matvecs <= 8 and info.rel_residual > 1e-14
