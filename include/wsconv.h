@@ -137,6 +137,16 @@ double conv_plan_radius(ws_plan_t plan);
 int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work,
                const ws_fs_desc* fs, void* stream);
 
+/* One of the three passes of conv_apply without Fourier smoothing, for callers
+ * that time or interleave them: pass 0 = row transforms of the density into
+ * `work`, pass 1 = column transforms with the multiply by ghat (in `work`),
+ * pass 2 = inverse row transforms from `work` into `out` (Section 2.1, eq. An).
+ * conv_apply(plan, batch, u, out, work, NULL, s) enqueues exactly pass 0, 1, 2.
+ * Arguments as for conv_apply; `density` is read by pass 0 only and `out`
+ * written by pass 2 only. */
+int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
+                    void* stream);
+
 /* Device scratch needed by ls_solve for a given restart length. */
 int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* work_bytes);
 

@@ -128,6 +128,13 @@ class ConvPlan:
                                         fs_arr, _stream_ptr(stream)))
         return out[0] if squeeze else out
 
+    def apply_pass(self, pass_index: int, density: torch.Tensor, out: torch.Tensor, work: torch.Tensor,
+                   stream=None) -> None:
+        """Enqueue one pass of the apply (conv_apply_pass); no argument copies, no checks beyond the C side."""
+        with torch.cuda.device(self.device):
+            L.check(self.lib.conv_apply_pass(self.handle, pass_index, density.shape[0], _dev_ptr(density),
+                                             _dev_ptr(out), _dev_ptr(work), _stream_ptr(stream)))
+
     def ls_workspace(self, restart: int, mixed: bool) -> torch.Tensor:
         nbytes = ctypes.c_size_t()
         L.check(self.lib.ls_solve_query(self.handle, restart, int(mixed), ctypes.byref(nbytes)))

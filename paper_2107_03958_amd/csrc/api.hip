@@ -232,6 +232,39 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
   return WS_OK;
 }
 
+int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
+                    void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (pass < 0 || pass > 2) return fail(WS_EINVAL, "pass must be 0, 1 or 2");
+  if (batch < 0) return fail(WS_EINVAL, "batch must be >= 0");
+  if (batch == 0) return WS_OK;
+  if (batch > 65535) return fail(WS_EUNSUPPORTED, "batch must be at most 65535 per call");
+  if (!work || (pass == 0 && !density) || (pass == 2 && !out))
+    return fail(WS_EINVAL, "density (pass 0), work and out (pass 2) must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(density) | reinterpret_cast<uintptr_t>(out) |
+       reinterpret_cast<uintptr_t>(work)) % 16)
+    return fail(WS_EINVAL, "device buffers must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ws::Plan& p = *plan;
+  hipError_t e;
+  if (!p.cplx) {
+    if (p.precision == WS_FP64)
+      e = ws::launch_pass_real<double>(p, pass, batch, (const double*)density, (double*)out, (ws::cx<double>*)work, s);
+    else
+      e = ws::launch_pass_real<float>(p, pass, batch, (const float*)density, (float*)out, (ws::cx<float>*)work, s);
+  } else {
+    if (p.precision == WS_FP64)
+      e = ws::launch_pass_cplx<double>(p, pass, batch, (const ws::cx<double>*)density, (ws::cx<double>*)out,
+                                       (ws::cx<double>*)work, s);
+    else
+      e = ws::launch_pass_cplx<float>(p, pass, batch, (const ws::cx<float>*)density, (ws::cx<float>*)out,
+                                      (ws::cx<float>*)work, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "conv_apply_pass");
+  return WS_OK;
+}
+
 int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* work_bytes) {
   g_err.clear();
   if (!plan) return fail(WS_EINVAL, "plan is NULL");

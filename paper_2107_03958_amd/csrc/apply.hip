@@ -415,18 +415,32 @@ template <> const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
 template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
 
 template <typename T, int LOGN>
-static hipError_t apply_real_n(const Plan& pl, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
+static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T* out, cx<T>* work,
+                              hipStream_t s) {
   using C = Cfg<T, LOGN>;
   constexpr int n = C::n;
   auto tw = make_tw<T>(pl);
-  const T* g = static_cast<const T*>(gtab_of<T>(pl));
   FsArgs none{};
-  k_rows_fwd_real<T, LOGN><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(u, work, tw);
-  k_cols<T, T, LOGN, false, false><<<dim3(n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, gnyq_of<T>(pl),
-                                                                                     tw, none, nullptr);
-  k_rows_inv_real<T, LOGN, false><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(work, out, tw, nullptr,
-                                                                                    none);
+  if (pass == 0) {
+    k_rows_fwd_real<T, LOGN><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(u, work, tw);
+  } else if (pass == 1) {
+    const T* g = static_cast<const T*>(gtab_of<T>(pl));
+    k_cols<T, T, LOGN, false, false><<<dim3(n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, gnyq_of<T>(pl),
+                                                                                       tw, none, nullptr);
+  } else {
+    k_rows_inv_real<T, LOGN, false><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(work, out, tw, nullptr,
+                                                                                      none);
+  }
   return hipGetLastError();
+}
+
+template <typename T, int LOGN>
+static hipError_t apply_real_n(const Plan& pl, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
+  for (int pass = 0; pass < 3; ++pass) {
+    hipError_t e = pass_real_n<T, LOGN>(pl, pass, batch, u, out, work, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T, int LOGN>
@@ -443,22 +457,36 @@ static hipError_t fs_real_n(const Plan& pl, const T* ut, T* out, cx<T>* work, co
 }
 
 template <typename T, int LOGN>
-static hipError_t apply_cplx_n(const Plan& pl, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                               cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
+static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* v, const T* m, T alpha, bool add,
+                              cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
   using C = Cfg<T, LOGN>;
   constexpr int n = C::n;
   auto tw = make_tw<T>(pl);
-  const cx<T>* g = static_cast<const cx<T>*>(gtab_of<T>(pl));
   FsArgs none{};
-  if (m)
-    k_rows_fwd_cplx<T, LOGN, true><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
-  else
-    k_rows_fwd_cplx<T, LOGN, false><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
-  k_cols<T, cx<T>, LOGN, true, false><<<dim3(2 * n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, nullptr,
-                                                                                         tw, none, skip);
-  k_rows_inv_cplx<T, LOGN><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(work, v, out, alpha,
-                                                                             add ? 1 : 0, tw, skip);
+  if (pass == 0) {
+    if (m)
+      k_rows_fwd_cplx<T, LOGN, true><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
+    else
+      k_rows_fwd_cplx<T, LOGN, false><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
+  } else if (pass == 1) {
+    const cx<T>* g = static_cast<const cx<T>*>(gtab_of<T>(pl));
+    k_cols<T, cx<T>, LOGN, true, false><<<dim3(2 * n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, nullptr,
+                                                                                           tw, none, skip);
+  } else {
+    k_rows_inv_cplx<T, LOGN><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(work, v, out, alpha,
+                                                                               add ? 1 : 0, tw, skip);
+  }
   return hipGetLastError();
+}
+
+template <typename T, int LOGN>
+static hipError_t apply_cplx_n(const Plan& pl, int batch, const cx<T>* v, const T* m, T alpha, bool add,
+                               cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
+  for (int pass = 0; pass < 3; ++pass) {
+    hipError_t e = pass_cplx_n<T, LOGN>(pl, pass, batch, v, m, alpha, add, out, work, s, skip);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 #define WS_DISPATCH_LOGN(LOGN, CALL) \
@@ -496,6 +524,28 @@ hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* 
 #undef CALL
 }
 
+template <typename T>
+hipError_t launch_pass_real(const Plan& p, int pass, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
+#define CALL(L) pass_real_n<T, L>(p, pass, batch, u, out, work, s)
+  WS_DISPATCH_LOGN(p.logn, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
+                            hipStream_t s) {
+#define CALL(L) pass_cplx_n<T, L>(p, pass, batch, v, nullptr, (T)1, false, out, work, s, nullptr)
+  WS_DISPATCH_LOGN(p.logn, CALL)
+#undef CALL
+}
+
+template hipError_t launch_pass_real<double>(const Plan&, int, int, const double*, double*, cx<double>*,
+                                             hipStream_t);
+template hipError_t launch_pass_real<float>(const Plan&, int, int, const float*, float*, cx<float>*, hipStream_t);
+template hipError_t launch_pass_cplx<double>(const Plan&, int, int, const cx<double>*, cx<double>*, cx<double>*,
+                                             hipStream_t);
+template hipError_t launch_pass_cplx<float>(const Plan&, int, int, const cx<float>*, cx<float>*, cx<float>*,
+                                            hipStream_t);
 template hipError_t launch_apply_real<double>(const Plan&, int, const double*, double*, cx<double>*, hipStream_t);
 template hipError_t launch_apply_real<float>(const Plan&, int, const float*, float*, cx<float>*, hipStream_t);
 template hipError_t launch_fs_real<double>(const Plan&, const double*, double*, cx<double>*, const ws_fs_desc&,

@@ -53,6 +53,13 @@ template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add_input,
                              cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr);
 
+// Single passes of the apply (pass 0: rows forward, 1: columns, 2: rows inverse).
+template <typename T>
+hipError_t launch_pass_real(const Plan& p, int pass, int batch, const T* u, T* out, cx<T>* work, hipStream_t s);
+template <typename T>
+hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
+                            hipStream_t s);
+
 // Plan construction kernels (moments.hip).
 hipError_t launch_build_tables(Plan& p, hipStream_t s);
 
