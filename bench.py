@@ -67,20 +67,26 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
         t_plan.append(time.perf_counter() - t0)
     u = u_host.to(dt).cuda()
     out = torch.empty_like(u)
-    work = torch.empty(batch * plans[0].work_bytes, dtype=torch.uint8, device="cuda")
+    work = torch.empty(max(1, plans[0].chunk) * plans[0].work_bytes, dtype=torch.uint8, device="cuda")
     nk = len(plans)
-    # One event before and after each pass of each kernel of each timed step, on the launch stream.
-    ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nk)] for _ in range(steps)]
+    chunk = plans[0].chunk            # densities taken through all three passes at a time (as conv_apply)
+    groups = [(b0, min(batch, b0 + chunk)) for b0 in range(0, batch, chunk)]
+    ng = len(groups)
+    # One event before and after each pass of each density group of each kernel, on the launch stream.
+    ev = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nk * ng)] for _ in range(steps)]
     pass_ms = np.zeros(3)
+    views = [(u[a:b], out[a:b]) for a, b in groups]
 
     def step(evs):
         for ki, p in enumerate(plans):
-            if evs is not None:
-                evs[ki][0].record(stream)
-            for ps in range(3):
-                p.apply_pass(ps, u, out, work, stream)
-                if evs is not None:
-                    evs[ki][ps + 1].record(stream)
+            for gi, (uv, ov) in enumerate(views):
+                e = None if evs is None else evs[ki * ng + gi]
+                if e is not None:
+                    e[0].record(stream)
+                for ps in range(3):
+                    p.apply_pass(ps, uv, ov, work, stream)
+                    if e is not None:
+                        e[ps + 1].record(stream)
 
     for _ in range(warmup):
         step(None)
@@ -91,11 +97,11 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for st in range(steps):
-        for ki in range(nk):
+        for e in ev[st]:
             for ps in range(3):
-                pass_ms[ps] += ev[st][ki][ps].elapsed_time(ev[st][ki][ps + 1])
-    launches = steps * nk
-    avg_pass_ms = pass_ms / launches
+                pass_ms[ps] += e[ps].elapsed_time(e[ps + 1])
+    launches = steps * nk * ng
+    avg_pass_ms = pass_ms / launches       # per launch of `chunk` densities
     applies = steps * nk * batch
     pb = pass_bytes(n, s)
     res = dict(
@@ -103,14 +109,16 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
         ms_per_step=elapsed / steps * 1e3,
         pass_model_gbps=applies * sum(pb) / elapsed / 1e9,
         pass_avg_ms={PASS_NAMES[i]: float(avg_pass_ms[i]) for i in range(3)},
-        pass_gbps={PASS_NAMES[i]: float(pb[i] * batch / (avg_pass_ms[i] * 1e-3) / 1e9) for i in range(3)},
+        pass_gbps={PASS_NAMES[i]: float(pb[i] * batch * steps * nk / (pass_ms[i] * 1e-3) / 1e9) for i in range(3)},
+        densities_per_launch=chunk,
         plan_build_s={KERNELS[i][0]: t_plan[i] for i in range(nk)},
     )
     dom = int(np.argmax(avg_pass_ms))
-    achieved = pb[dom] * batch / (avg_pass_ms[dom] * 1e-3) / 1e9
+    per_launch = pb[dom] * batch / ng                  # algorithmic bytes of one launch (average group)
+    achieved = per_launch / (avg_pass_ms[dom] * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=achieved, peak=PEAK_HBM_GBPS,
                            unit="GB/s", frac=achieved / PEAK_HBM_GBPS, traffic=None,
-                           bytes_per_launch=pb[dom] * batch, launch_avg_ms=float(avg_pass_ms[dom]))
+                           bytes_per_launch=per_launch, launch_avg_ms=float(avg_pass_ms[dom]))
     # Keep the last outputs of the first kernel for the FP32-vs-FP64 comparison.
     plans[0].apply(u, out=out, work=work)
     res["_out_first_kernel"] = out[:4].double().cpu().numpy()

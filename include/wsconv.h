@@ -147,6 +147,13 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
 int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
                     void* stream);
 
+/* Number of densities conv_apply takes through all three passes at a time:
+ * a chunk's intermediate is sized to stay in the GPU's last-level cache
+ * between passes.  Callers driving conv_apply_pass over a large batch should
+ * group densities the same way.  work_bytes_per_density times this count is
+ * the scratch conv_apply actually touches. */
+int conv_apply_chunk(ws_plan_t plan);
+
 /* Device scratch needed by ls_solve for a given restart length. */
 int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* work_bytes);
 

@@ -83,6 +83,7 @@ class ConvPlan:
                                        _dev_ptr(self.buf), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
         self.a = self.lib.conv_plan_radius(h)
+        self.chunk = L.check(self.lib.conv_apply_chunk(h))
         self._work = None
 
     # ------------------------------------------------------------------

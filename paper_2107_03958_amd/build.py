@@ -52,15 +52,17 @@ def _compile(src: str, obj: str, flags: list[str]) -> tuple[str, int, str]:
     return src, proc.returncode, err
 
 
-def build(jobs: int = 4, debug: bool = False, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int = 4, debug: bool = False, verbose: bool = False, out: str = LIB,
+          defines: list[str] | None = None, build_dir: str = BUILD) -> str:
+    """Compile every csrc/*.hip and link `out`; `defines` are NAME=VALUE tile overrides."""
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
-    flags = common_flags(debug)
+    flags = common_flags(debug) + [f"-D{d}" for d in (defines or [])]
     objs = []
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         futs = []
         for src in srcs:
-            obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+            obj = os.path.join(build_dir, os.path.basename(src)[:-4] + ".o")
             objs.append(obj)
             futs.append(ex.submit(_compile, src, obj, flags))
         failed = False
@@ -71,14 +73,14 @@ def build(jobs: int = 4, debug: bool = False, verbose: bool = False) -> str:
             failed = failed or rc != 0
     if failed:
         raise RuntimeError("HIP compilation failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 def main(argv=None):
@@ -86,8 +88,11 @@ def main(argv=None):
     ap.add_argument("--jobs", type=int, default=4)
     ap.add_argument("--debug", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--out", default=LIB, help="output library path")
+    ap.add_argument("--build-dir", default=BUILD)
+    ap.add_argument("-D", dest="defines", action="append", default=[], help="tile override NAME=VALUE")
     args = ap.parse_args(argv)
-    print(build(args.jobs, args.debug, args.verbose))
+    print(build(args.jobs, args.debug, args.verbose, args.out, args.defines, args.build_dir))
 
 
 if __name__ == "__main__":

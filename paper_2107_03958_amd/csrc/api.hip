@@ -67,12 +67,12 @@ Sizes sizes_for(int n, bool cplx, int precision) {
   const size_t nb = 2 * (size_t)n;
   const size_t te = ws::table_elems(n, cplx);
   s.tw64 = align_up(nb * 16);
-  s.tw32 = precision == WS_FP32 ? align_up(nb * 8) : 0;   // each of hi and lo
+  s.tw32 = precision == WS_FP32 ? align_up(nb * 16) : 0;  // (hi, lo) float pairs
   s.g64 = align_up(te * (cplx ? 16 : 8));
   s.nyq64 = cplx ? 0 : align_up((size_t)(n + 1) * 8);
   s.g32 = precision == WS_FP32 ? align_up(te * (cplx ? 8 : 4)) : 0;
   s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((size_t)(n + 1) * 4) : 0;
-  s.total = s.tw64 + 2 * s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
+  s.total = s.tw64 + s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
   const size_t elem = precision == WS_FP32 ? 8 : 16;
   s.work = (size_t)n * (cplx ? 2 * n : n) * elem;
   return s;
@@ -139,9 +139,7 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   p->tw64 = reinterpret_cast<ws::cx<double>*>(base + off);
   off += s.tw64;
   if (precision == WS_FP32) {
-    p->tw32hi = reinterpret_cast<ws::cx<float>*>(base + off);
-    off += s.tw32;
-    p->tw32lo = reinterpret_cast<ws::cx<float>*>(base + off);
+    p->tw32 = reinterpret_cast<ws::TwPair*>(base + off);
     off += s.tw32;
   }
   p->g64 = base + off;
@@ -160,7 +158,15 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   }
   p->plan_bytes = s.total;
   p->work_bytes = s.work;
-  hipError_t e = ws::launch_build_tables(*p, static_cast<hipStream_t>(stream));
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "conv_plan: device query");
+  }
+  p->cus = cus > 0 ? cus : 1;
+  e = ws::launch_build_tables(*p, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e, "conv_plan: table kernels");
@@ -170,6 +176,11 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
 }
 
 double conv_plan_radius(ws_plan_t plan) { return plan ? plan->a : 0.0; }
+
+int conv_apply_chunk(ws_plan_t plan) {
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  return ws::apply_chunk(*plan);
+}
 
 int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work, const ws_fs_desc* fs,
                void* stream) {

@@ -19,7 +19,14 @@
 // write RPB x CB contiguous elements per block.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "plan.hpp"
+
+#ifndef WS_CPB
+#define WS_CPB 1      // 0: a column block holds CB columns; 1: one column, XCD-paired blocks
+#endif
 
 namespace ws {
 
@@ -28,21 +35,84 @@ struct Cfg {
   static constexpr int n = 1 << LOGN;
   static constexpr int CB = Layout<T>::CB;
   static constexpr int RPB = Layout<T>::RPB;
-  static constexpr int emax(int L) { return L < 16 ? L : 16; }
-  // Half-length lines of the real row passes.
-  static constexpr int LH = n / 2;
-  static constexpr int EH = emax(LH);
-  static constexpr int PH = LH / EH;
-  // Full-length lines (columns, complex rows).
-  static constexpr int LF = n;
-  static constexpr int EF = emax(LF);
-  static constexpr int PF = LF / EF;
-  // Rows per block of the complex row passes (two full-length lines per row in LDS).
-  static constexpr int fit(int rows) {
-    return rows * 2 * padded(n) * (int)sizeof(cx<T>) <= 163840 ? rows : fit(rows / 2);
+  static constexpr int cap(int e, int lines, int L) {         // keep lines * L / e <= 1024 threads
+    while (lines * (L / e) > 1024) e *= 2;
+    return e < L ? e : L;
   }
-  static constexpr int RPBC = fit(RPB);
+  // Real row passes: two half-length lines (even/odd spectrum) per row, one line per thread group.
+  static constexpr int LH = n / 2;
+  static constexpr int EH = cap(Layout<T>::ER, 2 * RPB, LH);
+  static constexpr int PH = LH / EH;
+  static constexpr int NT_RH = 2 * RPB * PH;
+  static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
+  // Column passes: two full-length lines (even/odd frequencies) per column,
+  // CPB columns per block (CPB = CB, or 1 with XCD-paired blocks).
+  static constexpr int CPB = WS_CPB == 0 ? CB : 1;
+  static constexpr int LF = n;
+  static constexpr int EF = cap(Layout<T>::EC, 2 * CPB, LF);
+  static constexpr int PF = LF / EF;
+  static constexpr int NT_C = 2 * CPB * PF;
+  static constexpr int SF = LineLayout<LF, EF>::STRIDE;
+  // Waves per SIMD the launch bounds reserve registers for: as many blocks
+  // per CU (up to two) as the block's LDS allows.
+  static constexpr int waves(int threads, int lds_bytes) {
+    const int blocks = lds_bytes * 2 <= 163840 ? 2 : 1;
+    const int w = (blocks * threads + 255) / 256;
+    return w < 1 ? 1 : w;
+  }
+  static constexpr int WAVES_C = waves(NT_C, 2 * CPB * SF * (int)sizeof(cx<T>));
+  static constexpr int WAVES_RH = waves(NT_RH, 2 * RPB * SH_ * (int)sizeof(cx<T>));
+  // Complex row passes: two full-length lines per row, rows per block limited by LDS.
+  template <int ROWS>
+  static constexpr bool fits() {
+    constexpr int e = cap(Layout<T>::ER, 2 * ROWS, LF);
+    return ROWS * 2 * LineLayout<LF, e>::STRIDE * (int)sizeof(cx<T>) <= 163840;
+  }
+  static constexpr int R2_ = RPB / 2 > 1 ? RPB / 2 : 1, R4_ = RPB / 4 > 1 ? RPB / 4 : 1;
+  static constexpr int RPBC = fits<RPB>() ? RPB : fits<R2_>() ? R2_ : fits<R4_>() ? R4_ : 1;
+  static constexpr int EFR = cap(Layout<T>::ER, 2 * RPBC, LF);
+  static constexpr int PFR = LF / EFR;
+  static constexpr int NT_RC = 2 * RPBC * PFR;
+  static constexpr int SFR = LineLayout<LF, EFR>::STRIDE;
+  static constexpr int WAVES_RC = waves(NT_RC, 2 * RPBC * SFR * (int)sizeof(cx<T>));
 };
+
+// Thread -> (column c, line l, p) of a column pass.  When a wave can hold
+// 64/CB consecutive p of every column, the wave's lanes split into CB groups
+// of consecutive p: its global accesses cover one contiguous span and every
+// 8-lane LDS phase stays on one line.
+template <int CPB, int P>
+__device__ __forceinline__ void col_thread(int tid, int& c, int& p, int& l) {
+  constexpr int LPC = 64 / CPB;
+  if constexpr (CPB <= 64 && 64 % CPB == 0 && P % LPC == 0 && P >= LPC) {
+    constexpr int WPL = P / LPC;
+    const int w = tid / 64, lane = tid % 64;
+    c = lane / LPC;
+    l = w / WPL;
+    p = (w % WPL) * LPC + lane % LPC;
+  } else {
+    c = tid % CPB;
+    p = (tid / CPB) % P;
+    l = tid / (CPB * P);
+  }
+}
+
+// Block -> tile maps.  Blocks are dealt round-robin to the 8 XCDs (each with
+// its own L2).  Tiles that share 128-byte lines of the blocked intermediate
+// are given to blocks 8 apart, which land on the same XCD at about the same
+// time, so the second reader finds the lines in that XCD's L2.
+constexpr int kXcds = 8;
+// Column tiles: `pairs` tiles (cb, c) with c in [0, G) share a block-column cb.
+template <int G>
+__device__ __forceinline__ void xcd_group(int b, int& major, int& minor) {
+  if constexpr (G == 1) {
+    major = b;
+    minor = 0;
+  } else {
+    minor = (b / kXcds) % G;
+    major = (b / (kXcds * G)) * kXcds + b % kXcds;
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
@@ -91,6 +161,15 @@ __device__ inline double fs_window(double x1, double x2, const FsArgs& f) {
   return fs_step((r - f.r1) / (f.r2 - f.r1));
 }
 
+// All pass kernels are persistent: a block walks the tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ...  With kPrefetch the row passes load the next
+// tile's global data into registers right after consuming the current one, so
+// HBM traffic of one tile overlaps the LDS/FFT phases of the previous one.
+#ifndef WS_PREFETCH
+#define WS_PREFETCH 0
+#endif
+constexpr bool kPrefetch = WS_PREFETCH != 0;
+
 // ----------------------------------------------------------------------------
 // Real path, forward row pass: rows j1 < n of a real density -> half spectrum
 // X(j1, k2), k2 in [0, n), with column 0 holding X(j1,0) + i X(j1,n).
@@ -98,75 +177,99 @@ __device__ inline double fs_window(double x1, double x2, const FsArgs& f) {
 // sequence z_m = x_{2m} + i x_{2m+1} (n/2 nonzero of n): Z = DFT_n(z) splits
 // into DFT_{n/2}(z) (even k) and DFT_{n/2}(z w_n^m) (odd k), and
 // X_k = (Z_k + conj Z_{n-k})/2 - i w_{2n}^k (Z_k - conj Z_{n-k})/2.
+// Threads: (row r, line l, p); line 0 carries the even, line 1 the odd half.
+// LDS line (r, l) holds Z_{2q+l} at q.  Tile = RPB rows of one density.
 template <typename T, int LOGN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::RPB * Cfg<T, LOGN>::PH)) void k_rows_fwd_real(
-    const T* __restrict__ u, cx<T>* __restrict__ work, typename TwOf<T>::type tw) {
+__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_fwd_real(
+    const T* __restrict__ u, cx<T>* __restrict__ work, typename TwOf<T>::type tw, int ntiles) {
   using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL;
-  constexpr int NT = RPB * P;
-  __shared__ cx<T> lds[RPB][padded(n)];
-  const int tid = threadIdx.x, r = tid / P, p = tid % P;
-  const int row0 = blockIdx.x * RPB;
-  const size_t batch = blockIdx.y;
-  const cx<T>* src = reinterpret_cast<const cx<T>*>(u + (batch * n + row0 + r) * n);
-  cx<T> v[2][E];
+  using LL = LineLayout<C::LH, C::EH>;
+  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  __shared__ cx<T> lds[2 * RPB * S];
+  const int tid = threadIdx.x, p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* line[1] = {mine};
+  cx<T> x[E];
+  auto load = [&](int tile) {
+    const size_t batch = tile / TPD;
+    const int row = (tile % TPD) * RPB + r;
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(u + (batch * n + row) * n);
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int m = p + P * slot_elem<E, R0>(reg);
-    const cx<T> z = src[m];
-    v[0][reg] = z;
-    v[1][reg] = tw.template mul<-1>(z, 2 * m);   // w_n^m
+    for (int reg = 0; reg < E; ++reg) x[reg] = src[p + P * slot_elem<E, R0>(reg)];
+  };
+  int t = blockIdx.x;
+  if constexpr (kPrefetch) {
+    if (t < ntiles) load(t);
   }
-  cx<T>* lines[2] = {&lds[r][0], &lds[r][padded(L)]};
-  fft_lines<L, E, 2, -1>(v, lines, p, tw, 2 * n / L);
+  for (; t < ntiles; t += gridDim.x) {
+    if constexpr (!kPrefetch) load(t);
+    cx<T> v[1][E];
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int q = p + P * slot_elem<E, RL>(reg);
-    lds[r][pad(2 * q)] = v[0][reg];
-    lds[r][pad(2 * q + 1)] = v[1][reg];
-  }
-  __syncthreads();
-  cx<T>* dst = work + batch * (size_t)n * n;
-  for (int idx = tid; idx < RPB * n; idx += NT) {
-    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-    const int k = cb * CB + c;
-    const cx<T> zk = lds[rr][pad(k)];
-    cx<T> val;
-    if (k == 0) {
-      val = {zk.x + zk.y, zk.x - zk.y};
-    } else {
-      const cx<T> zm = cconj(lds[rr][pad(n - k)]);
-      const cx<T> a = cscale(zk + zm, (T)0.5);
-      const cx<T> d = cscale(zk - zm, (T)0.5);
-      const cx<T> bdiff = {d.y, -d.x};              // -i d
-      val = a + tw.template mul<-1>(bdiff, k);      // + w_{2n}^k (-i d)
+    for (int reg = 0; reg < E; ++reg) {
+      const int m = p + P * slot_elem<E, R0>(reg);
+      v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
     }
-    dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+    if constexpr (kPrefetch) {
+      if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);
+    }
+    fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
+#pragma unroll
+    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+    __syncthreads();
+    const size_t batch = t / TPD;
+    const int row0 = (t % TPD) * RPB;
+    cx<T>* dst = work + batch * (size_t)n * n;
+    for (int idx = tid; idx < RPB * n; idx += NT) {
+      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+      const int k = cb * CB + c;
+      const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+      cx<T> val;
+      if (k == 0) {
+        val = {zk.x + zk.y, zk.x - zk.y};
+      } else {
+        const int kk = n - k;
+        const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
+        const cx<T> a = cscale(zk + zm, (T)0.5);
+        const cx<T> d = cscale(zk - zm, (T)0.5);
+        const cx<T> bdiff = {d.y, -d.x};              // -i d
+        val = a + tw.template mul<-1>(bdiff, k);      // + w_{2n}^k (-i d)
+      }
+      dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+    }
+    __syncthreads();
   }
 }
 
 // ----------------------------------------------------------------------------
 // Column pass shared by the real (NCOLS = n) and complex (NCOLS = 2n) paths:
 // forward length-nb transform of n nonzero rows, multiply by the moments,
-// inverse transform keeping rows i1 < n.  GEN: instead of loading and
-// transforming, synthesise the spectrum chihat (Fourier smoothing pre-pass).
+// inverse transform keeping rows i1 < n.  Threads (column c, line l, p): line 0
+// transforms x (even frequencies k1 = 2q), line 1 transforms x w_{2n}^j (odd
+// k1 = 2q + 1); out_i = even_i + w_{2n}^{-i} odd_i is combined through LDS.
+// GEN: synthesise the spectrum chihat instead of loading and transforming
+// (Fourier smoothing pre-pass).  A block handles CPB columns of one density.
 template <typename T, typename G, int LOGN, bool CPLX, bool GEN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::CB * Cfg<T, LOGN>::PF)) void k_cols(
+__global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void k_cols(
     cx<T>* __restrict__ work, const G* __restrict__ gtab, const T* __restrict__ gnyq,
     typename TwOf<T>::type tw, FsArgs fs, const int* skip) {
   if (skip && *skip) return;
   using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL;
+  using LL = LineLayout<C::LF, C::EF>;
+  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB, CPB = C::CPB;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
   constexpr int NCOLS = CPLX ? 2 * n : n;
-  __shared__ cx<T> lds[CB][2][padded(n)];
-  const int tid = threadIdx.x, c = tid % CB, p = tid / CB;
-  const int cb = blockIdx.x;
+  __shared__ cx<T> lds[2 * CPB * S];
+  int cc, p, l;
+  col_thread<CPB, P>(threadIdx.x, cc, p, l);
+  int cb, csub;
+  xcd_group<CB / CPB>(blockIdx.x, cb, csub);
+  const int c = csub * CPB + cc;                       // column within the block-column cb
   const size_t batch = blockIdx.y;
   cx<T>* col = work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
-  cx<T>* lines[2] = {&lds[c][0][0], &lds[c][1][0]};
-  cx<T> v[2][E];
+  cx<T>* mine = lds + (2 * cc + l) * S;
+  cx<T>* line[1] = {mine};
+  cx<T> v[1][E];
   const int k2 = cb * CB + c;                          // FFT bin of this column
 
   if constexpr (!GEN) {
@@ -174,38 +277,30 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::CB * Cfg<T, LOGN>::PF)) void k_cols(
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
       const cx<T> x = col[(size_t)j * CB + c];
-      v[0][reg] = x;
-      v[1][reg] = tw.template mul<-1>(x, j);           // w_{2n}^j
+      v[0][reg] = l ? tw.template mul<-1>(x, j) : x;   // odd frequencies: x w_{2n}^j
     }
-    fft_lines<L, E, 2, -1>(v, lines, p, tw, 2);
-    // v[l][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
+    fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
+    // v[0][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {
-      if (cb == 0) {
+      if (cb == 0 && csub == 0) {
         // Column 0 packs the real columns k2 = 0 (D) and k2 = n (N):
         // Y = D^ + i N^ with D^, N^ Hermitian.  New value
-        // g0 D^ + i gN N^ = (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k).
+        // g0 D^ + i gN N^ = (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k); -k stays in the same half.
 #pragma unroll
-        for (int reg = 0; reg < E; ++reg) {
-          const int q = p + P * slot_elem<E, RL>(reg);
-          lds[c][0][pad(q)] = v[0][reg];
-          lds[c][1][pad(q)] = v[1][reg];
-        }
+        for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
         __syncthreads();
         if (c == 0) {
 #pragma unroll
           for (int reg = 0; reg < E; ++reg) {
             const int q = p + P * slot_elem<E, RL>(reg);
-#pragma unroll
-            for (int l = 0; l < 2; ++l) {
-              const int k1 = 2 * q + l;
-              const int k1f = k1 <= n ? k1 : 2 * n - k1;
-              const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
-              const cx<T> ym = cconj(lds[0][l][pad(partner)]);
-              const T g0 = (T)gtab[(size_t)k1f * CB];
-              const T gN = gnyq[k1f];
-              v[l][reg] = cscale(v[l][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
-            }
+            const int k1 = 2 * q + l;
+            const int k1f = k1 <= n ? k1 : 2 * n - k1;
+            const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
+            const cx<T> ym = cconj(mine[LL::pad(partner)]);
+            const T g0 = (T)gtab[(size_t)k1f * CB];
+            const T gN = gnyq[k1f];
+            v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
           }
           done = true;
         }
@@ -216,40 +311,37 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::CB * Cfg<T, LOGN>::PF)) void k_cols(
       const G* gc = gtab + (size_t)cb * (n + 1) * CB + c;
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
-        const int q = p + P * slot_elem<E, RL>(reg);
-#pragma unroll
-        for (int l = 0; l < 2; ++l) {
-          const int k1 = 2 * q + l;
-          const int k1f = k1 <= n ? k1 : 2 * n - k1;
-          if constexpr (CPLX) v[l][reg] = cmul(v[l][reg], gc[(size_t)k1f * CB]);
-          else v[l][reg] = cscale(v[l][reg], gc[(size_t)k1f * CB]);
-        }
+        const int k1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
+        const G g = gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB];
+        if constexpr (CPLX) v[0][reg] = cmul(v[0][reg], g);
+        else v[0][reg] = cscale(v[0][reg], g);
       }
     }
   } else {
     // Synthesised spectrum of the smoothed indicator (real path only).
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
-      const int q = p + P * slot_elem<E, RL>(reg);
-#pragma unroll
-      for (int l = 0; l < 2; ++l) {
-        const int b1 = 2 * q + l;
-        const int k1 = b1 < n ? b1 : b1 - 2 * n;      // F_n representative
-        cx<double> h = chihat(k1, k2, fs);
-        if (k2 == 0) {
-          const cx<double> hn = chihat(k1, -n, fs);  // column k2 = -nb/2, packed as imaginary part
-          h = {h.x - hn.y, h.y + hn.x};
-        }
-        v[l][reg] = {(T)h.x, (T)h.y};
+      const int b1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
+      const int k1 = b1 < n ? b1 : b1 - 2 * n;          // F_n representative
+      cx<double> h = chihat(k1, k2, fs);
+      if (k2 == 0) {
+        const cx<double> hn = chihat(k1, -n, fs);      // column k2 = -nb/2, packed as imaginary part
+        h = {h.x - hn.y, h.y + hn.x};
       }
+      v[0][reg] = {(T)h.x, (T)h.y};
     }
   }
   relayout<E, RL, R0>(v);
-  fft_lines<L, E, 2, +1>(v, lines, p, tw, 2);
+  fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int i = p + P * slot_elem<E, RL>(reg);
-    col[(size_t)i * CB + c] = v[0][reg] + tw.template mul<+1>(v[1][reg], i);   // + w_{2n}^{-i} odd
+  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+  __syncthreads();
+  const cx<T>* l0 = lds + (2 * cc) * S;
+  const cx<T>* l1 = l0 + S;
+#pragma unroll
+  for (int t = 0; t < E / 2; ++t) {
+    const int i = p + P * (l * (E / 2) + t);
+    col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
   }
 }
 
@@ -259,61 +351,72 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::CB * Cfg<T, LOGN>::PF)) void k_cols(
 // z = IDFT_n(Z) gives out_{2m} + i out_{2m+1}, m < n/2, computed as
 // IDFT_{n/2}(Z_even)_m + w_n^{-m} IDFT_{n/2}(Z_odd)_m.
 // FS: out = u_tilde * out * psi (the Fourier-smoothed density, Section 2.4).
+// LDS line (r, l) first holds Y_{2q+l} at q, then the inverse transform of line l.
 template <typename T, int LOGN, bool FS>
-__global__ __launch_bounds__((Cfg<T, LOGN>::RPB * Cfg<T, LOGN>::PH)) void k_rows_inv_real(
+__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_inv_real(
     const cx<T>* __restrict__ work, T* __restrict__ out, typename TwOf<T>::type tw,
-    const T* __restrict__ utilde, FsArgs fs) {
+    const T* __restrict__ utilde, FsArgs fs, int ntiles) {
   using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL;
-  constexpr int NT = RPB * P;
-  __shared__ cx<T> lds[RPB][padded(n)];
+  using LL = LineLayout<C::LH, C::EH>;
+  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  __shared__ cx<T> lds[2 * RPB * S];
   const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * RPB;
-  const size_t batch = blockIdx.y;
-  const cx<T>* src = work + batch * (size_t)n * n;
-  for (int idx = tid; idx < RPB * n; idx += NT) {
-    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-    lds[rr][pad(cb * CB + c)] = src[((size_t)cb * n + row0 + rr) * CB + c];
-  }
-  __syncthreads();
-  const int r = tid / P, p = tid % P;
-  cx<T> v[2][E];
+  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* line[1] = {mine};
+  const cx<T>* l0 = lds + (2 * r) * S;
+  const cx<T>* l1 = l0 + S;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    {
+      const cx<T>* src = work + (size_t)(t / TPD) * n * n;
+      const int row0 = (t % TPD) * RPB;
+      for (int idx = tid; idx < RPB * n; idx += NT) {
+        const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+        const int k = cb * CB + c;
+        lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] = src[((size_t)cb * n + row0 + rr) * CB + c];
+      }
+    }
+    __syncthreads();
+    cx<T> v[1][E];
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int q = p + P * slot_elem<E, R0>(reg);
-#pragma unroll
-    for (int l = 0; l < 2; ++l) {
+    for (int reg = 0; reg < E; ++reg) {
+      const int q = p + P * slot_elem<E, R0>(reg);
       const int k = 2 * q + l;
       cx<T> z;
       if (k == 0) {
-        const cx<T> y0 = lds[r][0];
+        const cx<T> y0 = mine[0];
         z = {y0.x + y0.y, y0.x - y0.y};
       } else {
-        const cx<T> yk = lds[r][pad(k)];
-        const cx<T> yk2 = cconj(lds[r][pad(n - k)]);
+        const cx<T> yk = mine[LL::pad(q)];
+        const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
         const cx<T> d = tw.template mul<+1>(yk - yk2, k);
         z = (yk + yk2) + times_i(d);
       }
-      v[l][reg] = z;
+      v[0][reg] = z;
     }
-  }
-  __syncthreads();
-  cx<T>* lines[2] = {&lds[r][0], &lds[r][padded(L)]};
-  fft_lines<L, E, 2, +1>(v, lines, p, tw, 2 * n / L);
-  cx<T>* dst = reinterpret_cast<cx<T>*>(out + (batch * n + row0 + r) * n);
+    __syncthreads();
+    fft_lines<L, E, 1, +1>(v, line, p, tw, 2 * n / L);
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int m = p + P * slot_elem<E, RL>(reg);
-    cx<T> zz = v[0][reg] + tw.template mul<+1>(v[1][reg], 2 * m);
-    if constexpr (FS) {
-      const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row0 + r) * n)[m];
-      const double x1 = (double)(row0 + r) / n;
-      const double w0 = fs_window(x1, (double)(2 * m) / n, fs);
-      const double w1 = fs_window(x1, (double)(2 * m + 1) / n, fs);
-      zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
+    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+    __syncthreads();
+    const size_t batch = t / TPD;
+    const int row = (t % TPD) * RPB + r;
+    cx<T>* dst = reinterpret_cast<cx<T>*>(out + (batch * n + row) * n);
+#pragma unroll
+    for (int tt = 0; tt < E / 2; ++tt) {
+      const int m = p + P * (l * (E / 2) + tt);
+      cx<T> zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
+      if constexpr (FS) {
+        const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row) * n)[m];
+        const double x1 = (double)row / n;
+        const double w0 = fs_window(x1, (double)(2 * m) / n, fs);
+        const double w1 = fs_window(x1, (double)(2 * m + 1) / n, fs);
+        zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
+      }
+      dst[m] = zz;
     }
-    dst[m] = zz;
+    __syncthreads();
   }
 }
 
@@ -321,83 +424,105 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::RPB * Cfg<T, LOGN>::PH)) void k_rows
 // Complex path, forward row pass: X(j1, k2), k2 in [0, 2n), natural order,
 // from rows of (m .* v); even k2 from DFT_n(x), odd k2 from DFT_n(x w_{2n}^j).
 template <typename T, int LOGN, bool MUL>
-__global__ __launch_bounds__((Cfg<T, LOGN>::RPBC * Cfg<T, LOGN>::PF)) void k_rows_fwd_cplx(
+__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_fwd_cplx(
     const cx<T>* __restrict__ vin, const T* __restrict__ mcon, cx<T>* __restrict__ work,
-    typename TwOf<T>::type tw, const int* skip) {
+    typename TwOf<T>::type tw, int ntiles, const int* skip) {
   if (skip && *skip) return;
   using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, RPB = C::RPBC, CB = C::CB;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL;
-  constexpr int NT = RPB * P;
-  __shared__ cx<T> lds[RPB][2 * padded(n)];
-  const int tid = threadIdx.x, r = tid / P, p = tid % P;
-  const int row0 = blockIdx.x * RPB;
-  const size_t batch = blockIdx.y;
-  const size_t roff = (batch * n + row0 + r) * n;
-  cx<T> v[2][E];
+  using LL = LineLayout<C::LF, C::EFR>;
+  constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  __shared__ cx<T> lds[2 * RPB * S];
+  const int tid = threadIdx.x, p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* line[1] = {mine};
+  cx<T> x[E];
+  auto load = [&](int tile) {
+    const int row = (tile % TPD) * RPB + r;
+    const size_t roff = ((size_t)(tile / TPD) * n + row) * n;
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int j = p + P * slot_elem<E, R0>(reg);
-    cx<T> x = vin[roff + j];
-    if constexpr (MUL) x = cscale(x, mcon[(row0 + r) * (size_t)n + j]);
-    v[0][reg] = x;
-    v[1][reg] = tw.template mul<-1>(x, j);
+    for (int reg = 0; reg < E; ++reg) {
+      const int j = p + P * slot_elem<E, R0>(reg);
+      x[reg] = vin[roff + j];
+      if constexpr (MUL) x[reg] = cscale(x[reg], mcon[(size_t)row * n + j]);
+    }
+  };
+  int t = blockIdx.x;
+  if constexpr (kPrefetch) {
+    if (t < ntiles) load(t);
   }
-  cx<T>* lines[2] = {&lds[r][0], &lds[r][padded(n)]};
-  fft_lines<L, E, 2, -1>(v, lines, p, tw, 2);
+  for (; t < ntiles; t += gridDim.x) {
+    if constexpr (!kPrefetch) load(t);
+    cx<T> v[1][E];
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int q = p + P * slot_elem<E, RL>(reg);
-    lds[r][pad(2 * q)] = v[0][reg];
-    lds[r][pad(2 * q + 1)] = v[1][reg];
-  }
-  __syncthreads();
-  cx<T>* dst = work + batch * (size_t)n * 2 * n;
-  for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
-    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-    dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[rr][pad(cb * CB + c)];
+    for (int reg = 0; reg < E; ++reg) {
+      const int j = p + P * slot_elem<E, R0>(reg);
+      v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
+    }
+    if constexpr (kPrefetch) {
+      if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);
+    }
+    fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
+#pragma unroll
+    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+    __syncthreads();
+    const int row0 = (t % TPD) * RPB;
+    cx<T>* dst = work + (size_t)(t / TPD) * n * 2 * n;
+    for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+      const int k = cb * CB + c;
+      dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+    }
+    __syncthreads();
   }
 }
 
 // Complex path, inverse row pass keeping i2 < n, fused out = [v] + alpha * result.
 template <typename T, int LOGN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::RPBC * Cfg<T, LOGN>::PF)) void k_rows_inv_cplx(
+__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_inv_cplx(
     const cx<T>* __restrict__ work, const cx<T>* vin, cx<T>* out, T alpha, int add_input,
-    typename TwOf<T>::type tw, const int* skip) {
+    typename TwOf<T>::type tw, int ntiles, const int* skip) {
   if (skip && *skip) return;
   using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, RPB = C::RPBC, CB = C::CB;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL;
-  constexpr int NT = RPB * P;
-  __shared__ cx<T> lds[RPB][2 * padded(n)];
+  using LL = LineLayout<C::LF, C::EFR>;
+  constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  __shared__ cx<T> lds[2 * RPB * S];
   const int tid = threadIdx.x;
-  const int row0 = blockIdx.x * RPB;
-  const size_t batch = blockIdx.y;
-  const cx<T>* src = work + batch * (size_t)n * 2 * n;
-  for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
-    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-    lds[rr][pad(cb * CB + c)] = src[((size_t)cb * n + row0 + rr) * CB + c];
-  }
-  __syncthreads();
-  const int r = tid / P, p = tid % P;
-  cx<T> v[2][E];
+  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* line[1] = {mine};
+  const cx<T>* l0 = lds + (2 * r) * S;
+  const cx<T>* l1 = l0 + S;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    {
+      const cx<T>* src = work + (size_t)(t / TPD) * n * 2 * n;
+      const int row0 = (t % TPD) * RPB;
+      for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+        const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+        const int k = cb * CB + c;
+        lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] = src[((size_t)cb * n + row0 + rr) * CB + c];
+      }
+    }
+    __syncthreads();
+    cx<T> v[1][E];
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int q = p + P * slot_elem<E, R0>(reg);
-    v[0][reg] = lds[r][pad(2 * q)];
-    v[1][reg] = lds[r][pad(2 * q + 1)];
-  }
-  __syncthreads();
-  cx<T>* lines[2] = {&lds[r][0], &lds[r][padded(n)]};
-  fft_lines<L, E, 2, +1>(v, lines, p, tw, 2);
-  const size_t roff = (batch * n + row0 + r) * n;
+    for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
+    __syncthreads();
+    fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) {
-    const int i = p + P * slot_elem<E, RL>(reg);
-    cx<T> y = v[0][reg] + tw.template mul<+1>(v[1][reg], i);
-    y = cscale(y, alpha);
-    if (add_input) y = y + vin[roff + i];
-    out[roff + i] = y;
+    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+    __syncthreads();
+    const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
+#pragma unroll
+    for (int tt = 0; tt < E / 2; ++tt) {
+      const int i = p + P * (l * (E / 2) + tt);
+      cx<T> y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
+      y = cscale(y, alpha);
+      if (add_input) y = y + vin[roff + i];
+      out[roff + i] = y;
+    }
+    __syncthreads();
   }
 }
 
@@ -405,7 +530,7 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::RPBC * Cfg<T, LOGN>::PF)) void k_row
 // Host launchers.
 template <typename T> typename TwOf<T>::type make_tw(const Plan& p);
 template <> TwD make_tw<double>(const Plan& p) { return TwD{p.tw64}; }
-template <> TwF make_tw<float>(const Plan& p) { return TwF{p.tw32hi, p.tw32lo}; }
+template <> TwF make_tw<float>(const Plan& p) { return TwF{p.tw32}; }
 
 template <typename T> const void* gtab_of(const Plan& p);
 template <> const void* gtab_of<double>(const Plan& p) { return p.g64; }
@@ -413,6 +538,27 @@ template <> const void* gtab_of<float>(const Plan& p) { return p.g32; }
 template <typename T> const T* gnyq_of(const Plan& p);
 template <> const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
 template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
+
+// Persistent grid: as many blocks as can be resident on the device at once
+// (occupancy per CU x CUs), never more than the number of tiles.
+static int blocks_per_cu(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;   // occupancy per kernel function
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, threads, 0) != hipSuccess || b < 1) b = 1;
+  cache[kernel] = b;
+  return b;
+}
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, int ntiles, int cus) {
+  if constexpr (!kPrefetch) return ntiles;         // one tile per block
+  const long g = (long)blocks_per_cu(reinterpret_cast<const void*>(kernel), threads) * cus;
+  return (int)(g < ntiles ? g : ntiles);
+}
 
 template <typename T, int LOGN>
 static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T* out, cx<T>* work,
@@ -422,23 +568,31 @@ static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T
   auto tw = make_tw<T>(pl);
   FsArgs none{};
   if (pass == 0) {
-    k_rows_fwd_real<T, LOGN><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(u, work, tw);
+    auto kf = k_rows_fwd_real<T, LOGN>;
+    const int nt = batch * (n / C::RPB);
+    kf<<<persistent_grid(kf, C::NT_RH, nt, pl.cus), C::NT_RH, 0, s>>>(u, work, tw, nt);
   } else if (pass == 1) {
     const T* g = static_cast<const T*>(gtab_of<T>(pl));
-    k_cols<T, T, LOGN, false, false><<<dim3(n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, gnyq_of<T>(pl),
-                                                                                       tw, none, nullptr);
+    k_cols<T, T, LOGN, false, false><<<dim3(n / C::CPB, batch), C::NT_C, 0, s>>>(work, g, gnyq_of<T>(pl), tw,
+                                                                                   none, nullptr);
   } else {
-    k_rows_inv_real<T, LOGN, false><<<dim3(n / C::RPB, batch), C::RPB * C::PH, 0, s>>>(work, out, tw, nullptr,
-                                                                                      none);
+    auto kf = k_rows_inv_real<T, LOGN, false>;
+    const int nt = batch * (n / C::RPB);
+    kf<<<persistent_grid(kf, C::NT_RH, nt, pl.cus), C::NT_RH, 0, s>>>(work, out, tw, nullptr, none, nt);
   }
   return hipGetLastError();
 }
 
 template <typename T, int LOGN>
 static hipError_t apply_real_n(const Plan& pl, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
-  for (int pass = 0; pass < 3; ++pass) {
-    hipError_t e = pass_real_n<T, LOGN>(pl, pass, batch, u, out, work, s);
-    if (e != hipSuccess) return e;
+  const size_t nn = (size_t)pl.n * pl.n;
+  const int chunk = apply_chunk(pl);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+    for (int pass = 0; pass < 3; ++pass) {
+      hipError_t e = pass_real_n<T, LOGN>(pl, pass, nb, u + b0 * nn, out + b0 * nn, work, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -450,9 +604,10 @@ static hipError_t fs_real_n(const Plan& pl, const T* ut, T* out, cx<T>* work, co
   constexpr int n = C::n;
   auto tw = make_tw<T>(pl);
   FsArgs f{d.shape, d.c1, d.c2, d.size, d.psi_r1, d.psi_r2};
-  k_cols<T, T, LOGN, false, true><<<dim3(n / C::CB, 1), C::CB * C::PF, 0, s>>>(work, nullptr, nullptr, tw, f,
-                                                                              nullptr);
-  k_rows_inv_real<T, LOGN, true><<<dim3(n / C::RPB, 1), C::RPB * C::PH, 0, s>>>(work, out, tw, ut, f);
+  k_cols<T, T, LOGN, false, true><<<dim3(n / C::CPB, 1), C::NT_C, 0, s>>>(work, nullptr, nullptr, tw, f, nullptr);
+  auto kr = k_rows_inv_real<T, LOGN, true>;
+  const int ntr = n / C::RPB;
+  kr<<<persistent_grid(kr, C::NT_RH, ntr, pl.cus), C::NT_RH, 0, s>>>(work, out, tw, ut, f, ntr);
   return hipGetLastError();
 }
 
@@ -464,17 +619,23 @@ static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* 
   auto tw = make_tw<T>(pl);
   FsArgs none{};
   if (pass == 0) {
-    if (m)
-      k_rows_fwd_cplx<T, LOGN, true><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
-    else
-      k_rows_fwd_cplx<T, LOGN, false><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(v, m, work, tw, skip);
+    const int nt = batch * (n / C::RPBC);
+    if (m) {
+      auto kf = k_rows_fwd_cplx<T, LOGN, true>;
+      kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
+    } else {
+      auto kf = k_rows_fwd_cplx<T, LOGN, false>;
+      kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
+    }
   } else if (pass == 1) {
     const cx<T>* g = static_cast<const cx<T>*>(gtab_of<T>(pl));
-    k_cols<T, cx<T>, LOGN, true, false><<<dim3(2 * n / C::CB, batch), C::CB * C::PF, 0, s>>>(work, g, nullptr,
-                                                                                           tw, none, skip);
+    k_cols<T, cx<T>, LOGN, true, false><<<dim3(2 * n / C::CPB, batch), C::NT_C, 0, s>>>(work, g, nullptr, tw,
+                                                                                       none, skip);
   } else {
-    k_rows_inv_cplx<T, LOGN><<<dim3(n / C::RPBC, batch), C::RPBC * C::PF, 0, s>>>(work, v, out, alpha,
-                                                                               add ? 1 : 0, tw, skip);
+    auto kf = k_rows_inv_cplx<T, LOGN>;
+    const int nt = batch * (n / C::RPBC);
+    kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(work, v, out, alpha, add ? 1 : 0, tw, nt,
+                                                                      skip);
   }
   return hipGetLastError();
 }
@@ -482,9 +643,14 @@ static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* 
 template <typename T, int LOGN>
 static hipError_t apply_cplx_n(const Plan& pl, int batch, const cx<T>* v, const T* m, T alpha, bool add,
                                cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
-  for (int pass = 0; pass < 3; ++pass) {
-    hipError_t e = pass_cplx_n<T, LOGN>(pl, pass, batch, v, m, alpha, add, out, work, s, skip);
-    if (e != hipSuccess) return e;
+  const size_t nn = (size_t)pl.n * pl.n;
+  const int chunk = apply_chunk(pl);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+    for (int pass = 0; pass < 3; ++pass) {
+      hipError_t e = pass_cplx_n<T, LOGN>(pl, pass, nb, v + b0 * nn, m, alpha, add, out + b0 * nn, work, s, skip);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

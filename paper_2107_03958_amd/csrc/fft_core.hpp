@@ -35,14 +35,17 @@ template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-// LDS index padding: one slot every 16 elements breaks power-of-two strides.
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // ---------------------------------------------------------------------------
 // Twiddle tables.  w(m) = exp(-2 pi i m / TWN); SGN = -1 forward, +1 inverse.
+// FP64: a butterfly loads its base twiddle w^jm once and forms the powers
+// w^(jm r) by repeated multiplication (a few ulps, far below the FP64 error of
+// the transform).  FP32: every twiddle is read as the pair (hi, lo) of floats
+// rounded from FP64 (one 16-byte load) and applied as x*hi + x*lo.
 struct TwD {
   const cx<double>* t;
+  static constexpr bool kPowers = true;
   template <int SGN>
   __device__ __forceinline__ cx<double> mul(cx<double> x, int m) const {
     cx<double> w = t[m];
@@ -55,12 +58,15 @@ struct TwD {
   }
 };
 
+struct alignas(16) TwPair { float hx, hy, lx, ly; };
+
 struct TwF {
-  const cx<float>* hi;
-  const cx<float>* lo;
+  const TwPair* t;
+  static constexpr bool kPowers = false;
   template <int SGN>
   __device__ __forceinline__ cx<float> mul(cx<float> x, int m) const {
-    cx<float> h = hi[m], l = lo[m];
+    const TwPair w = t[m];
+    const cx<float> h = {w.hx, w.hy}, l = {w.lx, w.ly};
     return SGN < 0 ? cmul(x, h) + cmul(x, l) : cmulc(x, h) + cmulc(x, l);
   }
 };
@@ -156,12 +162,21 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 }
 
 // ---------------------------------------------------------------------------
-// Radix plan for a line of length L with E elements per thread.
+// Radix plan for a line of length L with E elements per thread: the fewest
+// stages with radix <= min(E, 16), radices as equal as possible (larger first).
 template <int L, int E, int NS>
 struct Radix {
   static constexpr int RMAX = E < 16 ? E : 16;
-  static constexpr int REM = L / NS;
-  static constexpr int R = REM < RMAX ? REM : RMAX;   // radix of stage with span NS
+  static constexpr int lg(int x) { return x <= 1 ? 0 : 1 + lg(x / 2); }
+  static constexpr int LOGL = lg(L), LOGR = lg(RMAX);
+  static constexpr int STAGES = LOGL == 0 ? 1 : (LOGL + LOGR - 1) / LOGR;
+  static constexpr int DONE = lg(NS);                       // log2 of the span already covered
+  static constexpr int idx() {                              // index of the stage with span NS
+    int d = 0, i = 0;
+    while (d < DONE) { d += LOGL / STAGES + (i < LOGL % STAGES ? 1 : 0); ++i; }
+    return i;
+  }
+  static constexpr int R = 1 << (LOGL / STAGES + (idx() < LOGL % STAGES ? 1 : 0));
 };
 
 // Position s (element p + P*s) of register slot `reg` for a stage of radix R.
@@ -171,12 +186,34 @@ __host__ __device__ constexpr int slot_elem(int reg) { return reg / R + (reg % R
 // Radix of the first and the last stage.
 template <int L, int E> struct FirstLast {
   static constexpr int R0 = Radix<L, E, 1>::R;
-  static constexpr int last_ns() {
-    int ns = 1;
-    while (ns * Radix<L, E, 1>::RMAX < L) ns *= Radix<L, E, 1>::RMAX;
-    return ns;
+  static constexpr int last_ns() {             // span of the last stage
+    int d = 0, i = 0;
+    const int LOGL = Radix<L, E, 1>::LOGL, ST = Radix<L, E, 1>::STAGES;
+    while (i < ST - 1) { d += LOGL / ST + (i < LOGL % ST ? 1 : 0); ++i; }
+    return 1 << d;
   }
   static constexpr int RL = L / last_ns();
+};
+
+// LDS layout of one line of length L (E elements per thread): one padding slot
+// after every R0 elements (R0 = first-stage radix), so the stride-R0 writes of
+// the first exchange and the stride-2 accesses of the even/odd halves fall on
+// distinct banks; consecutive lines are STRIDE elements apart, which rotates
+// their bases by two slots so lines read side by side use different banks.
+template <int L, int E>
+struct LineLayout {
+  static constexpr int SH = ilog2(FirstLast<L, E>::R0);
+  static constexpr int LEN = L + (L >> SH);
+  static constexpr int STRIDE = LEN + 2;
+  __device__ __forceinline__ static int pad(int i) { return i + (i >> SH); }
+  // Padded index of element p + (L/E) * s: pad(p) + s * PSTEP when L/E is a multiple of R0.
+  static constexpr int P_ = L / E;
+  static constexpr int PSTEP = P_ + (P_ >> SH);
+  static constexpr bool LINEAR = (P_ % (1 << SH)) == 0;
+  __device__ __forceinline__ static int pad_ps(int p, int s) {
+    if constexpr (LINEAR) return pad(p) + s * PSTEP;
+    else return pad(p + P_ * s);
+  }
 };
 
 // Butterflies of one stage on every line a thread holds.
@@ -189,11 +226,22 @@ __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW
     if constexpr (NS > 1) {
       const int jm = j % NS;
       const int unit = (L / (NS * R)) * twstep;   // w_{NS R} in table units
+      if constexpr (TW::kPowers) {
+        const cx<T> w1 = tw.template get<SGN>(jm * unit);
+        cx<T> wr = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int m = jm * r * unit;
+        for (int r = 1; r < R; ++r) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l) v[l][q * R + r] = tw.template mul<SGN>(v[l][q * R + r], m);
+          for (int l = 0; l < NL; ++l) v[l][q * R + r] = cmul(v[l][q * R + r], wr);
+          if (r + 1 < R) wr = cmul(wr, w1);
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int m = jm * r * unit;
+#pragma unroll
+          for (int l = 0; l < NL; ++l) v[l][q * R + r] = tw.template mul<SGN>(v[l][q * R + r], m);
+        }
       }
     }
 #pragma unroll
@@ -202,26 +250,36 @@ __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW
 }
 
 // Exchange through LDS between stage (R, NS) and the next stage of radix R2.
+// With one padding slot per R0 elements (R0 = first radix >= every radix),
+// pad(b + r * NS) = pad(b) + r * (NS + NS / R0) for NS >= R0 and
+// pad(b + r) = pad(b) + r for the first stage (b a multiple of R0), so every
+// access is a per-butterfly base plus a compile-time offset.
 template <int L, int E, int NL, int R, int NS, int R2, typename T>
 __device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], cx<T>* const* lds, int p) {
+  using LL = LineLayout<L, E>;
   constexpr int P = L / E;
+  constexpr int R0 = FirstLast<L, E>::R0;
+  static_assert(NS == 1 ? R == R0 : NS % R0 == 0, "stage span must be a multiple of the first radix");
+  static_assert((L / R2) % R0 == 0, "exchange stride must be a multiple of the first radix");
+  constexpr int WSTEP = NS == 1 ? 1 : NS + NS / R0;
+  constexpr int RSTEP = L / R2 + (L / R2) / R0;
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
     const int j = p + q * P;
-    const int base = (j / NS) * NS * R + (j % NS);
+    const int pb = LL::pad((j / NS) * NS * R + (j % NS));
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int l = 0; l < NL; ++l) lds[l][pad(base + r * NS)] = v[l][q * R + r];
+      for (int l = 0; l < NL; ++l) lds[l][pb + r * WSTEP] = v[l][q * R + r];
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < E / R2; ++q) {
-    const int j = p + q * P;
+    const int pb = LL::pad(p + q * P);
 #pragma unroll
     for (int r = 0; r < R2; ++r)
 #pragma unroll
-      for (int l = 0; l < NL; ++l) v[l][q * R2 + r] = lds[l][pad(j + r * (L / R2))];
+      for (int l = 0; l < NL; ++l) v[l][q * R2 + r] = lds[l][pb + r * RSTEP];
   }
   __syncthreads();
 }
@@ -240,7 +298,7 @@ __device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], cx<T>* const* lds,
 
 // Full transform of NL lines of length L.  On entry register slot `reg` holds
 // element p + P*slot_elem<E,R0>(reg); on exit element p + P*slot_elem<E,RL>(reg).
-// twstep = TWN / L.  Uses the LDS line buffers lds[l] (padded(L) elements each)
+// twstep = TWN / L.  Uses the LDS line buffers lds[l] (LineLayout<L,E>::LEN elements)
 // and contains __syncthreads(): every thread of the block must call it.
 template <int L, int E, int NL, int SGN, typename T, typename TW>
 __device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,

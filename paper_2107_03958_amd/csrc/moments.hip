@@ -186,15 +186,14 @@ __global__ void k_table(int n, int ncols, KernelArgs K, double inv, int cplx, do
   }
 }
 
-__global__ void k_twiddles(int nb, cx<double>* t64, cx<float>* hi, cx<float>* lo) {
+__global__ void k_twiddles(int nb, cx<double>* t64, TwPair* t32) {
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nb; m += gridDim.x * blockDim.x) {
     double s, c;
     sincospi(-2.0 * (double)m / nb, &s, &c);         // exp(-2 pi i m / nb)
     t64[m] = {c, s};
-    if (hi) {
+    if (t32) {
       const float ch = (float)c, sh = (float)s;
-      hi[m] = {ch, sh};
-      lo[m] = {(float)(c - (double)ch), (float)(s - (double)sh)};
+      t32[m] = {ch, sh, (float)(c - (double)ch), (float)(s - (double)sh)};
     }
   }
 }
@@ -230,7 +229,7 @@ hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
   const int n = pl.n, nb = pl.nb;
   const double inv = 1.0 / ((double)nb * nb);
   const int threads = 256;
-  k_twiddles<<<(nb + threads - 1) / threads, threads, 0, s>>>(nb, pl.tw64, pl.tw32hi, pl.tw32lo);
+  k_twiddles<<<(nb + threads - 1) / threads, threads, 0, s>>>(nb, pl.tw64, pl.tw32);
   const int ncols = pl.cplx ? 2 * n : n;
   const size_t total = (size_t)ncols * (n + 1);
   const int blocks = (int)std::min<size_t>((total + threads - 1) / threads, 65536);

@@ -8,12 +8,51 @@
 
 namespace ws {
 
-// Column-block width of the blocked half-spectrum layout T[cb][row][c]: a
-// column pass reads one contiguous block of n rows x CB columns, and a row
-// pass over RPB rows writes RPB*CB contiguous elements per block (128 bytes).
+// Tile parameters (compile-time; the defaults were chosen by measurement on MI355X).
+//  CB:  column-block width of the blocked intermediate T[cb][row][c]: a column pass
+//       reads one contiguous block of n rows x CB columns; a row pass over RPB rows
+//       writes RPB x CB contiguous elements per block.
+//  RPB: rows per block of the row passes.
+//  ER / EC: elements per thread of a row / column line (raised where needed to keep
+//       a block within 1024 threads).
+//  CHUNK: a batch is run through all three passes CHUNK_BYTES of intermediate at a
+//       time, so the intermediate of a chunk stays in the 256 MB Infinity Cache
+//       between the passes instead of round-tripping through HBM.
+#ifndef WS_CB64
+#define WS_CB64 2
+#endif
+#ifndef WS_RPB64
+#define WS_RPB64 2
+#endif
+#ifndef WS_ER64
+#define WS_ER64 16
+#endif
+#ifndef WS_EC64
+#define WS_EC64 16
+#endif
+#ifndef WS_CB32
+#define WS_CB32 4
+#endif
+#ifndef WS_RPB32
+#define WS_RPB32 4
+#endif
+#ifndef WS_ER32
+#define WS_ER32 8
+#endif
+#ifndef WS_EC32
+#define WS_EC32 8
+#endif
+#ifndef WS_CHUNK_BYTES
+#define WS_CHUNK_BYTES (128u << 20)
+#endif
+
 template <typename T> struct Layout;
-template <> struct Layout<double> { static constexpr int CB = 2; static constexpr int RPB = 4; };
-template <> struct Layout<float> { static constexpr int CB = 4; static constexpr int RPB = 4; };
+template <> struct Layout<double> {
+  static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, EC = WS_EC64;
+};
+template <> struct Layout<float> {
+  static constexpr int CB = WS_CB32, RPB = WS_RPB32, ER = WS_ER32, EC = WS_EC32;
+};
 
 struct Plan {
   ws_kernel kern;
@@ -27,11 +66,18 @@ struct Plan {
   void* g32 = nullptr;        // FP32 copy (WS_FP32 plans)
   float* gnyq32 = nullptr;
   cx<double>* tw64 = nullptr; // exp(-2 pi i m / nb), m in [0, nb)
-  cx<float>* tw32hi = nullptr;
-  cx<float>* tw32lo = nullptr;
+  TwPair* tw32 = nullptr;     // (hi, lo) float pairs of the same twiddles
+  int cus = 256;               // compute units of the plan's device (persistent grids)
   size_t plan_bytes = 0;
   size_t work_bytes = 0;      // per density
 };
+
+// Densities run through all three passes at a time (intermediate <= WS_CHUNK_BYTES).
+inline int apply_chunk(const Plan& p) {
+  const size_t per = (size_t)p.n * (p.cplx ? 2 * p.n : p.n) * (p.precision == WS_FP64 ? 16 : 8);
+  const size_t c = (size_t)WS_CHUNK_BYTES / per;
+  return c < 1 ? 1 : (c > 65535 ? 65535 : (int)c);
+}
 
 // Sizes (in elements) of the moment tables for a plan.
 inline size_t table_elems(int n, bool cplx) {
