@@ -1,0 +1,130 @@
+"""Measured HBM traffic of the apply kernels from rocprofv3 PMC counters.
+
+Two modes:
+
+* ``python -m paper_2107_03958_amd.traffic target``: a short workload to run
+  under ``rocprofv3 --pmc FETCH_SIZE`` (then ``--pmc WRITE_SIZE``).  It applies
+  the FP64 plan for log|x| at n = 2048 to 4 densities (two chunks) and then
+  copies a 512 MiB device buffer, whose counters calibrate the byte scale.
+* ``python -m paper_2107_03958_amd.traffic summarise FETCH_DIR WRITE_DIR OUT``:
+  reads the two ``*_counter_collection.csv`` files, scales each kernel's
+  average counter per dispatch by the copy's (known bytes / counter), and
+  writes OUT.json (plus OUT.md) with a hash of the kernel sources, so a reader
+  can tell whether the figures still describe the current kernels.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def target() -> None:
+    import numpy as np
+    import torch
+
+    from . import api
+    n = 2048
+    plan = api.ConvPlan("log", n=n)
+    u = torch.as_tensor(np.random.default_rng(0).normal(size=(4, n, n))).cuda()
+    out = torch.empty_like(u)
+    work = torch.empty(plan.chunk * plan.work_bytes, dtype=torch.uint8, device="cuda")
+    plan.apply(u, out=out, work=work)
+    torch.cuda.synchronize()
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"target": "done", "chunk": plan.chunk}), flush=True)
+
+
+def _read(d: str, counter: str) -> dict:
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    acc: dict[str, list[float]] = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
+    fetch = _read(fetch_dir, "FETCH_SIZE")
+    write = _read(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    if not copy:
+        raise RuntimeError("calibration copy kernel not found in the counters")
+    ck = max(copy, key=lambda k: fetch[k])
+    f_scale = COPY_BYTES / (fetch[ck] * 1024.0)
+    w_scale = COPY_BYTES / (write[ck] * 1024.0)
+    kernels = {}
+    for k in fetch:
+        if not k.startswith("ws::k_"):
+            continue
+        kernels[k] = dict(fetch_kib=fetch[k], write_kib=write.get(k, 0.0),
+                          read_bytes=fetch[k] * 1024.0 * f_scale,
+                          write_bytes=write.get(k, 0.0) * 1024.0 * w_scale)
+        kernels[k]["traffic_bytes"] = kernels[k]["read_bytes"] + kernels[k]["write_bytes"]
+    res = dict(source_hash=source_hash(), calibration_kernel=ck, fetch_scale=f_scale, write_scale=w_scale,
+               copy_bytes=COPY_BYTES, workload="FP64 log|x| plan, n=2048, 4 densities (per-dispatch averages)",
+               kernels=kernels)
+    with open(out + ".json", "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["# HBM traffic per dispatch, FP64 apply at n=2048 (rocprofv3 PMC)", "",
+             "Commands (from the repository root $R on the GPU box):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp",
+             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o p --output-format csv -- "
+             "python3 -m paper_2107_03958_amd.traffic target",
+             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o p --output-format csv -- "
+             "python3 -m paper_2107_03958_amd.traffic target",
+             "python3 -m paper_2107_03958_amd.traffic summarise $R/gpurun_out/pmc_fetch $R/gpurun_out/pmc_write "
+             "profiles/apply_fp64_2048_traffic", "```", "",
+             f"Calibration: `{ck}` copying {COPY_BYTES >> 20} MiB read FETCH_SIZE {fetch[ck]:.0f} KiB "
+             f"(scale {f_scale:.3f}) and WRITE_SIZE {write[ck]:.0f} KiB (scale {w_scale:.3f}).", "",
+             "| kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (MB) | written (MB) |", "|---|---|---|---|---|"]
+    for k, v in kernels.items():
+        lines.append(f"| `{k}` | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['read_bytes'] / 1e6:.1f} | "
+                     f"{v['write_bytes'] / 1e6:.1f} |")
+    lines += ["", f"Kernel source hash: `{res['source_hash']}`."]
+    with open(out + ".md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return res
+
+
+def load_for_current_sources(path: str):
+    """The stored traffic summary if it was taken with the current kernel sources, else None."""
+    try:
+        with open(path) as fh:
+            res = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return res if res.get("source_hash") == source_hash() else None
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "target":
+        target()
+    elif len(sys.argv) == 5 and sys.argv[1] == "summarise":
+        print(json.dumps(summarise(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+    else:
+        print(__doc__)
+        sys.exit(2)
