@@ -53,6 +53,25 @@ def pass_bytes(n: int, s: int) -> list[float]:
     return [3.0 * n * n * s, 4.0 * n * n * s + (n + 1) * (n + 1) * s, 3.0 * n * n * s]
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_fp64_2048_traffic.json")
+
+
+def measured_traffic(kernel: str, precision: str, n: int, chunk: int):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE + WRITE_SIZE,
+    calibrated by a copy of known size), or None when the summary does not describe these
+    kernel sources, this precision or this launch shape."""
+    from paper_2107_03958_amd import traffic
+    if precision != "fp64" or n != 2048:
+        return None
+    res = traffic.load_for_current_sources(TRAFFIC_SUMMARY)
+    if res is None or res.get("densities_per_dispatch") != chunk:
+        return None
+    for name, v in res["kernels"].items():
+        if name.startswith("ws::" + kernel + "<double"):
+            return v["traffic_bytes"]
+    return None
+
+
 def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
     dt = torch.float64 if precision == "fp64" else torch.float32
     s = 8 if precision == "fp64" else 4
@@ -117,7 +136,8 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
     per_launch = pb[dom] * batch / ng                  # algorithmic bytes of one launch (average group)
     achieved = per_launch / (avg_pass_ms[dom] * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=achieved, peak=PEAK_HBM_GBPS,
-                           unit="GB/s", frac=achieved / PEAK_HBM_GBPS, traffic=None,
+                           unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
+                           traffic=measured_traffic(PASS_NAMES[dom], precision, n, chunk),
                            bytes_per_launch=per_launch, launch_avg_ms=float(avg_pass_ms[dom]))
     # Keep the last outputs of the first kernel for the FP32-vs-FP64 comparison.
     plans[0].apply(u, out=out, work=work)

@@ -19,14 +19,7 @@
 // write RPB x CB contiguous elements per block.
 #include <hip/hip_runtime.h>
 
-#include <mutex>
-#include <unordered_map>
-
 #include "plan.hpp"
-
-#ifndef WS_CPB
-#define WS_CPB 1      // 0: a column block holds CB columns; 1: one column, XCD-paired blocks
-#endif
 
 namespace ws {
 
@@ -47,7 +40,7 @@ struct Cfg {
   static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
   // Column passes: two full-length lines (even/odd frequencies) per column,
   // CPB columns per block (CPB = CB, or 1 with XCD-paired blocks).
-  static constexpr int CPB = WS_CPB == 0 ? CB : 1;
+  static constexpr int CPB = Layout<T>::CPB1 ? 1 : CB;
   static constexpr int LF = n;
   static constexpr int EF = cap(Layout<T>::EC, 2 * CPB, LF);
   static constexpr int PF = LF / EF;
@@ -75,6 +68,9 @@ struct Cfg {
   static constexpr int NT_RC = 2 * RPBC * PFR;
   static constexpr int SFR = LineLayout<LF, EFR>::STRIDE;
   static constexpr int WAVES_RC = waves(NT_RC, 2 * RPBC * SFR * (int)sizeof(cx<T>));
+  // Row tiles sharing 128-byte lines of the intermediate (real and complex row passes).
+  static constexpr int RG = 128 / (RPB * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPB * CB * (int)sizeof(cx<T>)) : 1;
+  static constexpr int RGC = 128 / (RPBC * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPBC * CB * (int)sizeof(cx<T>)) : 1;
 };
 
 // Thread -> (column c, line l, p) of a column pass.  When a wave can hold
@@ -111,6 +107,23 @@ __device__ __forceinline__ void xcd_group(int b, int& major, int& minor) {
   } else {
     minor = (b / kXcds) % G;
     major = (b / (kXcds * G)) * kXcds + b % kXcds;
+  }
+}
+
+// Row tiles: G consecutive tiles (RPB rows each) share the 128-byte lines of
+// the blocked intermediate when RPB x CB elements are narrower than a line;
+// the tiles of such a group go to blocks 8 apart.  Blocks past the last whole
+// group of 8 G keep the identity map.
+template <int G>
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  if constexpr (G <= 1) {
+    return b;
+  } else {
+    const int full = ntiles - ntiles % (kXcds * G);
+    if (b >= full) return b;
+    int major, minor;
+    xcd_group<G>(b, major, minor);
+    return major * G + minor;
   }
 }
 
@@ -161,14 +174,8 @@ __device__ inline double fs_window(double x1, double x2, const FsArgs& f) {
   return fs_step((r - f.r1) / (f.r2 - f.r1));
 }
 
-// All pass kernels are persistent: a block walks the tiles t = blockIdx.x,
-// blockIdx.x + gridDim.x, ...  With kPrefetch the row passes load the next
-// tile's global data into registers right after consuming the current one, so
-// HBM traffic of one tile overlaps the LDS/FFT phases of the previous one.
-#ifndef WS_PREFETCH
-#define WS_PREFETCH 0
-#endif
-constexpr bool kPrefetch = WS_PREFETCH != 0;
+// Row passes launch one block per tile (RPB rows of one density), the tile
+// index taken through xcd_tile so tiles that share lines meet in one L2.
 
 // ----------------------------------------------------------------------------
 // Real path, forward row pass: rows j1 < n of a real density -> half spectrum
@@ -191,27 +198,21 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_fwd_real(
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
   cx<T> x[E];
-  auto load = [&](int tile) {
-    const size_t batch = tile / TPD;
-    const int row = (tile % TPD) * RPB + r;
+  if ((int)blockIdx.x >= ntiles) return;
+  const int t = xcd_tile<C::RG>(blockIdx.x, ntiles);
+  {
+    const size_t batch = t / TPD;
+    const int row = (t % TPD) * RPB + r;
     const cx<T>* src = reinterpret_cast<const cx<T>*>(u + (batch * n + row) * n);
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) x[reg] = src[p + P * slot_elem<E, R0>(reg)];
-  };
-  int t = blockIdx.x;
-  if constexpr (kPrefetch) {
-    if (t < ntiles) load(t);
   }
-  for (; t < ntiles; t += gridDim.x) {
-    if constexpr (!kPrefetch) load(t);
+  {
     cx<T> v[1][E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int m = p + P * slot_elem<E, R0>(reg);
       v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
-    }
-    if constexpr (kPrefetch) {
-      if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);
     }
     fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
 #pragma unroll
@@ -237,7 +238,6 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_fwd_real(
       }
       dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
     }
-    __syncthreads();
   }
 }
 
@@ -367,7 +367,9 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_inv_real(
   cx<T>* line[1] = {mine};
   const cx<T>* l0 = lds + (2 * r) * S;
   const cx<T>* l1 = l0 + S;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  if ((int)blockIdx.x >= ntiles) return;
+  const int t = xcd_tile<C::RG>(blockIdx.x, ntiles);
+  {
     {
       const cx<T>* src = work + (size_t)(t / TPD) * n * n;
       const int row0 = (t % TPD) * RPB;
@@ -416,7 +418,6 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_inv_real(
       }
       dst[m] = zz;
     }
-    __syncthreads();
   }
 }
 
@@ -437,30 +438,24 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_fwd_cplx(
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
   cx<T> x[E];
-  auto load = [&](int tile) {
-    const int row = (tile % TPD) * RPB + r;
-    const size_t roff = ((size_t)(tile / TPD) * n + row) * n;
+  if ((int)blockIdx.x >= ntiles) return;
+  const int t = xcd_tile<C::RGC>(blockIdx.x, ntiles);
+  {
+    const int row = (t % TPD) * RPB + r;
+    const size_t roff = ((size_t)(t / TPD) * n + row) * n;
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
       x[reg] = vin[roff + j];
       if constexpr (MUL) x[reg] = cscale(x[reg], mcon[(size_t)row * n + j]);
     }
-  };
-  int t = blockIdx.x;
-  if constexpr (kPrefetch) {
-    if (t < ntiles) load(t);
   }
-  for (; t < ntiles; t += gridDim.x) {
-    if constexpr (!kPrefetch) load(t);
+  {
     cx<T> v[1][E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
       v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
-    }
-    if constexpr (kPrefetch) {
-      if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);
     }
     fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
 #pragma unroll
@@ -473,7 +468,6 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_fwd_cplx(
       const int k = cb * CB + c;
       dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
     }
-    __syncthreads();
   }
 }
 
@@ -494,7 +488,9 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_inv_cplx(
   cx<T>* line[1] = {mine};
   const cx<T>* l0 = lds + (2 * r) * S;
   const cx<T>* l1 = l0 + S;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  if ((int)blockIdx.x >= ntiles) return;
+  const int t = xcd_tile<C::RGC>(blockIdx.x, ntiles);
+  {
     {
       const cx<T>* src = work + (size_t)(t / TPD) * n * 2 * n;
       const int row0 = (t % TPD) * RPB;
@@ -522,7 +518,6 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_inv_cplx(
       if (add_input) y = y + vin[roff + i];
       out[roff + i] = y;
     }
-    __syncthreads();
   }
 }
 
@@ -539,27 +534,6 @@ template <typename T> const T* gnyq_of(const Plan& p);
 template <> const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
 template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
 
-// Persistent grid: as many blocks as can be resident on the device at once
-// (occupancy per CU x CUs), never more than the number of tiles.
-static int blocks_per_cu(const void* kernel, int threads) {
-  static std::mutex mu;
-  static std::unordered_map<const void*, int> cache;   // occupancy per kernel function
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(kernel);
-  if (it != cache.end()) return it->second;
-  int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, threads, 0) != hipSuccess || b < 1) b = 1;
-  cache[kernel] = b;
-  return b;
-}
-
-template <typename K>
-static int persistent_grid(K kernel, int threads, int ntiles, int cus) {
-  if constexpr (!kPrefetch) return ntiles;         // one tile per block
-  const long g = (long)blocks_per_cu(reinterpret_cast<const void*>(kernel), threads) * cus;
-  return (int)(g < ntiles ? g : ntiles);
-}
-
 template <typename T, int LOGN>
 static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T* out, cx<T>* work,
                               hipStream_t s) {
@@ -570,7 +544,7 @@ static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T
   if (pass == 0) {
     auto kf = k_rows_fwd_real<T, LOGN>;
     const int nt = batch * (n / C::RPB);
-    kf<<<persistent_grid(kf, C::NT_RH, nt, pl.cus), C::NT_RH, 0, s>>>(u, work, tw, nt);
+    kf<<<nt, C::NT_RH, 0, s>>>(u, work, tw, nt);
   } else if (pass == 1) {
     const T* g = static_cast<const T*>(gtab_of<T>(pl));
     k_cols<T, T, LOGN, false, false><<<dim3(n / C::CPB, batch), C::NT_C, 0, s>>>(work, g, gnyq_of<T>(pl), tw,
@@ -578,7 +552,7 @@ static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T
   } else {
     auto kf = k_rows_inv_real<T, LOGN, false>;
     const int nt = batch * (n / C::RPB);
-    kf<<<persistent_grid(kf, C::NT_RH, nt, pl.cus), C::NT_RH, 0, s>>>(work, out, tw, nullptr, none, nt);
+    kf<<<nt, C::NT_RH, 0, s>>>(work, out, tw, nullptr, none, nt);
   }
   return hipGetLastError();
 }
@@ -607,7 +581,7 @@ static hipError_t fs_real_n(const Plan& pl, const T* ut, T* out, cx<T>* work, co
   k_cols<T, T, LOGN, false, true><<<dim3(n / C::CPB, 1), C::NT_C, 0, s>>>(work, nullptr, nullptr, tw, f, nullptr);
   auto kr = k_rows_inv_real<T, LOGN, true>;
   const int ntr = n / C::RPB;
-  kr<<<persistent_grid(kr, C::NT_RH, ntr, pl.cus), C::NT_RH, 0, s>>>(work, out, tw, ut, f, ntr);
+  kr<<<ntr, C::NT_RH, 0, s>>>(work, out, tw, ut, f, ntr);
   return hipGetLastError();
 }
 
@@ -622,10 +596,10 @@ static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* 
     const int nt = batch * (n / C::RPBC);
     if (m) {
       auto kf = k_rows_fwd_cplx<T, LOGN, true>;
-      kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
+      kf<<<nt, C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
     } else {
       auto kf = k_rows_fwd_cplx<T, LOGN, false>;
-      kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
+      kf<<<nt, C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
     }
   } else if (pass == 1) {
     const cx<T>* g = static_cast<const cx<T>*>(gtab_of<T>(pl));
@@ -634,7 +608,7 @@ static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* 
   } else {
     auto kf = k_rows_inv_cplx<T, LOGN>;
     const int nt = batch * (n / C::RPBC);
-    kf<<<persistent_grid(kf, C::NT_RC, nt, pl.cus), C::NT_RC, 0, s>>>(work, v, out, alpha, add ? 1 : 0, tw, nt,
+    kf<<<nt, C::NT_RC, 0, s>>>(work, v, out, alpha, add ? 1 : 0, tw, nt,
                                                                       skip);
   }
   return hipGetLastError();

@@ -15,6 +15,9 @@ namespace ws {
 //  RPB: rows per block of the row passes.
 //  ER / EC: elements per thread of a row / column line (raised where needed to keep
 //       a block within 1024 threads).
+//  CPB: 1 = a column-pass block transforms one column and the CB blocks of a
+//       block-column run 8 apart (same XCD, shared L2 lines); 0 = one block
+//       transforms all CB columns of a block-column.
 //  CHUNK: a batch is run through all three passes CHUNK_BYTES of intermediate at a
 //       time, so the intermediate of a chunk stays in the 256 MB Infinity Cache
 //       between the passes instead of round-tripping through HBM.
@@ -34,13 +37,19 @@ namespace ws {
 #define WS_CB32 4
 #endif
 #ifndef WS_RPB32
-#define WS_RPB32 4
+#define WS_RPB32 2
 #endif
 #ifndef WS_ER32
-#define WS_ER32 8
+#define WS_ER32 16
 #endif
 #ifndef WS_EC32
-#define WS_EC32 8
+#define WS_EC32 16
+#endif
+#ifndef WS_CPB64
+#define WS_CPB64 1
+#endif
+#ifndef WS_CPB32
+#define WS_CPB32 1
 #endif
 #ifndef WS_CHUNK_BYTES
 #define WS_CHUNK_BYTES (128u << 20)
@@ -48,10 +57,10 @@ namespace ws {
 
 template <typename T> struct Layout;
 template <> struct Layout<double> {
-  static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, EC = WS_EC64;
+  static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, EC = WS_EC64, CPB1 = WS_CPB64;
 };
 template <> struct Layout<float> {
-  static constexpr int CB = WS_CB32, RPB = WS_RPB32, ER = WS_ER32, EC = WS_EC32;
+  static constexpr int CB = WS_CB32, RPB = WS_RPB32, ER = WS_ER32, EC = WS_EC32, CPB1 = WS_CPB32;
 };
 
 struct Plan {
@@ -67,7 +76,7 @@ struct Plan {
   float* gnyq32 = nullptr;
   cx<double>* tw64 = nullptr; // exp(-2 pi i m / nb), m in [0, nb)
   TwPair* tw32 = nullptr;     // (hi, lo) float pairs of the same twiddles
-  int cus = 256;               // compute units of the plan's device (persistent grids)
+  int cus = 256;               // compute units of the plan's device
   size_t plan_bytes = 0;
   size_t work_bytes = 0;      // per density
 };

@@ -2,11 +2,11 @@
 
 Two modes:
 
-* ``python -m paper_2107_03958_amd.traffic target``: a short workload to run
+* ``python paper_2107_03958_amd/traffic.py target``: a short workload to run
   under ``rocprofv3 --pmc FETCH_SIZE`` (then ``--pmc WRITE_SIZE``).  It applies
   the FP64 plan for log|x| at n = 2048 to 4 densities (two chunks) and then
   copies a 512 MiB device buffer, whose counters calibrate the byte scale.
-* ``python -m paper_2107_03958_amd.traffic summarise FETCH_DIR WRITE_DIR OUT``:
+* ``python paper_2107_03958_amd/traffic.py summarise FETCH_DIR WRITE_DIR OUT``:
   reads the two ``*_counter_collection.csv`` files, scales each kernel's
   average counter per dispatch by the copy's (known bytes / counter), and
   writes OUT.json (plus OUT.md) with a hash of the kernel sources, so a reader
@@ -38,7 +38,11 @@ def target() -> None:
     import numpy as np
     import torch
 
-    from . import api
+    if __package__:
+        from . import api
+    else:
+        sys.path.insert(0, os.path.dirname(HERE))
+        from paper_2107_03958_amd import api
     n = 2048
     plan = api.ConvPlan("log", n=n)
     u = torch.as_tensor(np.random.default_rng(0).normal(size=(4, n, n))).cuda()
@@ -67,6 +71,15 @@ def _read(d: str, counter: str) -> dict:
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def _chunk(d: str) -> int:
+    """Densities per apply dispatch, as printed by the target run (log next to the counter directory)."""
+    with open(d.rstrip("/") + ".log") as fh:
+        for line in fh:
+            if line.startswith("{") and '"target"' in line:
+                return int(json.loads(line)["chunk"])
+    raise RuntimeError(f"no target line in {d}.log")
+
+
 def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
     fetch = _read(fetch_dir, "FETCH_SIZE")
     write = _read(write_dir, "WRITE_SIZE")
@@ -84,7 +97,7 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
                           read_bytes=fetch[k] * 1024.0 * f_scale,
                           write_bytes=write.get(k, 0.0) * 1024.0 * w_scale)
         kernels[k]["traffic_bytes"] = kernels[k]["read_bytes"] + kernels[k]["write_bytes"]
-    res = dict(source_hash=source_hash(), calibration_kernel=ck, fetch_scale=f_scale, write_scale=w_scale,
+    res = dict(source_hash=source_hash(), densities_per_dispatch=_chunk(fetch_dir), calibration_kernel=ck, fetch_scale=f_scale, write_scale=w_scale,
                copy_bytes=COPY_BYTES, workload="FP64 log|x| plan, n=2048, 4 densities (per-dispatch averages)",
                kernels=kernels)
     with open(out + ".json", "w") as fh:
@@ -93,11 +106,12 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
              "Commands (from the repository root $R on the GPU box):", "", "```",
              "cd /tmp && export TMPDIR=/tmp",
              "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o p --output-format csv -- "
-             "python3 -m paper_2107_03958_amd.traffic target",
+             "python3 $R/paper_2107_03958_amd/traffic.py target > $R/gpurun_out/pmc_fetch.log",
              "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o p --output-format csv -- "
-             "python3 -m paper_2107_03958_amd.traffic target",
-             "python3 -m paper_2107_03958_amd.traffic summarise $R/gpurun_out/pmc_fetch $R/gpurun_out/pmc_write "
+             "python3 $R/paper_2107_03958_amd/traffic.py target > $R/gpurun_out/pmc_write.log",
+             "cd $R && python3 paper_2107_03958_amd/traffic.py summarise gpurun_out/pmc_fetch gpurun_out/pmc_write "
              "profiles/apply_fp64_2048_traffic", "```", "",
+             f"Each apply dispatch covers {res['densities_per_dispatch']} densities.", "",
              f"Calibration: `{ck}` copying {COPY_BYTES >> 20} MiB read FETCH_SIZE {fetch[ck]:.0f} KiB "
              f"(scale {f_scale:.3f}) and WRITE_SIZE {write[ck]:.0f} KiB (scale {w_scale:.3f}).", "",
              "| kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | read (MB) | written (MB) |", "|---|---|---|---|---|"]

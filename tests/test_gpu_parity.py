@@ -11,7 +11,7 @@ import pytest
 import synth
 from oracle import ls as ols
 from oracle import metrics, moments, scheme, smoothing
-from tests.gpu_common import A_DEFAULT, B, oracle_table, plan_kwargs
+from tests.gpu_common import A_DEFAULT, B, oracle_kernel, oracle_table, plan_kwargs
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,71 @@ def test_real_apply_n512_log(api, n):
     g = oracle_table("log", n)
     for i in range(2):
         assert metrics.rel_linf(got[i], np.real(scheme.apply(us[i], g, B))) <= FP64_TOL
+
+
+@pytest.fixture(scope="module")
+def full_size_case():
+    """Three seeded smooth densities at the largest grid (2048^2, a 4096^2 FFT) and their oracle applies."""
+    n = 2048
+    us = np.stack([synth.smooth_density(n, synth.SEED_PRECISION + i) for i in range(3)])
+    g = oracle_table("log", n)
+    refs = [np.real(scheme.apply(us[i], g, B)) for i in range(3)]
+    oracle_table.cache_clear()
+    return n, us, refs
+
+
+@pytest.mark.slow
+def test_full_size_fp64_apply(api, full_size_case):
+    # batch 3 runs as two chunks at this size (the tail chunk holds one density)
+    n, us, refs = full_size_case
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    assert plan.chunk < 3
+    got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    for i in range(3):
+        assert metrics.rel_linf(got[i], refs[i]) <= FP64_TOL, i
+
+
+@pytest.mark.slow
+def test_full_size_fp32_apply(api, full_size_case):
+    n, us, refs = full_size_case
+    plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("log"))
+    got = plan.apply(_gpu(us, torch.float32)).cpu().numpy().astype(np.float64)
+    for i in range(3):
+        assert metrics.rel_linf(got[i], refs[i]) <= 2e-6, i
+        assert metrics.rel_l2(got[i], refs[i]) <= 5e-7, i
+
+
+@pytest.mark.parametrize("kname", ["pow-1/2", "pow-1/3"])
+def test_full_size_moments_sampled(api, kname):
+    # the apply machinery is shared by every real kernel; what differs per
+    # kernel is the moment table, checked here at the full size
+    n = 2048
+    plan = api.ConvPlan(n=n, **plan_kwargs(kname))
+    rng = np.random.default_rng(11)
+    k1 = np.concatenate([[0, 1, -n, -n, n - 1, 1447, 2047], rng.integers(-n, n, 60)])
+    k2 = np.concatenate([[0, 0, 0, -n, n - 1, 1448, -2048], rng.integers(-n, n, 60)])
+    got = plan.moments(k1, k2)
+    kabs = np.sqrt((k1.astype(np.int64) ** 2 + k2.astype(np.int64) ** 2).astype(np.float64))
+    ref = moments.ghat(oracle_kernel(kname), kabs, A_DEFAULT, B)
+    scale = abs(moments.ghat(oracle_kernel(kname), np.zeros(1), A_DEFAULT, B)[0])
+    assert np.max(np.abs(got - ref)) <= 1e-14 * scale
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_complex_apply_n1024(api, precision):
+    n = 1024
+    rng = np.random.default_rng(n)
+    v = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * synth.cutoff(n)
+    plan = api.ConvPlan(n=n, precision=precision, **plan_kwargs("helm40"))
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    got = plan.apply(_gpu(v, dt)).cpu().numpy().astype(np.complex128)
+    ref = scheme.apply(v, oracle_table("helm40", n), B)
+    if precision == "fp64":
+        assert metrics.rel_linf(got, ref) <= FP64_TOL
+    else:
+        assert metrics.rel_linf(got, ref) <= 2e-6
+        assert metrics.rel_l2(got, ref) <= 5e-7
 
 
 @pytest.mark.parametrize("kname", ["helm20", "helm40"])
