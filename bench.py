@@ -180,6 +180,208 @@ def run_ls_bench(api, torch, ns, kappas, repeats):
     return out
 
 
+# Serving trace: grid sides, apply kernels and LS wavenumbers of the request stream.
+SERVE_NS = [64, 128, 256, 512, 1024]
+SERVE_APPLY_KERNELS = [("log|x|", dict(family="log")), ("|x|^-1/2", dict(family="power", gamma=-0.5)),
+                       ("helm20", dict(family="helmholtz", kappa=20.0)),
+                       ("helm40", dict(family="helmholtz", kappa=40.0))]
+SERVE_LS_KAPPAS = [20.0, 40.0]
+SERVE_POOL = 4          # distinct inputs per (kind, n[, kappa]); request i uses entry pool[i]
+SERVE_WINDOW = 64       # requests outstanding in the saturated (closed-loop) run
+
+
+def make_trace(nreq: int):
+    """Seeded request stream: unit-rate exponential gaps (scaled by 1/lambda at replay), 70% applies,
+    n uniform over SERVE_NS, apply kernel uniform over SERVE_APPLY_KERNELS, LS kappa over SERVE_LS_KAPPAS."""
+    import synth
+    rng = np.random.default_rng(synth.SEED_TRACE)
+    gaps = rng.exponential(1.0, nreq)
+    is_apply = rng.random(nreq) < 0.7
+    ns = rng.choice(SERVE_NS, nreq)
+    kern = rng.integers(0, len(SERVE_APPLY_KERNELS), nreq)
+    kap = rng.integers(0, len(SERVE_LS_KAPPAS), nreq)
+    pool = rng.integers(0, SERVE_POOL, nreq)
+    return [dict(gap=float(gaps[i]), kind="apply" if is_apply[i] else "ls", n=int(ns[i]), kernel=int(kern[i]),
+                 kappa=SERVE_LS_KAPPAS[kap[i]], pool=int(pool[i])) for i in range(nreq)]
+
+
+class ServeInputs:
+    """Page-locked input pools (seeds SEED_TRACE + 1 + j) and recycled page-locked output buffers."""
+
+    def __init__(self, torch):
+        import threading
+
+        import synth
+        self.torch = torch
+        self.real, self.cplx, self.contrast, self.uinc = {}, {}, {}, {}
+        for n in SERVE_NS:
+            self.real[n] = [self._pin(synth.smooth_density(n, synth.SEED_TRACE + 1 + j), torch.float64)
+                            for j in range(SERVE_POOL)]
+            self.cplx[n] = [self._pin(r.numpy().astype(np.complex128), torch.complex128) for r in self.real[n]]
+            self.contrast[n] = self._pin(synth.contrast(n), torch.float64)
+            for kappa in SERVE_LS_KAPPAS:
+                self.uinc[n, kappa] = [self._pin(synth.plane_wave(n, kappa, synth.plane_wave_angle(
+                    synth.SEED_TRACE + 1 + j)), torch.complex128) for j in range(SERVE_POOL)]
+        # output buffers, allocated up front: page-locked allocation can stall the device
+        self.free = {(n, dt): [torch.empty((n, n), dtype=dt, pin_memory=True) for _ in range(SERVE_WINDOW)]
+                     for n in SERVE_NS for dt in (torch.float64, torch.complex128)}
+        self.grown = 0
+        self.lock = threading.Lock()
+
+    def _pin(self, a, dtype):
+        t = self.torch.empty(a.shape, dtype=dtype, pin_memory=True)
+        t.copy_(self.torch.as_tensor(np.ascontiguousarray(a)))
+        return t
+
+    def out(self, n, dtype):
+        with self.lock:
+            lst = self.free.setdefault((n, dtype), [])
+            if lst:
+                return lst.pop()
+            self.grown += 1
+        return self.torch.empty((n, n), dtype=dtype, pin_memory=True)
+
+    def give_back(self, t):
+        with self.lock:
+            self.free.setdefault((t.shape[-1], t.dtype), []).append(t)
+
+    def submit(self, eng, r):
+        n = r["n"]
+        if r["kind"] == "apply":
+            name, spec = SERVE_APPLY_KERNELS[r["kernel"]]
+            cplx = spec["family"] == "helmholtz"
+            src = (self.cplx if cplx else self.real)[n][r["pool"]]
+            return eng.submit_apply(spec, src, out=self.out(n, src.dtype))
+        return eng.submit_ls(r["kappa"], self.contrast[n], self.uinc[n, r["kappa"]][r["pool"]], tol=1e-8,
+                             restart=50, max_matvecs=4000, out=self.out(n, self.torch.complex128))
+
+
+def replay(eng, inputs, trace, lam, keep=None):
+    """Submit the trace at its arrival times on the engine clock (lam = arrival rate), or, with lam None,
+    closed-loop with SERVE_WINDOW requests outstanding; a second thread collects every result.
+    Returns per-request infos (latency from the scheduled arrival, or from submission when saturated),
+    the outputs of the request indices in `keep`, and the span from the first arrival to the last result."""
+    import queue
+    import threading
+    nreq = len(trace)
+    q = queue.Queue()
+    infos = [None] * nreq
+    kept = {}
+    slots = threading.Semaphore(SERVE_WINDOW)
+    t0 = eng.now() + 0.05
+    arrivals = t0 + np.cumsum([r["gap"] for r in trace]) / lam if lam else None
+
+    def collect():
+        for i in range(nreq):
+            tk = q.get()
+            out, info = eng.wait(tk)
+            info["latency"] = info["t_done"] - (arrivals[i] if lam else info["t_submit"])
+            infos[i] = info
+            if keep is not None and i in keep:
+                kept[i] = out.numpy().copy()
+            inputs.give_back(out)
+            if not lam:
+                slots.release()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    for i, r in enumerate(trace):
+        if lam:
+            delay = arrivals[i] - eng.now()
+            if delay > 0:
+                time.sleep(delay)
+        else:
+            slots.acquire()
+        q.put(inputs.submit(eng, r))
+    th.join()
+    first = arrivals[0] if lam else min(x["t_submit"] for x in infos)
+    span = max(x["t_done"] for x in infos) - first
+    return infos, kept, span
+
+
+def serve_summary(trace, infos, span, st0, st1):
+    lat = np.array([x["latency"] for x in infos]) * 1e3
+    kinds = np.array([r["kind"] for r in trace])
+    pts = sum(r["n"] ** 2 for r in trace)
+    launches = st1["launches"] - st0["launches"]
+    out = dict(requests=len(trace), requests_per_s=len(trace) / span, grid_points_per_s=pts / span,
+               p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+               launches=launches, mean_batch=len(trace) / max(1, launches),
+               max_batch=max(x["batch"] for x in infos),
+               plan_builds=st1["plan_builds"] - st0["plan_builds"],
+               plan_evictions=st1["plan_evictions"] - st0["plan_evictions"],
+               arena_peak_gb=st1["arena_peak_bytes"] / 1e9)
+    for k in ("apply", "ls"):
+        v = lat[kinds == k]
+        out[k] = dict(count=int(v.size), p50_ms=float(np.percentile(v, 50)), p99_ms=float(np.percentile(v, 99)))
+    ls_res = [x["rel_residual"] for x, r in zip(infos, trace) if r["kind"] == "ls"]
+    out["ls_max_rel_residual"] = float(max(ls_res)) if ls_res else None
+    out["ls_unconverged"] = int(sum(1 for x, r in zip(infos, trace) if r["kind"] == "ls" and x["status"] != 0))
+    return out
+
+
+def run_serve_bench(torch, nreq, arena_gb):
+    """Serving: one seeded Poisson trace replayed on the plain FP64 one-at-a-time engine and on the
+    batched FP32 + refinement engine (4 streams, batches of up to 16 applies)."""
+    from paper_2107_03958_amd import serve
+    trace = make_trace(nreq)
+    log(f"serve: building input pools for {nreq} requests ...")
+    inputs = ServeInputs(torch)
+    arena = int(arena_gb * (1 << 30))
+
+    def warm(eng):
+        # build every plan of the trace before timing (cold plan builds are reported by plan_build_s)
+        seen, tks = set(), []
+        for r in trace:
+            key = (r["kind"], r["n"], r["kernel"] if r["kind"] == "apply" else r["kappa"])
+            if key not in seen:
+                seen.add(key)
+                tks.append(inputs.submit(eng, r))
+        for tk in tks:
+            inputs.give_back(eng.wait(tk)[0])
+
+    # Calibrate the rate: mean service time of the FP64 one-at-a-time engine, back to back.
+    cal = serve.Engine("fp64", streams=1, max_batch=1, arena_bytes=arena)
+    warm(cal)
+    ncal = min(300, nreq)
+    t0 = time.perf_counter()
+    for r in trace[:ncal]:
+        inputs.give_back(cal.wait(inputs.submit(cal, r))[0])
+    svc = (time.perf_counter() - t0) / ncal
+    cal.close()
+    lam = 0.9 / svc
+    log(f"serve: FP64 one-at-a-time service {svc * 1e3:.2f} ms -> lambda {lam:.1f} req/s (90% load)")
+    keep = {i for i, r in enumerate(trace) if r["kind"] == "apply"}
+    keep = set(sorted(keep)[:64])
+    res = dict(trace=dict(requests=nreq, seed="SEED_TRACE", apply_fraction=0.7, ns=SERVE_NS,
+                          apply_kernels=[k for k, _ in SERVE_APPLY_KERNELS], ls_kappas=SERVE_LS_KAPPAS,
+                          ls_tol=1e-8, ls_restart=50, input_pool=SERVE_POOL),
+               calibration_service_ms=svc * 1e3, lambda_per_s=lam)
+    outs = {}
+    for name, prec, streams, mb in (("fp64_one_at_a_time", "fp64", 1, 1), ("fp32_batched", "fp32", 4, 16)):
+        eng = serve.Engine(prec, streams=streams, max_batch=mb, arena_bytes=arena)
+        warm(eng)
+        res[name] = dict(config=dict(precision=prec, streams=streams, max_batch=mb))
+        for mode, rate in (("poisson", lam), ("saturated", None)):
+            st0 = eng.stats()
+            infos, kept, span = replay(eng, inputs, trace, rate, keep if mode == "poisson" else None)
+            res[name][mode] = serve_summary(trace, infos, span, st0, eng.stats())
+            if mode == "poisson":
+                outs[name] = kept
+            r = res[name][mode]
+            log(f"serve {name} {mode}: {r['requests_per_s']:.1f} req/s, p50 {r['p50_ms']:.2f} ms, "
+                f"p99 {r['p99_ms']:.2f} ms, mean batch {r['mean_batch']:.2f}")
+        eng.close()
+    res["saturated_window"] = SERVE_WINDOW
+    res["output_buffers_allocated_during_runs"] = inputs.grown
+    errs = []
+    for i in keep:
+        a, b = outs["fp32_batched"][i], outs["fp64_one_at_a_time"][i]
+        errs.append(float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+    res["fp32_apply_rel_linf_vs_fp64"] = dict(max=max(errs), median=float(np.median(errs)), sampled=len(errs))
+    return res
+
+
 def cpu_baseline(n, u0):
     """The oracle (plain FP64 CPU) on one density of the workload: moments + apply, one thread."""
     from threadpoolctl import threadpool_limits
@@ -213,6 +415,9 @@ def main(argv=None):
     ap.add_argument("--ls-n", type=int, nargs="*", default=[256, 512])
     ap.add_argument("--ls-kappa", type=float, nargs="*", default=[20.0, 40.0, 80.0])
     ap.add_argument("--ls-repeats", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-arena-gb", type=float, default=8.0)
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -252,6 +457,10 @@ def main(argv=None):
     if not args.no_ls:
         log("LS latency bench ...")
         ls = run_ls_bench(api, torch, args.ls_n, args.ls_kappa, args.ls_repeats)
+    srv = None
+    if not args.no_serve:
+        log("serving bench ...")
+        srv = run_serve_bench(torch, args.serve_requests, args.serve_arena_gb)
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (bounded sample) ...")
@@ -292,6 +501,8 @@ def main(argv=None):
                                             "roofline")}
     if ls is not None:
         line["ls_latency"] = ls
+    if srv is not None:
+        line["serving"] = srv
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -41,6 +41,32 @@ class WsLsInfo(ctypes.Structure):
                 ("refinements", c_int), ("rel_residual", c_double)]
 
 
+WS_REQ_APPLY, WS_REQ_LS = 0, 1
+
+
+class WsServeConfig(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("streams", c_int), ("max_batch", c_int), ("max_plans", c_int),
+                ("max_skips", c_int)]
+
+
+class WsRequest(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("kernel", WsKernel), ("n", c_int), ("input", c_void_p),
+                ("contrast", c_void_p), ("output", c_void_p), ("tol", c_double), ("restart", c_int),
+                ("max_matvecs", c_int)]
+
+
+class WsResult(ctypes.Structure):
+    _fields_ = [("status", c_int), ("batch", c_int), ("t_submit", c_double), ("t_start", c_double),
+                ("t_done", c_double), ("ls", WsLsInfo)]
+
+
+class WsServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_ulonglong), ("completed", ctypes.c_ulonglong),
+                ("launches", ctypes.c_ulonglong), ("plan_builds", ctypes.c_ulonglong),
+                ("plan_evictions", ctypes.c_ulonglong), ("arena_bytes", c_size_t),
+                ("arena_peak_bytes", c_size_t), ("cached_plans", c_int), ("pending", c_int)]
+
+
 EXPORTS = {
     "conv_plan_query": (c_int, [POINTER(WsKernel), POINTER(WsGrid), c_int, POINTER(c_size_t), POINTER(c_size_t)]),
     "conv_plan": (c_int, [POINTER(WsKernel), POINTER(WsGrid), c_int, c_void_p, c_void_p, POINTER(c_void_p)]),
@@ -53,6 +79,13 @@ EXPORTS = {
                          POINTER(WsLsInfo), c_void_p]),
     "conv_plan_moments": (c_int, [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_double), c_void_p]),
     "conv_destroy": (None, [c_void_p]),
+    "serve_footprint": (c_int, [POINTER(WsServeConfig), POINTER(WsRequest), POINTER(c_size_t)]),
+    "serve_create": (c_int, [POINTER(WsServeConfig), c_void_p, c_size_t, POINTER(c_void_p)]),
+    "serve_submit": (c_int, [c_void_p, POINTER(WsRequest), POINTER(ctypes.c_ulonglong)]),
+    "serve_wait": (c_int, [c_void_p, ctypes.c_ulonglong, c_double, POINTER(WsResult)]),
+    "serve_now": (c_double, [c_void_p]),
+    "serve_stats": (c_int, [c_void_p, POINTER(WsServeStats)]),
+    "serve_destroy": (None, [c_void_p]),
     "conv_last_error": (ctypes.c_char_p, []),
 }
 

@@ -91,6 +91,13 @@ int check_fs(const ws_fs_desc& d, int n) {
 
 }  // namespace
 
+namespace ws {
+int set_last_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace ws
+
 extern "C" {
 
 const char* conv_last_error(void) { return g_err.c_str(); }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <string>
+
 #include "../../include/wsconv.h"
 #include "fft_core.hpp"
 
@@ -82,6 +84,9 @@ struct Plan {
 };
 
 // Densities run through all three passes at a time (intermediate <= WS_CHUNK_BYTES).
+// Record `msg` as this host thread's conv_last_error() message; returns `code`.
+int set_last_error(int code, const std::string& msg);
+
 inline int apply_chunk(const Plan& p) {
   const size_t per = (size_t)p.n * (p.cplx ? 2 * p.n : p.n) * (p.precision == WS_FP64 ? 16 : 8);
   const size_t c = (size_t)WS_CHUNK_BYTES / per;
