@@ -147,6 +147,19 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
 int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
                     void* stream);
 
+/* Apply several plans' operators at once: item i applies plans[i] to batch[i]
+ * densities at density[i] (layout and element type as conv_apply) into out[i]
+ * (may equal density[i]), with work[i] holding
+ * min(batch[i], conv_apply_chunk(plans[i])) * work_bytes_per_density of plan i.
+ * Every pass of the apply is one launch shared by all items (up to 8 items per
+ * launch), so densities of different grid sizes and kernels run together;
+ * each result equals what conv_apply gives for that item alone.  All plans
+ * must have the same precision and be all real-kernel (WS_LOG / WS_POWER) or
+ * all WS_HELMHOLTZ (else WS_EUNSUPPORTED); no Fourier smoothing.  Items must
+ * not share work buffers.  count = 0 is a no-op. */
+int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const void* const* density,
+                     void* const* out, void* const* work, void* stream);
+
 /* Number of densities conv_apply takes through all three passes at a time:
  * a chunk's intermediate is sized to stay in the GPU's last-level cache
  * between passes.  Callers driving conv_apply_pass over a large batch should

@@ -176,3 +176,33 @@ class ConvPlan:
         if h is not None and h.value:
             self.lib.conv_destroy(h)
             self.handle = None
+
+
+def apply_multi(plans, densities, outs=None, stream=None):
+    """conv_apply_multi: item i applies plans[i] to densities[i] ([batch_i, n_i, n_i] on the device).
+
+    Densities of different sizes and kernels share each pass's launch.  Returns the outputs
+    (allocated here unless given)."""
+    if len(plans) != len(densities):
+        raise ValueError("one density tensor per plan")
+    count = len(plans)
+    if count == 0:
+        return []
+    lib = plans[0].lib
+    dev = plans[0].device
+    us, os_, ws = [], [], []
+    for i, (p, d) in enumerate(zip(plans, densities)):
+        u = d.unsqueeze(0) if d.dim() == 2 else d
+        if u.dtype != p.dtype or u.device != p.device or not u.is_contiguous() or u.shape[-2:] != (p.n, p.n):
+            raise ValueError(f"density {i} must be a contiguous {p.dtype} [batch, {p.n}, {p.n}] tensor on {p.device}")
+        o = torch.empty_like(u) if outs is None else (outs[i].unsqueeze(0) if outs[i].dim() == 2 else outs[i])
+        us.append(u)
+        os_.append(o)
+        # one work buffer per item (items must not share scratch)
+        ws.append(torch.empty(max(1, min(u.shape[0], p.chunk)) * p.work_bytes, dtype=torch.uint8, device=dev))
+    arr = lambda xs: (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    handles = (ctypes.c_void_p * count)(*[p.handle.value for p in plans])
+    batches = (ctypes.c_int * count)(*[u.shape[0] for u in us])
+    with torch.cuda.device(dev):
+        L.check(lib.conv_apply_multi(count, handles, batches, arr(us), arr(os_), arr(ws), _stream_ptr(stream)))
+    return [o[0] if d.dim() == 2 else o for o, d in zip(os_, densities)]

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ls.hpp"
 #include "plan.hpp"
@@ -280,6 +281,41 @@ int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, vo
                                       (ws::cx<float>*)work, s);
   }
   if (e != hipSuccess) return hip_fail(e, "conv_apply_pass");
+  return WS_OK;
+}
+
+int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const void* const* density,
+                     void* const* out, void* const* work, void* stream) {
+  g_err.clear();
+  if (count < 0) return fail(WS_EINVAL, "count must be >= 0");
+  if (count == 0) return WS_OK;
+  if (!plans || !batch || !density || !out || !work) return fail(WS_EINVAL, "NULL argument array");
+  std::vector<ws::ApplyItem> items;
+  int precision = -1;
+  int cplx = -1;
+  for (int i = 0; i < count; ++i) {
+    const ws_plan_t p = plans[i];
+    if (!p) return fail(WS_EINVAL, "plan " + std::to_string(i) + " is NULL");
+    if (batch[i] < 0) return fail(WS_EINVAL, "batch must be >= 0");
+    if (batch[i] == 0) continue;
+    if (batch[i] > 65535) return fail(WS_EUNSUPPORTED, "batch must be at most 65535 per item");
+    if (!density[i] || !out[i] || !work[i]) return fail(WS_EINVAL, "density, out and work must be non-NULL");
+    if ((reinterpret_cast<uintptr_t>(density[i]) | reinterpret_cast<uintptr_t>(out[i]) |
+         reinterpret_cast<uintptr_t>(work[i])) % 16)
+      return fail(WS_EINVAL, "device buffers must be 16-byte aligned");
+    if (precision < 0) precision = p->precision;
+    if (cplx < 0) cplx = p->cplx ? 1 : 0;
+    if (p->precision != precision) return fail(WS_EUNSUPPORTED, "all plans must have the same precision");
+    if ((p->cplx ? 1 : 0) != cplx)
+      return fail(WS_EUNSUPPORTED, "real-kernel and Helmholtz plans cannot share one call");
+    items.push_back(ws::ApplyItem{p, batch[i], density[i], out[i], work[i]});
+  }
+  if (items.empty()) return WS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = precision == WS_FP64
+                           ? ws::launch_apply_multi<double>(items.data(), (int)items.size(), cplx == 1, s)
+                           : ws::launch_apply_multi<float>(items.data(), (int)items.size(), cplx == 1, s);
+  if (e != hipSuccess) return hip_fail(e, "conv_apply_multi");
   return WS_OK;
 }
 

@@ -17,118 +17,25 @@
 // The intermediate lives in a column-blocked layout T[cb][row][c] (CB columns
 // per block): column passes read and write one contiguous block, row passes
 // write RPB x CB contiguous elements per block.
+//
+// Launches.  A tile is the unit of work of one pass (RPB rows, or CPB
+// columns, of one density) and is handled by NT(n) threads.  Every launch uses
+// one block size per kind of pass (the largest NT over all n), and a block
+// runs block-size / NT(n) tiles of one size side by side, each in its own LDS
+// slice, so small grids fill whole wavefronts.  A launch covers up to
+// kMaxSegs segments (a plan with a batch of densities each); a block finds its
+// segment in the launch's table and dispatches on that segment's n, so
+// densities of different sizes run in one launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+#include "apply_cfg.hpp"
 #include "plan.hpp"
 
 namespace ws {
-
-template <typename T, int LOGN>
-struct Cfg {
-  static constexpr int n = 1 << LOGN;
-  static constexpr int CB = Layout<T>::CB;
-  static constexpr int RPB = Layout<T>::RPB;
-  static constexpr int cap(int e, int lines, int L) {         // keep lines * L / e <= 1024 threads
-    while (lines * (L / e) > 1024) e *= 2;
-    return e < L ? e : L;
-  }
-  // Real row passes: two half-length lines (even/odd spectrum) per row, one line per thread group.
-  static constexpr int LH = n / 2;
-  static constexpr int EH = cap(Layout<T>::ER, 2 * RPB, LH);
-  static constexpr int PH = LH / EH;
-  static constexpr int NT_RH = 2 * RPB * PH;
-  static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
-  // Column passes: two full-length lines (even/odd frequencies) per column,
-  // CPB columns per block (CPB = CB, or 1 with XCD-paired blocks).
-  static constexpr int CPB = Layout<T>::CPB1 ? 1 : CB;
-  static constexpr int LF = n;
-  static constexpr int EF = cap(Layout<T>::EC, 2 * CPB, LF);
-  static constexpr int PF = LF / EF;
-  static constexpr int NT_C = 2 * CPB * PF;
-  static constexpr int SF = LineLayout<LF, EF>::STRIDE;
-  // Waves per SIMD the launch bounds reserve registers for: as many blocks
-  // per CU (up to two) as the block's LDS allows.
-  static constexpr int waves(int threads, int lds_bytes) {
-    const int blocks = lds_bytes * 2 <= 163840 ? 2 : 1;
-    const int w = (blocks * threads + 255) / 256;
-    return w < 1 ? 1 : w;
-  }
-  static constexpr int WAVES_C = waves(NT_C, 2 * CPB * SF * (int)sizeof(cx<T>));
-  static constexpr int WAVES_RH = waves(NT_RH, 2 * RPB * SH_ * (int)sizeof(cx<T>));
-  // Complex row passes: two full-length lines per row, rows per block limited by LDS.
-  template <int ROWS>
-  static constexpr bool fits() {
-    constexpr int e = cap(Layout<T>::ER, 2 * ROWS, LF);
-    return ROWS * 2 * LineLayout<LF, e>::STRIDE * (int)sizeof(cx<T>) <= 163840;
-  }
-  static constexpr int R2_ = RPB / 2 > 1 ? RPB / 2 : 1, R4_ = RPB / 4 > 1 ? RPB / 4 : 1;
-  static constexpr int RPBC = fits<RPB>() ? RPB : fits<R2_>() ? R2_ : fits<R4_>() ? R4_ : 1;
-  static constexpr int EFR = cap(Layout<T>::ER, 2 * RPBC, LF);
-  static constexpr int PFR = LF / EFR;
-  static constexpr int NT_RC = 2 * RPBC * PFR;
-  static constexpr int SFR = LineLayout<LF, EFR>::STRIDE;
-  static constexpr int WAVES_RC = waves(NT_RC, 2 * RPBC * SFR * (int)sizeof(cx<T>));
-  // Row tiles sharing 128-byte lines of the intermediate (real and complex row passes).
-  static constexpr int RG = 128 / (RPB * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPB * CB * (int)sizeof(cx<T>)) : 1;
-  static constexpr int RGC = 128 / (RPBC * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPBC * CB * (int)sizeof(cx<T>)) : 1;
-};
-
-// Thread -> (column c, line l, p) of a column pass.  When a wave can hold
-// 64/CB consecutive p of every column, the wave's lanes split into CB groups
-// of consecutive p: its global accesses cover one contiguous span and every
-// 8-lane LDS phase stays on one line.
-template <int CPB, int P>
-__device__ __forceinline__ void col_thread(int tid, int& c, int& p, int& l) {
-  constexpr int LPC = 64 / CPB;
-  if constexpr (CPB <= 64 && 64 % CPB == 0 && P % LPC == 0 && P >= LPC) {
-    constexpr int WPL = P / LPC;
-    const int w = tid / 64, lane = tid % 64;
-    c = lane / LPC;
-    l = w / WPL;
-    p = (w % WPL) * LPC + lane % LPC;
-  } else {
-    c = tid % CPB;
-    p = (tid / CPB) % P;
-    l = tid / (CPB * P);
-  }
-}
-
-// Block -> tile maps.  Blocks are dealt round-robin to the 8 XCDs (each with
-// its own L2).  Tiles that share 128-byte lines of the blocked intermediate
-// are given to blocks 8 apart, which land on the same XCD at about the same
-// time, so the second reader finds the lines in that XCD's L2.
-constexpr int kXcds = 8;
-// Column tiles: `pairs` tiles (cb, c) with c in [0, G) share a block-column cb.
-template <int G>
-__device__ __forceinline__ void xcd_group(int b, int& major, int& minor) {
-  if constexpr (G == 1) {
-    major = b;
-    minor = 0;
-  } else {
-    minor = (b / kXcds) % G;
-    major = (b / (kXcds * G)) * kXcds + b % kXcds;
-  }
-}
-
-// Row tiles: G consecutive tiles (RPB rows each) share the 128-byte lines of
-// the blocked intermediate when RPB x CB elements are narrower than a line;
-// the tiles of such a group go to blocks 8 apart.  Blocks past the last whole
-// group of 8 G keep the identity map.
-template <int G>
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  if constexpr (G <= 1) {
-    return b;
-  } else {
-    const int full = ntiles - ntiles % (kXcds * G);
-    if (b >= full) return b;
-    int major, minor;
-    xcd_group<G>(b, major, minor);
-    return major * G + minor;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ cx<T> ldg(const cx<T>* p) { return *p; }
 
 template <typename T>
 __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.y, a.x}; }
@@ -174,8 +81,39 @@ __device__ inline double fs_window(double x1, double x2, const FsArgs& f) {
   return fs_step((r - f.r1) / (f.r2 - f.r1));
 }
 
-// Row passes launch one block per tile (RPB rows of one density), the tile
-// index taken through xcd_tile so tiles that share lines meet in one L2.
+// ----------------------------------------------------------------------------
+// One segment of a launch: a plan's tables and a batch of densities.
+template <typename T>
+struct Seg {
+  int logn;                          // log2 n of the plan
+  int block0, nblocks, ntiles;       // this segment's blocks [block0, block0 + nblocks) and tiles
+  typename TwOf<T>::type tw;         // the plan's twiddles (nb entries)
+  const void* src;                   // pass 0: densities; real pass 2 with FS: u_tilde; complex pass 2: v
+  void* dst;                         // pass 2: results
+  cx<T>* work;                       // intermediate, n x NCOLS per density
+  const void* gtab;                  // pass 1: moments in the blocked layout
+  const T* gnyq;                     // pass 1, real path: moments of the Nyquist column
+  const T* mcon;                     // complex pass 0: contrast m (or null)
+  T alpha;                           // complex pass 2: out = [v] + alpha * result
+  int add;
+  FsArgs fs;
+};
+
+template <typename T>
+struct Segs {
+  Seg<T> s[kMaxSegs];
+  int count;
+  const int* skip;                   // optional device flag: nonzero -> every block returns at entry
+};
+
+template <typename T>
+__device__ __forceinline__ int find_seg(const Segs<T>& tab, int b) {
+  int i = 0;
+  while (i + 1 < tab.count && b >= tab.s[i + 1].block0) ++i;
+  return i;
+}
+
+#define WS_FOR_EACH_LOGN(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
 
 // ----------------------------------------------------------------------------
 // Real path, forward row pass: rows j1 < n of a real density -> half spectrum
@@ -186,58 +124,54 @@ __device__ inline double fs_window(double x1, double x2, const FsArgs& f) {
 // X_k = (Z_k + conj Z_{n-k})/2 - i w_{2n}^k (Z_k - conj Z_{n-k})/2.
 // Threads: (row r, line l, p); line 0 carries the even, line 1 the odd half.
 // LDS line (r, l) holds Z_{2q+l} at q.  Tile = RPB rows of one density.
-template <typename T, int LOGN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_fwd_real(
-    const T* __restrict__ u, cx<T>* __restrict__ work, typename TwOf<T>::type tw, int ntiles) {
+template <typename T, int LOGN, bool GUARD>
+__device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LH, C::EH>;
   constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  __shared__ cx<T> lds[2 * RPB * S];
-  const int tid = threadIdx.x, p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const auto tw = sg.tw;
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
-  cx<T> x[E];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int t = xcd_tile<C::RG>(blockIdx.x, ntiles);
+  const size_t batch = t / TPD;
+  const int row0 = (t % TPD) * RPB;
+  cx<T> v[1][E];
   {
-    const size_t batch = t / TPD;
-    const int row = (t % TPD) * RPB + r;
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(u + (batch * n + row) * n);
+    // all loads first (they overlap in flight), then the twiddles of the odd half
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(static_cast<const T*>(sg.src) + (batch * n + row0 + r) * n);
+    cx<T> x[E];
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) x[reg] = src[p + P * slot_elem<E, R0>(reg)];
-  }
-  {
-    cx<T> v[1][E];
+    for (int reg = 0; reg < E; ++reg)
+      x[reg] = (!GUARD || valid) ? src[p + P * slot_elem<E, R0>(reg)] : cx<T>{0, 0};
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int m = p + P * slot_elem<E, R0>(reg);
       v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
     }
-    fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
+  }
+  fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-    __syncthreads();
-    const size_t batch = t / TPD;
-    const int row0 = (t % TPD) * RPB;
-    cx<T>* dst = work + batch * (size_t)n * n;
-    for (int idx = tid; idx < RPB * n; idx += NT) {
-      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-      const int k = cb * CB + c;
-      const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
-      cx<T> val;
-      if (k == 0) {
-        val = {zk.x + zk.y, zk.x - zk.y};
-      } else {
-        const int kk = n - k;
-        const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
-        const cx<T> a = cscale(zk + zm, (T)0.5);
-        const cx<T> d = cscale(zk - zm, (T)0.5);
-        const cx<T> bdiff = {d.y, -d.x};              // -i d
-        val = a + tw.template mul<-1>(bdiff, k);      // + w_{2n}^k (-i d)
-      }
-      dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+  __syncthreads();
+  if (GUARD && !valid) return;
+  cx<T>* dst = sg.work + batch * (size_t)n * n;
+  for (int idx = tid; idx < RPB * n; idx += NT) {
+    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+    const int k = cb * CB + c;
+    const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+    cx<T> val;
+    if (k == 0) {
+      val = {zk.x + zk.y, zk.x - zk.y};
+    } else {
+      const int kk = n - k;
+      const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
+      const cx<T> a = cscale(zk + zm, (T)0.5);
+      const cx<T> d = cscale(zk - zm, (T)0.5);
+      const cx<T> bdiff = {d.y, -d.x};              // -i d
+      val = a + tw.template mul<-1>(bdiff, k);      // + w_{2n}^k (-i d)
     }
+    dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
   }
 }
 
@@ -248,49 +182,56 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_fwd_real(
 // transforms x (even frequencies k1 = 2q), line 1 transforms x w_{2n}^j (odd
 // k1 = 2q + 1); out_i = even_i + w_{2n}^{-i} odd_i is combined through LDS.
 // GEN: synthesise the spectrum chihat instead of loading and transforming
-// (Fourier smoothing pre-pass).  A block handles CPB columns of one density.
-template <typename T, typename G, int LOGN, bool CPLX, bool GEN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void k_cols(
-    cx<T>* __restrict__ work, const G* __restrict__ gtab, const T* __restrict__ gnyq,
-    typename TwOf<T>::type tw, FsArgs fs, const int* skip) {
-  if (skip && *skip) return;
+// (Fourier smoothing pre-pass).  A tile holds CPB columns of one density.
+// dc_block: the block holds the tile of block-column 0 (packed DC/Nyquist
+// column of the real path), whose extra exchange every thread of the block joins.
+template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD>
+__device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
+                                          bool dc_block) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LF, C::EF>;
   constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB, CPB = C::CPB;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
-  constexpr int NCOLS = CPLX ? 2 * n : n;
-  __shared__ cx<T> lds[2 * CPB * S];
+  constexpr int NCOLS = CPLX ? 2 * n : n, NCT = NCOLS / CPB, GC = CB / CPB;
   int cc, p, l;
-  col_thread<CPB, P>(threadIdx.x, cc, p, l);
-  int cb, csub;
-  xcd_group<CB / CPB>(blockIdx.x, cb, csub);
+  col_thread<CPB, P>(tid, cc, p, l);
+  const int ct = t % NCT;
+  const size_t batch = t / NCT;
+  const int cb = ct / GC, csub = ct % GC;
   const int c = csub * CPB + cc;                       // column within the block-column cb
-  const size_t batch = blockIdx.y;
-  cx<T>* col = work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
+  const auto tw = sg.tw;
+  cx<T>* col = sg.work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
   cx<T>* mine = lds + (2 * cc + l) * S;
   cx<T>* line[1] = {mine};
   cx<T> v[1][E];
   const int k2 = cb * CB + c;                          // FFT bin of this column
 
   if constexpr (!GEN) {
+    const G* gtab = static_cast<const G*>(sg.gtab);
+    cx<T> x[E];
+#pragma unroll
+    for (int reg = 0; reg < E; ++reg)
+      x[reg] = (!GUARD || valid) ? col[(size_t)(p + P * slot_elem<E, R0>(reg)) * CB + c] : cx<T>{0, 0};
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
-      const cx<T> x = col[(size_t)j * CB + c];
-      v[0][reg] = l ? tw.template mul<-1>(x, j) : x;   // odd frequencies: x w_{2n}^j
+      v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];   // odd frequencies: x w_{2n}^j
     }
     fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
     // v[0][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {
-      if (cb == 0 && csub == 0) {
+      if (dc_block) {
         // Column 0 packs the real columns k2 = 0 (D) and k2 = n (N):
         // Y = D^ + i N^ with D^, N^ Hermitian.  New value
         // g0 D^ + i gN N^ = (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k); -k stays in the same half.
+        const bool dc = (!GUARD || valid) && cb == 0 && csub == 0;
+        if (dc) {
 #pragma unroll
-        for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+          for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+        }
         __syncthreads();
-        if (c == 0) {
+        if (dc && c == 0) {
 #pragma unroll
           for (int reg = 0; reg < E; ++reg) {
             const int q = p + P * slot_elem<E, RL>(reg);
@@ -299,7 +240,7 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void
             const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
             const cx<T> ym = cconj(mine[LL::pad(partner)]);
             const T g0 = (T)gtab[(size_t)k1f * CB];
-            const T gN = gnyq[k1f];
+            const T gN = sg.gnyq[k1f];
             v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
           }
           done = true;
@@ -307,7 +248,7 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void
         __syncthreads();
       }
     }
-    if (!done) {
+    if (!done && (!GUARD || valid)) {
       const G* gc = gtab + (size_t)cb * (n + 1) * CB + c;
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
@@ -323,9 +264,9 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void
     for (int reg = 0; reg < E; ++reg) {
       const int b1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
       const int k1 = b1 < n ? b1 : b1 - 2 * n;          // F_n representative
-      cx<double> h = chihat(k1, k2, fs);
+      cx<double> h = chihat(k1, k2, sg.fs);
       if (k2 == 0) {
-        const cx<double> hn = chihat(k1, -n, fs);      // column k2 = -nb/2, packed as imaginary part
+        const cx<double> hn = chihat(k1, -n, sg.fs);   // column k2 = -nb/2, packed as imaginary part
         h = {h.x - hn.y, h.y + hn.x};
       }
       v[0][reg] = {(T)h.x, (T)h.y};
@@ -336,11 +277,12 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
+  if (GUARD && !valid) return;
   const cx<T>* l0 = lds + (2 * cc) * S;
   const cx<T>* l1 = l0 + S;
 #pragma unroll
-  for (int t = 0; t < E / 2; ++t) {
-    const int i = p + P * (l * (E / 2) + t);
+  for (int tt = 0; tt < E / 2; ++tt) {
+    const int i = p + P * (l * (E / 2) + tt);
     col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
   }
 }
@@ -352,177 +294,286 @@ __global__ __launch_bounds__((Cfg<T, LOGN>::NT_C), (Cfg<T, LOGN>::WAVES_C)) void
 // IDFT_{n/2}(Z_even)_m + w_n^{-m} IDFT_{n/2}(Z_odd)_m.
 // FS: out = u_tilde * out * psi (the Fourier-smoothed density, Section 2.4).
 // LDS line (r, l) first holds Y_{2q+l} at q, then the inverse transform of line l.
-template <typename T, int LOGN, bool FS>
-__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RH)) void k_rows_inv_real(
-    const cx<T>* __restrict__ work, T* __restrict__ out, typename TwOf<T>::type tw,
-    const T* __restrict__ utilde, FsArgs fs, int ntiles) {
+template <typename T, int LOGN, bool FS, bool GUARD>
+__device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LH, C::EH>;
   constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  __shared__ cx<T> lds[2 * RPB * S];
-  const int tid = threadIdx.x;
   const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const auto tw = sg.tw;
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
   const cx<T>* l0 = lds + (2 * r) * S;
   const cx<T>* l1 = l0 + S;
-  if ((int)blockIdx.x >= ntiles) return;
-  const int t = xcd_tile<C::RG>(blockIdx.x, ntiles);
+  const size_t batch = t / TPD;
+  const int row0 = (t % TPD) * RPB;
   {
-    {
-      const cx<T>* src = work + (size_t)(t / TPD) * n * n;
-      const int row0 = (t % TPD) * RPB;
-      for (int idx = tid; idx < RPB * n; idx += NT) {
-        const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-        const int k = cb * CB + c;
-        lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] = src[((size_t)cb * n + row0 + rr) * CB + c];
-      }
+    const cx<T>* src = sg.work + batch * n * n;
+    for (int idx = tid; idx < RPB * n; idx += NT) {
+      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+      const int k = cb * CB + c;
+      lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] =
+          (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
     }
-    __syncthreads();
-    cx<T> v[1][E];
+  }
+  __syncthreads();
+  cx<T> v[1][E];
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) {
-      const int q = p + P * slot_elem<E, R0>(reg);
-      const int k = 2 * q + l;
-      cx<T> z;
-      if (k == 0) {
-        const cx<T> y0 = mine[0];
-        z = {y0.x + y0.y, y0.x - y0.y};
-      } else {
-        const cx<T> yk = mine[LL::pad(q)];
-        const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
-        const cx<T> d = tw.template mul<+1>(yk - yk2, k);
-        z = (yk + yk2) + times_i(d);
-      }
-      v[0][reg] = z;
+  for (int reg = 0; reg < E; ++reg) {
+    const int q = p + P * slot_elem<E, R0>(reg);
+    const int k = 2 * q + l;
+    cx<T> z;
+    if (k == 0) {
+      const cx<T> y0 = mine[0];
+      z = {y0.x + y0.y, y0.x - y0.y};
+    } else {
+      const cx<T> yk = mine[LL::pad(q)];
+      const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
+      const cx<T> d = tw.template mul<+1>(yk - yk2, k);
+      z = (yk + yk2) + times_i(d);
     }
-    __syncthreads();
-    fft_lines<L, E, 1, +1>(v, line, p, tw, 2 * n / L);
+    v[0][reg] = z;
+  }
+  __syncthreads();
+  fft_lines<L, E, 1, +1>(v, line, p, tw, 2 * n / L);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-    __syncthreads();
-    const size_t batch = t / TPD;
-    const int row = (t % TPD) * RPB + r;
-    cx<T>* dst = reinterpret_cast<cx<T>*>(out + (batch * n + row) * n);
+  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+  __syncthreads();
+  if (GUARD && !valid) return;
+  const int row = row0 + r;
+  cx<T>* dst = reinterpret_cast<cx<T>*>(static_cast<T*>(sg.dst) + (batch * n + row) * n);
 #pragma unroll
-    for (int tt = 0; tt < E / 2; ++tt) {
-      const int m = p + P * (l * (E / 2) + tt);
-      cx<T> zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
-      if constexpr (FS) {
-        const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row) * n)[m];
-        const double x1 = (double)row / n;
-        const double w0 = fs_window(x1, (double)(2 * m) / n, fs);
-        const double w1 = fs_window(x1, (double)(2 * m + 1) / n, fs);
-        zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
-      }
-      dst[m] = zz;
+  for (int tt = 0; tt < E / 2; ++tt) {
+    const int m = p + P * (l * (E / 2) + tt);
+    cx<T> zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
+    if constexpr (FS) {
+      const T* utilde = static_cast<const T*>(sg.src);
+      const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row) * n)[m];
+      const double x1 = (double)row / n;
+      const double w0 = fs_window(x1, (double)(2 * m) / n, sg.fs);
+      const double w1 = fs_window(x1, (double)(2 * m + 1) / n, sg.fs);
+      zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
     }
+    dst[m] = zz;
   }
 }
 
 // ----------------------------------------------------------------------------
 // Complex path, forward row pass: X(j1, k2), k2 in [0, 2n), natural order,
 // from rows of (m .* v); even k2 from DFT_n(x), odd k2 from DFT_n(x w_{2n}^j).
-template <typename T, int LOGN, bool MUL>
-__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_fwd_cplx(
-    const cx<T>* __restrict__ vin, const T* __restrict__ mcon, cx<T>* __restrict__ work,
-    typename TwOf<T>::type tw, int ntiles, const int* skip) {
-  if (skip && *skip) return;
+template <typename T, int LOGN, bool MUL, bool GUARD>
+__device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LF, C::EFR>;
   constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  __shared__ cx<T> lds[2 * RPB * S];
-  const int tid = threadIdx.x, p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const auto tw = sg.tw;
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
-  cx<T> x[E];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int t = xcd_tile<C::RGC>(blockIdx.x, ntiles);
+  const int row0 = (t % TPD) * RPB;
+  cx<T> v[1][E];
   {
-    const int row = (t % TPD) * RPB + r;
+    const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
+    const int row = row0 + r;
     const size_t roff = ((size_t)(t / TPD) * n + row) * n;
+    cx<T> x[E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
-      x[reg] = vin[roff + j];
-      if constexpr (MUL) x[reg] = cscale(x[reg], mcon[(size_t)row * n + j]);
+      x[reg] = (!GUARD || valid) ? vin[roff + j] : cx<T>{0, 0};
+      if constexpr (MUL) {
+        if (!GUARD || valid) x[reg] = cscale(x[reg], sg.mcon[(size_t)row * n + j]);
+      }
     }
-  }
-  {
-    cx<T> v[1][E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
       const int j = p + P * slot_elem<E, R0>(reg);
       v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
     }
-    fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
+  }
+  fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-    __syncthreads();
-    const int row0 = (t % TPD) * RPB;
-    cx<T>* dst = work + (size_t)(t / TPD) * n * 2 * n;
-    for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
-      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-      const int k = cb * CB + c;
-      dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
-    }
+  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+  __syncthreads();
+  if (GUARD && !valid) return;
+  cx<T>* dst = sg.work + (size_t)(t / TPD) * n * 2 * n;
+  for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+    const int k = cb * CB + c;
+    dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
   }
 }
 
 // Complex path, inverse row pass keeping i2 < n, fused out = [v] + alpha * result.
-template <typename T, int LOGN>
-__global__ __launch_bounds__((Cfg<T, LOGN>::NT_RC)) void k_rows_inv_cplx(
-    const cx<T>* __restrict__ work, const cx<T>* vin, cx<T>* out, T alpha, int add_input,
-    typename TwOf<T>::type tw, int ntiles, const int* skip) {
-  if (skip && *skip) return;
+template <typename T, int LOGN, bool GUARD>
+__device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LF, C::EFR>;
   constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  __shared__ cx<T> lds[2 * RPB * S];
-  const int tid = threadIdx.x;
   const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  const auto tw = sg.tw;
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
   const cx<T>* l0 = lds + (2 * r) * S;
   const cx<T>* l1 = l0 + S;
-  if ((int)blockIdx.x >= ntiles) return;
-  const int t = xcd_tile<C::RGC>(blockIdx.x, ntiles);
   {
-    {
-      const cx<T>* src = work + (size_t)(t / TPD) * n * 2 * n;
-      const int row0 = (t % TPD) * RPB;
-      for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
-        const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-        const int k = cb * CB + c;
-        lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] = src[((size_t)cb * n + row0 + rr) * CB + c];
-      }
+    const cx<T>* src = sg.work + (size_t)(t / TPD) * n * 2 * n;
+    const int row0 = (t % TPD) * RPB;
+    for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+      const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
+      const int k = cb * CB + c;
+      lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] =
+          (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
     }
-    __syncthreads();
-    cx<T> v[1][E];
+  }
+  __syncthreads();
+  cx<T> v[1][E];
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
-    __syncthreads();
-    fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
+  for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
+  __syncthreads();
+  fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-    __syncthreads();
-    const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
+  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+  __syncthreads();
+  if (GUARD && !valid) return;
+  const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
+  cx<T>* out = static_cast<cx<T>*>(sg.dst);
+  const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
 #pragma unroll
-    for (int tt = 0; tt < E / 2; ++tt) {
-      const int i = p + P * (l * (E / 2) + tt);
-      cx<T> y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
-      y = cscale(y, alpha);
-      if (add_input) y = y + vin[roff + i];
-      out[roff + i] = y;
-    }
+  for (int tt = 0; tt < E / 2; ++tt) {
+    const int i = p + P * (l * (E / 2) + tt);
+    cx<T> y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
+    y = cscale(y, sg.alpha);
+    if (sg.add) y = y + vin[roff + i];
+    out[roff + i] = y;
   }
 }
 
 // ----------------------------------------------------------------------------
-// Host launchers.
+// Tile groups: a block runs BLK / NT tiles of one segment side by side.
+// Tiles past the segment's end run with valid = false: they read and write
+// nothing outside LDS but join every barrier.
+// Tile groups: a block of BLOCK threads runs BLOCK / NT tiles of one segment
+// side by side.  In a block whose group runs past the segment's end
+// (GUARD), the tiles past it read and write nothing outside LDS but join every
+// barrier.
+template <typename T, int LOGN, int K, int BLOCK, bool GUARD>
+__device__ __forceinline__ void run_tiles(const Seg<T>& sg, int b, cx<T>* lds) {
+  using C = Cfg<T, LOGN>;
+  using KO = KindOf<T, K>;
+  constexpr int NT = KO::template nt<LOGN>();
+  constexpr int TPB = BLOCK / NT;
+  constexpr int LDS = KO::template lds_tile<LOGN>();
+  const int sub = threadIdx.x / NT, tid = threadIdx.x % NT;
+  const int t = b * TPB + sub;
+  const bool valid = !GUARD || t < sg.ntiles;
+  const int tt = valid ? t : 0;
+  cx<T>* mylds = lds + sub * LDS;
+  if constexpr (K == kRowsFwdReal) rows_fwd_real_tile<T, LOGN, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvReal) rows_inv_real_tile<T, LOGN, false, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvFs) rows_inv_real_tile<T, LOGN, true, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsFwdCplx) rows_fwd_cplx_tile<T, LOGN, false, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsFwdCplxMul) rows_fwd_cplx_tile<T, LOGN, true, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvCplx) rows_inv_cplx_tile<T, LOGN, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kColsReal || K == kColsGen || K == kColsCplx) {
+    constexpr bool CPLX = K == kColsCplx;
+    constexpr int NCT = (CPLX ? 2 * C::n : C::n) / C::CPB;
+    // does this block hold a tile of block-column 0 (first column of a density)?
+    const int first = b * TPB;
+    const int last = std::min(first + TPB, sg.ntiles) - 1;
+    const bool dc_block = first % NCT == 0 || first / NCT != last / NCT;
+    if constexpr (K == kColsReal) cols_tile<T, T, LOGN, false, false, GUARD>(sg, tt, valid, tid, mylds, dc_block);
+    if constexpr (K == kColsGen) cols_tile<T, T, LOGN, false, true, GUARD>(sg, tt, valid, tid, mylds, false);
+    if constexpr (K == kColsCplx) cols_tile<T, cx<T>, LOGN, true, false, GUARD>(sg, tt, valid, tid, mylds, false);
+  }
+}
+
+template <typename T, int LOGN, int K, int BLOCK>
+__device__ __forceinline__ void run_group(const Seg<T>& sg, int blk, cx<T>* lds) {
+  using KO = KindOf<T, K>;
+  constexpr int TPB = BLOCK / KO::template nt<LOGN>();
+  constexpr int G = KO::template line_group<LOGN>();
+  constexpr int GB = G / TPB > 1 ? G / TPB : 1;
+  const int b = xcd_tile<GB>(blk, sg.nblocks);
+  if constexpr (TPB == 1) {
+    run_tiles<T, LOGN, K, BLOCK, false>(sg, b, lds);
+  } else {
+    if ((b + 1) * TPB <= sg.ntiles) run_tiles<T, LOGN, K, BLOCK, false>(sg, b, lds);
+    else run_tiles<T, LOGN, K, BLOCK, true>(sg, b, lds);
+  }
+}
+
+// Launches of one segment (one grid size): block and LDS sized for that size.
+// Every pointer comes in as its own argument; all but the density and result
+// of the smoothing pre-pass (which may be the same array) are restrict, which
+// lets the compiler move loads past stores and barriers.
+template <typename T, int K, int LOGN>
+__device__ __forceinline__ void pass1_body(const void* src, void* dst, cx<T>* work, const void* gtab,
+                                           const T* gnyq, const T* mcon, typename TwOf<T>::type tw, int ntiles,
+                                           int nblocks, T alpha, int add, const FsArgs& fs, cx<T>* lds) {
+  Seg<T> sg;
+  sg.logn = LOGN;
+  sg.block0 = 0;
+  sg.nblocks = nblocks;
+  sg.ntiles = ntiles;
+  sg.tw = tw;
+  sg.src = src;
+  sg.dst = dst;
+  sg.work = work;
+  sg.gtab = gtab;
+  sg.gnyq = gnyq;
+  sg.mcon = mcon;
+  sg.alpha = alpha;
+  sg.add = add;
+  sg.fs = fs;
+  run_group<T, LOGN, K, Single<T, K, LOGN>::BLOCK>(sg, blockIdx.x, lds);
+}
+
+template <typename T, int K, int LOGN>
+__global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::WAVES)) void k_pass1(
+    const void* __restrict__ src, void* __restrict__ dst, cx<T>* __restrict__ work, const void* __restrict__ gtab,
+    const T* __restrict__ gnyq, const T* __restrict__ mcon, typename TwOf<T>::type tw, int ntiles, int nblocks,
+    T alpha, int add, FsArgs fs, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ cx<T> lds[Single<T, K, LOGN>::LDS];
+  pass1_body<T, K, LOGN>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+}
+
+template <typename T, int K, int LOGN>
+__global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::WAVES)) void k_pass1_alias(
+    const void* src, void* dst, cx<T>* __restrict__ work, const void* __restrict__ gtab,
+    const T* __restrict__ gnyq, const T* __restrict__ mcon, typename TwOf<T>::type tw, int ntiles, int nblocks,
+    T alpha, int add, FsArgs fs, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ cx<T> lds[Single<T, K, LOGN>::LDS];
+  pass1_body<T, K, LOGN>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+}
+
+// Launches over several segments of any sizes: one block size for all.
+template <typename T, int K>
+__global__ __launch_bounds__((KindOf<T, K>::BLK), (KindOf<T, K>::WAVES)) void k_pass(Segs<T> tab) {
+  if (tab.skip && *tab.skip) return;
+  __shared__ cx<T> lds[KindOf<T, K>::LDS];
+  const int si = find_seg(tab, blockIdx.x);
+  const Seg<T>& sg = tab.s[si];
+  const int blk = blockIdx.x - sg.block0;
+  switch (sg.logn) {
+#define WS_CASE(L)                                         \
+  case L:                                                  \
+    run_group<T, L, K, KindOf<T, K>::BLK>(sg, blk, lds);   \
+    break;
+    WS_FOR_EACH_LOGN(WS_CASE)
+#undef WS_CASE
+    default:
+      break;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Host side.
 template <typename T> typename TwOf<T>::type make_tw(const Plan& p);
 template <> TwD make_tw<double>(const Plan& p) { return TwD{p.tw64}; }
 template <> TwF make_tw<float>(const Plan& p) { return TwF{p.tw32}; }
@@ -534,149 +585,199 @@ template <typename T> const T* gnyq_of(const Plan& p);
 template <> const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
 template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
 
-template <typename T, int LOGN>
-static hipError_t pass_real_n(const Plan& pl, int pass, int batch, const T* u, T* out, cx<T>* work,
-                              hipStream_t s) {
-  using C = Cfg<T, LOGN>;
-  constexpr int n = C::n;
-  auto tw = make_tw<T>(pl);
-  FsArgs none{};
-  if (pass == 0) {
-    auto kf = k_rows_fwd_real<T, LOGN>;
-    const int nt = batch * (n / C::RPB);
-    kf<<<nt, C::NT_RH, 0, s>>>(u, work, tw, nt);
-  } else if (pass == 1) {
-    const T* g = static_cast<const T*>(gtab_of<T>(pl));
-    k_cols<T, T, LOGN, false, false><<<dim3(n / C::CPB, batch), C::NT_C, 0, s>>>(work, g, gnyq_of<T>(pl), tw,
-                                                                                   none, nullptr);
-  } else {
-    auto kf = k_rows_inv_real<T, LOGN, false>;
-    const int nt = batch * (n / C::RPB);
-    kf<<<nt, C::NT_RH, 0, s>>>(work, out, tw, nullptr, none, nt);
+// Tiles per density, threads per tile and the single-size block of a kind of pass at size 2^logn.
+struct Geo {
+  int tiles_per_density, nt, block_single;
+};
+template <typename T, int LOGN, int K>
+Geo geo_of() {
+  using KO = KindOf<T, K>;
+  return Geo{KO::template tiles_per_density<LOGN>(), KO::template nt<LOGN>(), Single<T, K, LOGN>::BLOCK};
+}
+template <typename T, int K>
+Geo geo(int logn) {
+  switch (logn) {
+#define WS_CASE(L) \
+  case L: return geo_of<T, L, K>();
+    WS_FOR_EACH_LOGN(WS_CASE)
+#undef WS_CASE
+    default: return Geo{0, 1, 1};
+  }
+}
+
+// One segment of pass kind K for `batch` densities of plan p, for a launch of
+// the single-size kernel (multi = false) or of the several-size kernel.
+template <typename T, int K>
+Seg<T> make_seg(const Plan& p, int batch, const void* src, void* dst, cx<T>* work, bool multi) {
+  Seg<T> s{};
+  s.logn = p.logn;
+  s.tw = make_tw<T>(p);
+  s.src = src;
+  s.dst = dst;
+  s.work = work;
+  s.gtab = gtab_of<T>(p);
+  s.gnyq = gnyq_of<T>(p);
+  s.alpha = (T)1;
+  const Geo g = geo<T, K>(p.logn);
+  s.ntiles = batch * g.tiles_per_density;
+  const int tpb = (multi ? KindOf<T, K>::BLK : g.block_single) / g.nt;
+  s.nblocks = (s.ntiles + tpb - 1) / tpb;
+  return s;
+}
+
+// Launch pass kind K over tab.count segments (block offsets filled in here).
+template <typename T, int K>
+hipError_t launch_segs(Segs<T>& tab, hipStream_t st) {
+  long total = 0;
+  for (int i = 0; i < tab.count; ++i) {
+    tab.s[i].block0 = (int)total;
+    total += tab.s[i].nblocks;
+  }
+  if (total == 0) return hipSuccess;
+  if (total > 0x7fffffffL) return hipErrorInvalidValue;
+  k_pass<T, K><<<(unsigned)total, KindOf<T, K>::BLK, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t launch_one(const Plan& p, int batch, const void* src, void* dst, cx<T>* work, hipStream_t st,
+                      const int* skip = nullptr, const T* mcon = nullptr, T alpha = (T)1, bool add = false,
+                      const FsArgs* fs = nullptr) {
+  Seg<T> sg = make_seg<T, K>(p, batch, src, dst, work, false);
+  sg.mcon = mcon;
+  sg.alpha = alpha;
+  sg.add = add ? 1 : 0;
+  if (fs) sg.fs = *fs;
+  if (sg.nblocks == 0) return hipSuccess;
+  switch (p.logn) {
+#define WS_CASE(L)                                                                          \
+  case L:                                                                                   \
+    if constexpr (K == kRowsInvFs)                                                          \
+      k_pass1_alias<T, K, L><<<sg.nblocks, Single<T, K, L>::BLOCK, 0, st>>>(                 \
+          sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,  \
+          sg.alpha, sg.add, sg.fs, skip);                                                    \
+    else                                                                                    \
+      k_pass1<T, K, L><<<sg.nblocks, Single<T, K, L>::BLOCK, 0, st>>>(                       \
+          sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,  \
+          sg.alpha, sg.add, sg.fs, skip);                                                    \
+    break;
+    WS_FOR_EACH_LOGN(WS_CASE)
+#undef WS_CASE
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T, int LOGN>
-static hipError_t apply_real_n(const Plan& pl, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
-  const size_t nn = (size_t)pl.n * pl.n;
-  const int chunk = apply_chunk(pl);
-  for (int b0 = 0; b0 < batch; b0 += chunk) {
-    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
-    for (int pass = 0; pass < 3; ++pass) {
-      hipError_t e = pass_real_n<T, LOGN>(pl, pass, nb, u + b0 * nn, out + b0 * nn, work, s);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipSuccess;
+template <typename T>
+hipError_t launch_pass_real(const Plan& p, int pass, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
+  if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+  if (pass == 0) return launch_one<T, kRowsFwdReal>(p, batch, u, nullptr, work, s);
+  if (pass == 1) return launch_one<T, kColsReal>(p, batch, nullptr, nullptr, work, s);
+  return launch_one<T, kRowsInvReal>(p, batch, nullptr, out, work, s);
 }
-
-template <typename T, int LOGN>
-static hipError_t fs_real_n(const Plan& pl, const T* ut, T* out, cx<T>* work, const ws_fs_desc& d,
-                            hipStream_t s) {
-  using C = Cfg<T, LOGN>;
-  constexpr int n = C::n;
-  auto tw = make_tw<T>(pl);
-  FsArgs f{d.shape, d.c1, d.c2, d.size, d.psi_r1, d.psi_r2};
-  k_cols<T, T, LOGN, false, true><<<dim3(n / C::CPB, 1), C::NT_C, 0, s>>>(work, nullptr, nullptr, tw, f, nullptr);
-  auto kr = k_rows_inv_real<T, LOGN, true>;
-  const int ntr = n / C::RPB;
-  kr<<<ntr, C::NT_RH, 0, s>>>(work, out, tw, ut, f, ntr);
-  return hipGetLastError();
-}
-
-template <typename T, int LOGN>
-static hipError_t pass_cplx_n(const Plan& pl, int pass, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                              cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
-  using C = Cfg<T, LOGN>;
-  constexpr int n = C::n;
-  auto tw = make_tw<T>(pl);
-  FsArgs none{};
-  if (pass == 0) {
-    const int nt = batch * (n / C::RPBC);
-    if (m) {
-      auto kf = k_rows_fwd_cplx<T, LOGN, true>;
-      kf<<<nt, C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
-    } else {
-      auto kf = k_rows_fwd_cplx<T, LOGN, false>;
-      kf<<<nt, C::NT_RC, 0, s>>>(v, m, work, tw, nt, skip);
-    }
-  } else if (pass == 1) {
-    const cx<T>* g = static_cast<const cx<T>*>(gtab_of<T>(pl));
-    k_cols<T, cx<T>, LOGN, true, false><<<dim3(2 * n / C::CPB, batch), C::NT_C, 0, s>>>(work, g, nullptr, tw,
-                                                                                       none, skip);
-  } else {
-    auto kf = k_rows_inv_cplx<T, LOGN>;
-    const int nt = batch * (n / C::RPBC);
-    kf<<<nt, C::NT_RC, 0, s>>>(work, v, out, alpha, add ? 1 : 0, tw, nt,
-                                                                      skip);
-  }
-  return hipGetLastError();
-}
-
-template <typename T, int LOGN>
-static hipError_t apply_cplx_n(const Plan& pl, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                               cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
-  const size_t nn = (size_t)pl.n * pl.n;
-  const int chunk = apply_chunk(pl);
-  for (int b0 = 0; b0 < batch; b0 += chunk) {
-    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
-    for (int pass = 0; pass < 3; ++pass) {
-      hipError_t e = pass_cplx_n<T, LOGN>(pl, pass, nb, v + b0 * nn, m, alpha, add, out + b0 * nn, work, s, skip);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipSuccess;
-}
-
-#define WS_DISPATCH_LOGN(LOGN, CALL) \
-  switch (LOGN) {                     \
-    case 4: return CALL(4);           \
-    case 5: return CALL(5);           \
-    case 6: return CALL(6);           \
-    case 7: return CALL(7);           \
-    case 8: return CALL(8);           \
-    case 9: return CALL(9);           \
-    case 10: return CALL(10);         \
-    case 11: return CALL(11);         \
-    default: return hipErrorInvalidValue; \
-  }
 
 template <typename T>
 hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
-#define CALL(L) apply_real_n<T, L>(p, batch, u, out, work, s)
-  WS_DISPATCH_LOGN(p.logn, CALL)
-#undef CALL
+  const size_t nn = (size_t)p.n * p.n;
+  const int chunk = apply_chunk(p);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+    for (int pass = 0; pass < 3; ++pass) {
+      hipError_t e = launch_pass_real<T>(p, pass, nb, u + b0 * nn, out + b0 * nn, work, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 template <typename T>
-hipError_t launch_fs_real(const Plan& p, const T* ut, T* out, cx<T>* work, const ws_fs_desc& fs, hipStream_t s) {
-#define CALL(L) fs_real_n<T, L>(p, ut, out, work, fs, s)
-  WS_DISPATCH_LOGN(p.logn, CALL)
-#undef CALL
+hipError_t launch_fs_real(const Plan& p, const T* ut, T* out, cx<T>* work, const ws_fs_desc& d, hipStream_t s) {
+  if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+  FsArgs f{d.shape, d.c1, d.c2, d.size, d.psi_r1, d.psi_r2};
+  hipError_t e = launch_one<T, kColsGen>(p, 1, nullptr, nullptr, work, s, nullptr, nullptr, (T)1, false, &f);
+  if (e != hipSuccess) return e;
+  return launch_one<T, kRowsInvFs>(p, 1, ut, out, work, s, nullptr, nullptr, (T)1, false, &f);
+}
+
+template <typename T>
+static hipError_t pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, const T* m, T alpha, bool add,
+                            cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
+  if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+  if (pass == 0) {
+    if (m) return launch_one<T, kRowsFwdCplxMul>(p, batch, v, nullptr, work, s, skip, m);
+    return launch_one<T, kRowsFwdCplx>(p, batch, v, nullptr, work, s, skip);
+  }
+  if (pass == 1) return launch_one<T, kColsCplx>(p, batch, nullptr, nullptr, work, s, skip);
+  return launch_one<T, kRowsInvCplx>(p, batch, v, out, work, s, skip, nullptr, alpha, add);
 }
 
 template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add,
                              cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
-#define CALL(L) apply_cplx_n<T, L>(p, batch, v, m, alpha, add, out, work, s, skip)
-  WS_DISPATCH_LOGN(p.logn, CALL)
-#undef CALL
-}
-
-template <typename T>
-hipError_t launch_pass_real(const Plan& p, int pass, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
-#define CALL(L) pass_real_n<T, L>(p, pass, batch, u, out, work, s)
-  WS_DISPATCH_LOGN(p.logn, CALL)
-#undef CALL
+  const size_t nn = (size_t)p.n * p.n;
+  const int chunk = apply_chunk(p);
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+    for (int pass = 0; pass < 3; ++pass) {
+      hipError_t e = pass_cplx<T>(p, pass, nb, v + b0 * nn, m, alpha, add, out + b0 * nn, work, s, skip);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
                             hipStream_t s) {
-#define CALL(L) pass_cplx_n<T, L>(p, pass, batch, v, nullptr, (T)1, false, out, work, s, nullptr)
-  WS_DISPATCH_LOGN(p.logn, CALL)
-#undef CALL
+  return pass_cplx<T>(p, pass, batch, v, nullptr, (T)1, false, out, work, s, nullptr);
+}
+
+// Several plans in one set of launches: round r takes the r-th chunk of every
+// item, and each pass of a round is one launch per kMaxSegs items.
+template <typename T>
+hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipStream_t s) {
+  std::vector<int> done(count, 0);
+  for (;;) {
+    std::vector<Seg<T>> seg[3];
+    for (int i = 0; i < count; ++i) {
+      const Plan& p = *items[i].plan;
+      if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+      const int left = items[i].batch - done[i];
+      if (left <= 0) continue;
+      const int nb = std::min(left, apply_chunk(p));
+      const size_t off = (size_t)done[i] * p.n * p.n * (cplx ? sizeof(cx<T>) : sizeof(T));
+      const auto* in = static_cast<const char*>(items[i].in) + off;
+      auto* out = static_cast<char*>(items[i].out) + off;
+      auto* w = static_cast<cx<T>*>(items[i].work);
+      if (cplx) {
+        seg[0].push_back(make_seg<T, kRowsFwdCplx>(p, nb, in, nullptr, w, true));
+        seg[1].push_back(make_seg<T, kColsCplx>(p, nb, nullptr, nullptr, w, true));
+        seg[2].push_back(make_seg<T, kRowsInvCplx>(p, nb, in, out, w, true));
+      } else {
+        seg[0].push_back(make_seg<T, kRowsFwdReal>(p, nb, in, nullptr, w, true));
+        seg[1].push_back(make_seg<T, kColsReal>(p, nb, nullptr, nullptr, w, true));
+        seg[2].push_back(make_seg<T, kRowsInvReal>(p, nb, nullptr, out, w, true));
+      }
+      done[i] += nb;
+    }
+    if (seg[0].empty()) return hipSuccess;
+    for (int pass = 0; pass < 3; ++pass) {
+      for (size_t g0 = 0; g0 < seg[pass].size(); g0 += kMaxSegs) {
+        Segs<T> tab{};
+        tab.count = (int)std::min<size_t>(kMaxSegs, seg[pass].size() - g0);
+        for (int k = 0; k < tab.count; ++k) tab.s[k] = seg[pass][g0 + k];
+        hipError_t e;
+        if (cplx)
+          e = pass == 0 ? launch_segs<T, kRowsFwdCplx>(tab, s)
+              : pass == 1 ? launch_segs<T, kColsCplx>(tab, s) : launch_segs<T, kRowsInvCplx>(tab, s);
+        else
+          e = pass == 0 ? launch_segs<T, kRowsFwdReal>(tab, s)
+              : pass == 1 ? launch_segs<T, kColsReal>(tab, s) : launch_segs<T, kRowsInvReal>(tab, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
 }
 
 template hipError_t launch_pass_real<double>(const Plan&, int, int, const double*, double*, cx<double>*,
@@ -696,5 +797,7 @@ template hipError_t launch_apply_cplx<double>(const Plan&, int, const cx<double>
                                               cx<double>*, cx<double>*, hipStream_t, const int*);
 template hipError_t launch_apply_cplx<float>(const Plan&, int, const cx<float>*, const float*, float, bool,
                                              cx<float>*, cx<float>*, hipStream_t, const int*);
+template hipError_t launch_apply_multi<double>(const ApplyItem*, int, bool, hipStream_t);
+template hipError_t launch_apply_multi<float>(const ApplyItem*, int, bool, hipStream_t);
 
 }  // namespace ws

@@ -1,0 +1,196 @@
+// Tile geometry of the apply kernels (apply.hip): threads, LDS and tile
+// shapes per grid size, block sizes per kind of pass, and the block -> tile
+// and thread -> element maps.  Host and device code, so the geometry can be
+// checked on a host without a GPU.
+#pragma once
+#include <algorithm>
+#include <utility>
+
+#include "fft_core.hpp"
+#include "plan.hpp"
+
+namespace ws {
+
+template <typename T, int LOGN>
+struct Cfg {
+  static constexpr int n = 1 << LOGN;
+  static constexpr int CB = Layout<T>::CB;
+  static constexpr int RPB = Layout<T>::RPB;
+  static constexpr int cap(int e, int lines, int L) {         // keep lines * L / e <= 1024 threads
+    while (lines * (L / e) > 1024) e *= 2;
+    return e < L ? e : L;
+  }
+  // Real row passes: two half-length lines (even/odd spectrum) per row, one line per thread group.
+  static constexpr int LH = n / 2;
+  static constexpr int EH = cap(Layout<T>::ER, 2 * RPB, LH);
+  static constexpr int PH = LH / EH;
+  static constexpr int NT_RH = 2 * RPB * PH;
+  static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
+  static constexpr int LDS_RH = 2 * RPB * SH_;               // LDS elements per real row tile
+  // Column passes: two full-length lines (even/odd frequencies) per column,
+  // CPB columns per tile (CPB = CB, or 1 with XCD-paired tiles).
+  static constexpr int CPB = Layout<T>::CPB1 ? 1 : CB;
+  static constexpr int LF = n;
+  static constexpr int EF = cap(Layout<T>::EC, 2 * CPB, LF);
+  static constexpr int PF = LF / EF;
+  static constexpr int NT_C = 2 * CPB * PF;
+  static constexpr int SF = LineLayout<LF, EF>::STRIDE;
+  static constexpr int LDS_C = 2 * CPB * SF;
+  // Complex row passes: two full-length lines per row, rows per tile limited by LDS.
+  template <int ROWS>
+  static constexpr bool fits() {
+    constexpr int e = cap(Layout<T>::ER, 2 * ROWS, LF);
+    return ROWS * 2 * LineLayout<LF, e>::STRIDE * (int)sizeof(cx<T>) <= 81920;
+  }
+  static constexpr int R2_ = RPB / 2 > 1 ? RPB / 2 : 1, R4_ = RPB / 4 > 1 ? RPB / 4 : 1;
+  static constexpr int RPBC = fits<RPB>() ? RPB : fits<R2_>() ? R2_ : fits<R4_>() ? R4_ : 1;
+  static constexpr int EFR = cap(Layout<T>::ER, 2 * RPBC, LF);
+  static constexpr int PFR = LF / EFR;
+  static constexpr int NT_RC = 2 * RPBC * PFR;
+  static constexpr int SFR = LineLayout<LF, EFR>::STRIDE;
+  static constexpr int LDS_RC = 2 * RPBC * SFR;
+  // Row tiles sharing 128-byte lines of the intermediate (real and complex row passes).
+  static constexpr int RG = 128 / (RPB * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPB * CB * (int)sizeof(cx<T>)) : 1;
+  static constexpr int RGC = 128 / (RPBC * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPBC * CB * (int)sizeof(cx<T>)) : 1;
+};
+
+constexpr int kMinLogn = 4, kMaxLogn = 11;
+constexpr int kMaxSegs = 8;
+
+// Block size and LDS of each kind of pass: the largest over all sizes.
+template <typename T>
+struct Blk {
+  template <int... L>
+  static constexpr int max_nt(int which, std::integer_sequence<int, L...>) {
+    int m = 64;
+    ((m = std::max(m, which == 0 ? Cfg<T, L + kMinLogn>::NT_RH
+                      : which == 1 ? Cfg<T, L + kMinLogn>::NT_C : Cfg<T, L + kMinLogn>::NT_RC)), ...);
+    return m;
+  }
+  using Seq = std::make_integer_sequence<int, kMaxLogn - kMinLogn + 1>;
+  static constexpr int RH = max_nt(0, Seq{});
+  static constexpr int C = max_nt(1, Seq{});
+  static constexpr int RC = max_nt(2, Seq{});
+  template <int... L>
+  static constexpr int max_lds(int which, std::integer_sequence<int, L...>) {
+    int m = 0;
+    ((m = std::max(m, which == 0 ? (RH / Cfg<T, L + kMinLogn>::NT_RH) * Cfg<T, L + kMinLogn>::LDS_RH
+                      : which == 1 ? (C / Cfg<T, L + kMinLogn>::NT_C) * Cfg<T, L + kMinLogn>::LDS_C
+                                   : (RC / Cfg<T, L + kMinLogn>::NT_RC) * Cfg<T, L + kMinLogn>::LDS_RC)), ...);
+    return m;
+  }
+  static constexpr int LDS_RH = max_lds(0, Seq{});
+  static constexpr int LDS_C = max_lds(1, Seq{});
+  static constexpr int LDS_RC = max_lds(2, Seq{});
+  static_assert(LDS_RH * sizeof(cx<T>) <= 163840 && LDS_C * sizeof(cx<T>) <= 163840 &&
+                LDS_RC * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
+  // Waves per SIMD the column kernel reserves registers for: as many blocks
+  // per CU (up to two) as its LDS allows.
+  static constexpr int waves(int threads, int lds_bytes) {
+    const int blocks = lds_bytes * 2 <= 163840 ? 2 : 1;
+    const int w = (blocks * threads + 255) / 256;
+    return w < 1 ? 1 : w;
+  }
+  static constexpr int WAVES_C = waves(C, LDS_C * (int)sizeof(cx<T>));
+};
+
+// Thread -> (column c, line l, p) of a column tile.  When a wave can hold
+// 64/CPB consecutive p of every column, the wave's lanes split into CPB groups
+// of consecutive p: its global accesses cover one contiguous span and every
+// 8-lane LDS phase stays on one line.
+template <int CPB, int P>
+__host__ __device__ inline void col_thread(int tid, int& c, int& p, int& l) {
+  constexpr int LPC = 64 / CPB;
+  if constexpr (CPB <= 64 && 64 % CPB == 0 && P % LPC == 0 && P >= LPC) {
+    constexpr int WPL = P / LPC;
+    const int w = tid / 64, lane = tid % 64;
+    c = lane / LPC;
+    l = w / WPL;
+    p = (w % WPL) * LPC + lane % LPC;
+  } else {
+    c = tid % CPB;
+    p = (tid / CPB) % P;
+    l = tid / (CPB * P);
+  }
+}
+
+// Block -> tile-group maps.  Blocks are dealt round-robin to the 8 XCDs (each
+// with its own L2).  When G consecutive groups share 128-byte lines of the
+// blocked intermediate they are given to blocks 8 apart, which land on the
+// same XCD at about the same time, so the second reader finds the lines in
+// that XCD's L2.  Blocks past the last whole set of 8 G keep the identity map.
+constexpr int kXcds = 8;
+template <int G>
+__host__ __device__ inline int xcd_tile(int b, int nblocks) {
+  if constexpr (G <= 1) {
+    return b;
+  } else {
+    const int full = nblocks - nblocks % (kXcds * G);
+    if (b >= full) return b;
+    const int minor = (b / kXcds) % G;
+    const int major = (b / (kXcds * G)) * kXcds + b % kXcds;
+    return major * G + minor;
+  }
+}
+
+// Kinds of pass kernels.
+enum PassKind { kRowsFwdReal, kColsReal, kColsGen, kRowsInvReal, kRowsInvFs, kRowsFwdCplx, kRowsFwdCplxMul,
+                kColsCplx, kRowsInvCplx };
+
+template <typename T, int K>
+struct KindOf {
+  static constexpr bool ROWS_R = K == kRowsFwdReal || K == kRowsInvReal || K == kRowsInvFs;
+  static constexpr bool ROWS_C = K == kRowsFwdCplx || K == kRowsFwdCplxMul || K == kRowsInvCplx;
+  static constexpr bool CPLX_COLS = K == kColsCplx;
+  // block size, LDS elements and waves of the several-size kernel
+  static constexpr int BLK = ROWS_R ? Blk<T>::RH : ROWS_C ? Blk<T>::RC : Blk<T>::C;
+  static constexpr int LDS = ROWS_R ? Blk<T>::LDS_RH : ROWS_C ? Blk<T>::LDS_RC : Blk<T>::LDS_C;
+  static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : Blk<T>::WAVES_C;
+  template <int LOGN>
+  static constexpr int nt() {
+    return ROWS_R ? Cfg<T, LOGN>::NT_RH : ROWS_C ? Cfg<T, LOGN>::NT_RC : Cfg<T, LOGN>::NT_C;
+  }
+  template <int LOGN>
+  static constexpr int lds_tile() {
+    return ROWS_R ? Cfg<T, LOGN>::LDS_RH : ROWS_C ? Cfg<T, LOGN>::LDS_RC : Cfg<T, LOGN>::LDS_C;
+  }
+  // tiles of a density, and consecutive tiles that share 128-byte lines of the intermediate
+  template <int LOGN>
+  static constexpr int tiles_per_density() {
+    using C = Cfg<T, LOGN>;
+    return ROWS_R ? C::n / C::RPB : ROWS_C ? C::n / C::RPBC : (CPLX_COLS ? 2 * C::n : C::n) / C::CPB;
+  }
+  template <int LOGN>
+  static constexpr int line_group() {
+    using C = Cfg<T, LOGN>;
+    return ROWS_R ? C::RG : ROWS_C ? C::RGC : C::CB / C::CPB;
+  }
+};
+
+// Block of the single-size kernel: at least WS_MIN_BLOCK threads, so the
+// tiles of small grids share blocks; LDS for that many tiles of this size.
+#ifndef WS_MIN_BLOCK
+#define WS_MIN_BLOCK 64
+#endif
+template <typename T, int K, int LOGN>
+struct Single {
+  static constexpr int NT = KindOf<T, K>::template nt<LOGN>();
+  static constexpr int BLOCK = NT > WS_MIN_BLOCK ? NT : WS_MIN_BLOCK;
+  static constexpr int TPB = BLOCK / NT;
+  static constexpr int LDS = TPB * KindOf<T, K>::template lds_tile<LOGN>();
+  // Waves per SIMD the registers are sized for.  Row kernels: as many blocks
+  // as the LDS admits (at most 8 waves per SIMD).  Column kernels: at most two
+  // blocks per CU (their butterflies need the registers).
+  static constexpr int lds_waves() {
+    const int blocks = 163840 / (LDS * (int)sizeof(cx<T>));
+    const int w = blocks * BLOCK / 256;
+    return w < 1 ? 1 : w > 8 ? 8 : w;
+  }
+  static constexpr int WAVES = (KindOf<T, K>::ROWS_R || KindOf<T, K>::ROWS_C)
+                                   ? lds_waves()
+                                   : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>));
+  static_assert(BLOCK % NT == 0 && BLOCK <= 1024, "bad block size");
+  static_assert(LDS * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
+};
+
+}  // namespace ws

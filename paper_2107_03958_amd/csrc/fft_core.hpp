@@ -205,12 +205,12 @@ struct LineLayout {
   static constexpr int SH = ilog2(FirstLast<L, E>::R0);
   static constexpr int LEN = L + (L >> SH);
   static constexpr int STRIDE = LEN + 2;
-  __device__ __forceinline__ static int pad(int i) { return i + (i >> SH); }
+  __host__ __device__ static int pad(int i) { return i + (i >> SH); }
   // Padded index of element p + (L/E) * s: pad(p) + s * PSTEP when L/E is a multiple of R0.
   static constexpr int P_ = L / E;
   static constexpr int PSTEP = P_ + (P_ >> SH);
   static constexpr bool LINEAR = (P_ % (1 << SH)) == 0;
-  __device__ __forceinline__ static int pad_ps(int p, int s) {
+  __host__ __device__ static int pad_ps(int p, int s) {
     if constexpr (LINEAR) return pad(p) + s * PSTEP;
     else return pad(p + P_ * s);
   }

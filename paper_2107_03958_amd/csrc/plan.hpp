@@ -120,6 +120,20 @@ template <typename T>
 hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
                             hipStream_t s);
 
+// One item of a multi-plan apply: `batch` densities of one plan.  work holds
+// min(batch, apply_chunk(plan)) * work_bytes.
+struct ApplyItem {
+  const Plan* plan;
+  int batch;
+  const void* in;
+  void* out;
+  void* work;
+};
+// Apply several plans (same precision T; all real-path or all complex-path)
+// in one set of launches per pass: densities of different sizes share launches.
+template <typename T>
+hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipStream_t s);
+
 // Plan construction kernels (moments.hip).
 hipError_t launch_build_tables(Plan& p, hipStream_t s);
 

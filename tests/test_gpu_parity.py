@@ -53,7 +53,7 @@ def test_real_apply_batch(api, kname, n):
         assert metrics.rel_linf(got[i], ref) <= FP64_TOL, (kname, n, i)
 
 
-@pytest.mark.parametrize("n", [512])
+@pytest.mark.parametrize("n", [512, 1024])
 def test_real_apply_n512_log(api, n):
     us = np.stack([synth.smooth_density(n, 1000 + i) for i in range(2)])
     plan = api.ConvPlan(n=n, **plan_kwargs("log"))
@@ -188,7 +188,7 @@ def test_mixed_fs_and_plain_batch(api):
 
 
 @pytest.mark.parametrize("kname", ["log", "pow-1/2"])
-@pytest.mark.parametrize("n", [64, 256])
+@pytest.mark.parametrize("n", [16, 32, 64, 256])
 def test_fp32_apply_bound(api, kname, n):
     us = np.stack([synth.smooth_density(n, 2000 + i) for i in range(2)])
     plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs(kname))
@@ -289,3 +289,61 @@ def test_ls_maxit_status(api):
     u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-14, restart=5,
                             max_matvecs=7)
     assert info.status == 1 and info.matvecs <= 8 and info.rel_residual > 1e-14
+
+
+# Densities of different sizes and kernels in shared launches (conv_apply_multi).
+MULTI_REAL = [("log", 64, 3), ("pow-1/2", 128, 2), ("pow-1/3", 16, 5), ("log", 512, 1), ("log", 32, 4),
+              ("pow-1/2", 256, 2), ("log", 16, 1), ("pow-1/3", 1024, 1), ("log", 2048, 3), ("pow-1/2", 64, 2)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_apply_multi_uneven_sizes_real(api, precision):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    plans = [api.ConvPlan(n=n, precision=precision, **plan_kwargs(k)) for k, n, _ in MULTI_REAL]
+    hosts = [np.stack([synth.smooth_density(n, 1300 + 10 * i + j) for j in range(b)])
+             for i, (_, n, b) in enumerate(MULTI_REAL)]
+    dens = [_gpu(h, dt) for h in hosts]
+    outs = api.apply_multi(plans, dens)            # 10 items: more than one launch per pass
+    # The same arithmetic as a single-plan apply, compiled into a different kernel
+    # (another block shape), so results agree to rounding rather than bitwise.
+    same = 1e-14 if precision == "fp64" else 2e-6
+    for (k, n, b), p, d, o in zip(MULTI_REAL, plans, dens, outs):
+        one = p.apply(d).cpu().numpy().astype(np.float64)
+        got = o.cpu().numpy().astype(np.float64)
+        assert metrics.rel_linf(got, one) <= same, (k, n)
+        # against the oracle where its moment table is cheap (the power-kernel table is
+        # a quadrature per distinct |k|: minutes of CPU above n = 256)
+        if n > (1024 if k == "log" else 256):
+            continue
+        for j in range(b):
+            ref = np.real(scheme.apply(hosts[MULTI_REAL.index((k, n, b))][j], oracle_table(k, n), B))
+            if precision == "fp64":
+                assert metrics.rel_linf(got[j], ref) <= FP64_TOL, (k, n, j)
+            else:
+                assert metrics.rel_linf(got[j], ref) <= 2e-6 and metrics.rel_l2(got[j], ref) <= 5e-7, (k, n, j)
+
+
+def test_apply_multi_uneven_sizes_complex(api):
+    specs = [("helm20", 64, 2), ("helm40", 128, 1), ("helm20", 16, 3), ("helm40", 256, 2)]
+    plans = [api.ConvPlan(n=n, **plan_kwargs(k)) for k, n, _ in specs]
+    rng = np.random.default_rng(77)
+    hosts = [(rng.normal(size=(b, n, n)) + 1j * rng.normal(size=(b, n, n))) * synth.cutoff(n) for _, n, b in specs]
+    dens = [_gpu(h, torch.complex128) for h in hosts]
+    outs = api.apply_multi(plans, dens)
+    for (k, n, b), p, d, o, h in zip(specs, plans, dens, outs, hosts):
+        assert metrics.rel_linf(o.cpu().numpy(), p.apply(d).cpu().numpy()) <= 1e-14, (k, n)
+        for j in range(b):
+            ref = scheme.apply(h[j], oracle_table(k, n), B)
+            assert metrics.rel_linf(o[j].cpu().numpy(), ref) <= FP64_TOL, (k, n, j)
+
+
+def test_apply_multi_rejects_mixed_kinds(api):
+    from paper_2107_03958_amd import _lib as L
+    a = api.ConvPlan(n=32, **plan_kwargs("log"))
+    b = api.ConvPlan(n=32, **plan_kwargs("helm20"))
+    c = api.ConvPlan(n=32, precision="fp32", **plan_kwargs("log"))
+    u = torch.zeros((1, 32, 32), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.WsError):
+        api.apply_multi([a, b], [u, u.to(torch.complex128)])
+    with pytest.raises(L.WsError):
+        api.apply_multi([a, c], [u, u.float()])
