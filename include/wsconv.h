@@ -184,7 +184,12 @@ int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* wor
  *  max_matvecs: bound on operator applications (all cycles).
  *  work:      ls_solve_query bytes of device scratch.
  *  info:      host struct, filled on return.
- * Synchronises `stream` once per restart cycle to read the convergence state.
+ * Arnoldi steps are enqueued in chunks of four, replayed from graphs captured
+ * on first use and cached in the plan per (work, contrast, restart) buffers;
+ * with the environment variable WSCONV_LS_GRAPHS=0 set when the plan is built
+ * they are launched directly.  On the null stream the solve runs on a
+ * library-owned stream ordered after and before the caller's work.
+ * Synchronises the stream a few times per restart cycle to read the convergence state.
  * Returns WS_OK when it converged, 1 (positive) when it stopped at max_matvecs
  * (u_out holds the last iterate) and WS_LS_BREAKDOWN status with return 2 on a
  * non-finite residual. */

@@ -179,6 +179,9 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
     delete p;
     return hip_fail(e, "conv_plan: table kernels");
   }
+  // GMRES steps of Helmholtz plans replay captured graphs unless WSCONV_LS_GRAPHS=0.
+  const char* gr = std::getenv("WSCONV_LS_GRAPHS");
+  if (cplx && !(gr && std::strcmp(gr, "0") == 0)) p->graphs = ws::ls_graph_cache_create();
   *out_plan = p;
   return WS_OK;
 }
@@ -382,6 +385,10 @@ int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, d
   return WS_OK;
 }
 
-void conv_destroy(ws_plan_t plan) { delete plan; }
+void conv_destroy(ws_plan_t plan) {
+  if (!plan) return;
+  if (plan->graphs) ws::ls_graph_cache_destroy(plan->graphs);
+  delete plan;
+}
 
 }  // extern "C"

@@ -4,10 +4,15 @@
 // The paper solves it with a matrix-free GMRES; restart length, tolerance and
 // orthogonalisation are not stated.  Here: x0 = 0, classical Gram-Schmidt
 // applied twice (CGS2) with FP64 accumulation, Givens rotations on the
-// Hessenberg matrix, all on the device.  The host enqueues a whole restart
-// cycle without waiting (later steps of a converged cycle exit at entry on a
-// device flag), then synchronises once to read the cycle's state, and once to
-// read the true residual ||rhs - K x|| that decides convergence.
+// Hessenberg matrix, all on the device.  An Arnoldi step is eight launches:
+// the three passes of the operator, two (dot products, update) pairs in which
+// the update blocks finish the dot products, and the normalisation, whose
+// blocks finish the norm and whose first block applies the Givens rotation.
+// The host enqueues a cycle's steps in chunks (replayed as captured graphs),
+// watches the device's stop flag one chunk behind through page-locked memory
+// (steps enqueued past the stop exit at entry), then synchronises once to read
+// the cycle's state and once to read the true residual ||rhs - K x|| that
+// decides convergence.
 //
 // Mixed precision: iterative refinement with the FP64 residual r = u_inc - K x
 // (FP64 operator) and corrections from GMRES on the FP32 operator applied to
@@ -15,7 +20,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ls.hpp"
@@ -55,7 +63,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// partial[i][b] = sum over block b's elements of conj(V_i) w
+// ---------------------------------------------------------------------------
+// Arnoldi step kernels.  Reductions finish in the next kernel of the step
+// (stream order makes the partials visible), each block repeating the small
+// final sum in a fixed order, so the results do not depend on timing.
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partial[i][b] = sum over block b's elements of conj(V_i) w, i < nv (grid nbd x nv).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dots(const cx<T>* V, size_t N, const cx<T>* w, cx<double>* partial,
                                                    const GState* st) {
@@ -74,33 +92,30 @@ __global__ __launch_bounds__(kThreads) void k_dots(const cx<T>* V, size_t N, con
   if (threadIdx.x == 0) partial[(size_t)i * gridDim.x + blockIdx.x] = {re, im};
 }
 
-// h[i] = sum_b partial[i][b]; Hcol[i] += h[i]
-__global__ __launch_bounds__(kThreads) void k_dots_finish(const cx<double>* partial, int nb, cx<double>* h,
-                                                          cx<double>* Hcol, const GState* st) {
-  if (st->done) return;
-  __shared__ double sh[kThreads];
-  const int i = blockIdx.x;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    re += partial[(size_t)i * nb + b].x;
-    im += partial[(size_t)i * nb + b].y;
-  }
-  re = block_sum(re, sh);
-  im = block_sum(im, sh);
-  if (threadIdx.x == 0) {
-    h[i] = {re, im};
-    Hcol[i] = {Hcol[i].x + re, Hcol[i].y + im};
-  }
-}
-
-// w -= sum_{i<nv} V_i h_i; optionally partial |w|^2 per block.
+// h_i = sum_b partial[i][b] (every block, one wave per coefficient; block 0
+// adds h into Hessenberg column Hcol), then w -= sum_{i<nv} V_i h_i and, on
+// the second Gram-Schmidt pass, per-block partial sums of |w|^2.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, int nv, cx<T>* w,
-                                                     const cx<double>* h, double* npart, const GState* st) {
+                                                     const cx<double>* partial, int nbd, cx<double>* Hcol,
+                                                     double* npart, const GState* st) {
   if (st->done) return;
   __shared__ cx<double> hs[256];
   __shared__ double sh[kThreads];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+  for (int i = wave; i < nv; i += nw) {
+    double sr = 0.0, si = 0.0;
+    for (int b = lane; b < nbd; b += 64) {
+      sr += partial[(size_t)i * nbd + b].x;
+      si += partial[(size_t)i * nbd + b].y;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+      hs[i] = {sr, si};
+      if (blockIdx.x == 0) Hcol[i] = {Hcol[i].x + sr, Hcol[i].y + si};
+    }
+  }
   __syncthreads();
   double acc = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
@@ -121,42 +136,37 @@ __global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, i
   }
 }
 
-// Norm of the new direction, Givens rotation of Hessenberg column j, stop test.
-__global__ void k_givens(cx<double>* H, int ldh, cx<double>* cs, cx<double>* sn, cx<double>* g,
-                         const double* npart, int nb, int j, GState* st) {
-  if (st->done) return;
-  __shared__ double sh[kThreads];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += npart[b];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x != 0) return;
-  const double nrm = sqrt(acc);
+// Givens rotation of Hessenberg column j given the new direction's norm, and
+// the stop test (one thread).
+__device__ void givens_step(cx<double>* H, int ldh, cx<double>* cs, cx<double>* sn, cx<double>* g, int j, double nrm,
+                            GState* st) {
   cx<double>* col = H + (size_t)j * ldh;      // column j, rows 0..j+1
   col[j + 1] = {nrm, 0.0};
   st->norm = nrm;
   for (int i = 0; i < j; ++i) {
     const cx<double> a = col[i], b = col[i + 1];
-    const cx<double> c = cs[i], s = sn[i];
+    const cx<double> c = cs[i], sv = sn[i];
     // [c s; -conj(s) conj(c)] applied to (a, b)
-    col[i] = {c.x * a.x - c.y * a.y + s.x * b.x - s.y * b.y, c.x * a.y + c.y * a.x + s.x * b.y + s.y * b.x};
-    col[i + 1] = {-(s.x * a.x + s.y * a.y) + (c.x * b.x + c.y * b.y), -(s.x * a.y - s.y * a.x) + (c.x * b.y - c.y * b.x)};
+    col[i] = {c.x * a.x - c.y * a.y + sv.x * b.x - sv.y * b.y, c.x * a.y + c.y * a.x + sv.x * b.y + sv.y * b.x};
+    col[i + 1] = {-(sv.x * a.x + sv.y * a.y) + (c.x * b.x + c.y * b.y),
+                  -(sv.x * a.y - sv.y * a.x) + (c.x * b.y - c.y * b.x)};
   }
   const cx<double> a = col[j];
   const double den = sqrt(a.x * a.x + a.y * a.y + nrm * nrm);
-  cx<double> c, s;
+  cx<double> c, sv;
   if (den == 0.0) {
     c = {1.0, 0.0};
-    s = {0.0, 0.0};
+    sv = {0.0, 0.0};
   } else {
     c = {a.x / den, -a.y / den};   // conj(a)/den
-    s = {nrm / den, 0.0};          // conj(b)/den, b = nrm real
+    sv = {nrm / den, 0.0};         // conj(b)/den, b = nrm real
   }
   cs[j] = c;
-  sn[j] = s;
+  sn[j] = sv;
   col[j] = {den, 0.0};
   col[j + 1] = {0.0, 0.0};
   const cx<double> gj = g[j];
-  g[j + 1] = {-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};   // -conj(s) g_j
+  g[j + 1] = {-(sv.x * gj.x + sv.y * gj.y), -(sv.x * gj.y - sv.y * gj.x)};   // -conj(s) g_j
   g[j] = {c.x * gj.x - c.y * gj.y, c.x * gj.y + c.y * gj.x};
   const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
   st->est = est;
@@ -169,11 +179,21 @@ __global__ void k_givens(cx<double>* H, int ldh, cx<double>* cs, cx<double>* sn,
   }
 }
 
-// w /= ||w|| (the norm stored by k_givens).
+// ||w|| from the partials (every block, same order); block 0 rotates
+// Hessenberg column j and applies the stop test; every block scales its part
+// of w to unit norm.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_normalise(cx<T>* w, size_t N, const GState* st) {
+__global__ __launch_bounds__(kThreads) void k_normalise_givens(cx<T>* w, size_t N, const double* npart, int nbn,
+                                                               cx<double>* H, int ldh, cx<double>* cs,
+                                                               cx<double>* sn, cx<double>* g, int j, GState* st) {
   if (st->done) return;
-  const double inv = 1.0 / st->norm;
+  __shared__ double sh[kThreads];
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < nbn; b += blockDim.x) tot += npart[b];
+  tot = block_sum(tot, sh);
+  const double nrm = sqrt(tot);
+  if (blockIdx.x == 0 && threadIdx.x == 0) givens_step(H, ldh, cs, sn, g, j, nrm, st);
+  const double inv = 1.0 / nrm;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
     const cx<double> x = up(w[e]);
     w[e] = down<T>({x.x * inv, x.y * inv});
@@ -396,14 +416,128 @@ hipError_t norm_sync(Krylov<T>& K, const cx<T>* v, double* out, hipStream_t s) {
   return e;
 }
 
+// Arnoldi steps are enqueued kChunk at a time.  After each chunk the cycle's
+// state is copied (asynchronously) to page-locked host memory; before the
+// next chunk is enqueued the host reads the state copied kLag chunks earlier
+// and stops enqueuing once the device has met the stop test there, so at most
+// kLag chunks of steps that exit at entry are enqueued after convergence.
+constexpr int kChunk = 4, kLag = 1, kMaxSnap = 64;
+
+struct HostSnapshots {
+  GState* pinned = nullptr;        // kMaxSnap page-locked slots
+  hipEvent_t ev[kMaxSnap] = {};
+  bool ok = false;
+  HostSnapshots() {
+    if (hipHostMalloc((void**)&pinned, sizeof(GState) * kMaxSnap, 0) != hipSuccess) return;
+    for (auto& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+    ok = true;
+  }
+};
+// One set per host thread, kept for the thread's lifetime.
+HostSnapshots& snapshots() {
+  static thread_local HostSnapshots h;
+  return h;
+}
+
+// Steps [j0, j0 + c) of an Arnoldi cycle: the operator, classical
+// Gram-Schmidt twice (FP64 coefficients), Givens rotation, normalisation.
+template <typename T, typename OpF>
+hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
+  const size_t N = K.N;
+  const int ldh = K.restart + 1;
+  const int nbu = grid_for(N);
+  // dot-product blocks per vector: few, so every update block can finish the sums cheaply
+  const int nbd = (int)std::min<size_t>(64, std::max<size_t>(8, N / 4096));
+  for (int j = j0; j < j0 + c; ++j) {
+    cx<T>* vj = K.V + (size_t)j * N;
+    cx<T>* w = K.V + (size_t)(j + 1) * N;
+    hipError_t e = op(vj, w, &K.st->done);
+    if (e != hipSuccess) return e;
+    cx<double>* Hcol = K.H + (size_t)j * ldh;
+    for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
+      k_dots<T><<<dim3(nbd, j + 1), kThreads, 0, s>>>(K.V, N, w, K.partial, K.st);
+      k_update<T><<<nbu, kThreads, 0, s>>>(K.V, N, j + 1, w, K.partial, nbd, Hcol, pass == 1 ? K.npart : nullptr,
+                                           K.st);
+    }
+    k_normalise_givens<T><<<nbu, kThreads, 0, s>>>(w, N, K.npart, nbu, K.H, ldh, K.cs, K.sn, K.g, j, K.st);
+  }
+  return hipGetLastError();
+}
+
+// Graphs of Arnoldi chunks, cached per plan: captured once for a Krylov
+// instance (its scratch address), an operator (contrast address) and a chunk,
+// then replayed.  The captured kernels read every changing value (the cycle
+// state, the stop flag) from device memory.
+struct GraphKey {
+  const void* st;          // Krylov instance (its scratch layout follows from restart and T)
+  const void* op;          // operator's contrast
+  int restart, elem, j0, c;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(st, op, restart, elem, j0, c) < std::tie(o.st, o.op, o.restart, o.elem, o.j0, o.c);
+  }
+};
+struct GraphCache {
+  std::mutex mu;
+  std::map<GraphKey, std::pair<hipGraphExec_t, uint64_t>> map;
+  uint64_t clock = 0;
+  static constexpr size_t kMax = 256;
+  ~GraphCache() {
+    for (auto& kv : map) (void)hipGraphExecDestroy(kv.second.first);
+  }
+};
+
+template <typename T, typename OpF>
+hipError_t run_chunk(const Plan& p, Krylov<T>& K, OpF& op, const void* op_id, int j0, int c, hipStream_t s,
+                     bool graphs) {
+  if (!graphs) return arnoldi_steps(K, op, j0, c, s);
+  auto* cache = static_cast<GraphCache*>(p.graphs);
+  const GraphKey key{K.st, op_id, K.restart, (int)sizeof(T), j0, c};
+  hipGraphExec_t ex = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(cache->mu);
+    auto it = cache->map.find(key);
+    if (it != cache->map.end()) {
+      it->second.second = ++cache->clock;
+      ex = it->second.first;
+    }
+  }
+  if (!ex) {
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ek = arnoldi_steps(K, op, j0, c, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (ek != hipSuccess) e = ek;
+    if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&ex, g, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(cache->mu);
+    if (cache->map.size() >= GraphCache::kMax) {   // drop the least recently used
+      auto victim = cache->map.begin();
+      for (auto it = cache->map.begin(); it != cache->map.end(); ++it)
+        if (it->second.second < victim->second.second) victim = it;
+      (void)hipGraphExecDestroy(victim->second.first);
+      cache->map.erase(victim);
+    }
+    cache->map[key] = {ex, ++cache->clock};
+  }
+  return hipGraphLaunch(ex, s);
+}
+
 // GMRES(restart) for Op x = rhs from x = 0 (x must be zeroed by the caller).
 // Stops when the true residual ||rhs - Op x|| <= tol_rel ||rhs||, at max_mv
 // operator applications, or on a non-finite value.  Returns the status code.
 template <typename T, typename OpF>
-int gmres(Krylov<T>& K, OpF op, const cx<T>* rhs, cx<T>* x, double tol_rel, int max_mv, Counters& cnt,
-          double* relres, hipStream_t s, hipError_t* herr) {
+int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* rhs, cx<T>* x, double tol_rel,
+          int max_mv, Counters& cnt, double* relres, hipStream_t s, bool graphs, hipError_t* herr) {
   const size_t N = K.N;
   const int ldh = K.restart + 1;
+  HostSnapshots& snap = snapshots();
+  if (!snap.ok) {
+    *herr = hipErrorOutOfMemory;
+    return -1;
+  }
   double rhsn = 0.0;
   if ((*herr = norm_sync(K, rhs, &rhsn, s)) != hipSuccess) return -1;
   if (!std::isfinite(rhsn)) return WS_LS_BREAKDOWN;
@@ -422,18 +556,22 @@ int gmres(Krylov<T>& K, OpF op, const cx<T>* rhs, cx<T>* x, double tol_rel, int 
     if (cnt.matvecs >= max_mv) return WS_LS_MAXIT;
     k_cycle_start<T><<<grid_for(N), kThreads, 0, s>>>(rcur, K.V, N, K.H, ldh * K.restart, K.g, ldh, K.st, tol_abs);
     const int steps = std::min(K.restart, max_mv - cnt.matvecs);
-    for (int j = 0; j < steps; ++j) {
-      cx<T>* vj = K.V + (size_t)j * N;
-      cx<T>* w = K.V + (size_t)(j + 1) * N;
-      if ((*herr = op(vj, w, &K.st->done)) != hipSuccess) return -1;
-      cx<double>* Hcol = K.H + (size_t)j * ldh;
-      for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
-        k_dots<T><<<dim3(kBlocks, j + 1), kThreads, 0, s>>>(K.V, N, w, K.partial, K.st);
-        k_dots_finish<<<j + 1, kThreads, 0, s>>>(K.partial, kBlocks, K.h, Hcol, K.st);
-        k_update<T><<<kBlocks, kThreads, 0, s>>>(K.V, N, j + 1, w, K.h, pass == 1 ? K.npart : nullptr, K.st);
+    int nsnap = 0;
+    for (int j0 = 0; j0 < steps; j0 += kChunk) {
+      const int c = std::min(kChunk, steps - j0);
+      if ((*herr = run_chunk(p, K, op, op_id, j0, c, s, graphs)) != hipSuccess) return -1;
+      if (nsnap < kMaxSnap) {
+        if ((*herr = hipMemcpyAsync(&snap.pinned[nsnap], K.st, sizeof(GState), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (*herr = hipEventRecord(snap.ev[nsnap], s)) != hipSuccess)
+          return -1;
+        ++nsnap;
       }
-      k_givens<<<1, kThreads, 0, s>>>(K.H, ldh, K.cs, K.sn, K.g, K.npart, kBlocks, j, K.st);
-      k_normalise<T><<<kBlocks, kThreads, 0, s>>>(w, N, K.st);
+      if (nsnap > kLag && j0 + c < steps) {
+        const int k = nsnap - 1 - kLag;
+        if ((*herr = hipEventSynchronize(snap.ev[k])) != hipSuccess) return -1;
+        if (snap.pinned[k].done) break;
+      }
     }
     if ((*herr = hipGetLastError()) != hipSuccess) return -1;
     GState hs;
@@ -472,8 +610,59 @@ size_t ls_work_bytes(const Plan& p, int restart, bool mixed) {
   return b;
 }
 
+void* ls_graph_cache_create() { return new GraphCache(); }
+void ls_graph_cache_destroy(void* c) { delete static_cast<GraphCache*>(c); }
+
+namespace {
+// A non-blocking stream per host thread for callers on the null stream, which
+// cannot be captured into graphs.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  bool ok = false;
+  SideStream() {
+    ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+  }
+};
+SideStream& side_stream() {
+  static thread_local SideStream ss;
+  return ss;
+}
+}  // namespace
+
+int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart,
+              int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
+              bool graphs, std::string* err);
+
 int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart, int max_matvecs,
            bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s, std::string* err) {
+  const bool graphs = p.graphs != nullptr;
+  if (!graphs || s != nullptr)
+    return ls_run_on(p, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, s, graphs, err);
+  // Null stream: run on this thread's side stream, ordered after and before the caller's work.
+  SideStream& ss = side_stream();
+  hipError_t e = ss.ok ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = hipEventRecord(ss.fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ss.s, ss.fork, 0);
+  if (e != hipSuccess) {
+    *err = std::string("ls_solve: ") + hipGetErrorString(e);
+    return WS_EDEVICE;
+  }
+  const int rc = ls_run_on(p, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, ss.s, true, err);
+  e = hipEventRecord(ss.join, ss.s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ss.join, 0);
+  if (e != hipSuccess && rc >= 0) {
+    *err = std::string("ls_solve: ") + hipGetErrorString(e);
+    return WS_EDEVICE;
+  }
+  return rc;
+}
+
+int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart,
+              int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
+              bool graphs, std::string* err) {
   const size_t N = (size_t)p.n * p.n;
   const double k2 = p.kern.kappa * p.kern.kappa;
   Counters cnt;
@@ -488,7 +677,7 @@ int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, doubl
       return launch_apply_cplx<double>(p, 1, in, contrast, k2, true, out, K.awork, s, skip);
     };
     k_zero<double><<<grid_for(N), kThreads, 0, s>>>(u_out, N);
-    status = gmres<double>(K, op, u_inc, u_out, tol, max_matvecs, cnt, &relres, s, &he);
+    status = gmres<double>(p, K, op, contrast, u_inc, u_out, tol, max_matvecs, cnt, &relres, s, graphs, &he);
     if (status < 0) goto device_error;
   } else {
     Krylov<float> K32;
@@ -527,8 +716,8 @@ int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, doubl
         k_convert<double, float><<<grid_for(N), kThreads, 0, s>>>(r64, rhs32, N, K64.st, 1);
         k_zero<float><<<grid_for(N), kThreads, 0, s>>>(delta, N);
         double inner_rel = 0.0;
-        const int ist = gmres<float>(K32, op32, rhs32, delta, inner_tol, max_matvecs - cnt.matvecs, cnt,
-                                     &inner_rel, s, &he);
+        const int ist = gmres<float>(p, K32, op32, m32, rhs32, delta, inner_tol, max_matvecs - cnt.matvecs, cnt,
+                                     &inner_rel, s, graphs, &he);
         if (ist < 0) goto device_error;
         if (ist == WS_LS_BREAKDOWN) { status = WS_LS_BREAKDOWN; break; }
         k_axpy<float, double><<<grid_for(N), kThreads, 0, s>>>(delta, u_out, N, rn);

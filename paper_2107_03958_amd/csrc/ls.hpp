@@ -15,4 +15,9 @@ size_t ls_work_bytes(const Plan& p, int restart, bool mixed);
 int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart, int max_matvecs,
            bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s, std::string* err);
 
+// Cache of captured GMRES step graphs kept by a Helmholtz plan (created with
+// the plan, destroyed with it).
+void* ls_graph_cache_create();
+void ls_graph_cache_destroy(void* cache);
+
 }  // namespace ws

@@ -79,6 +79,7 @@ struct Plan {
   cx<double>* tw64 = nullptr; // exp(-2 pi i m / nb), m in [0, nb)
   TwPair* tw32 = nullptr;     // (hi, lo) float pairs of the same twiddles
   int cus = 256;               // compute units of the plan's device
+  void* graphs = nullptr;      // Helmholtz plans: captured GMRES step graphs (ls.hip)
   size_t plan_bytes = 0;
   size_t work_bytes = 0;      // per density
 };

@@ -347,3 +347,40 @@ def test_apply_multi_rejects_mixed_kinds(api):
         api.apply_multi([a, b], [u, u.to(torch.complex128)])
     with pytest.raises(L.WsError):
         api.apply_multi([a, c], [u, u.float()])
+
+
+def test_ls_graph_replays_match_eager(api, monkeypatch):
+    # GMRES steps replayed from captured graphs give the eager launches' results,
+    # replay after replay, with other GPU work and synchronisations in between,
+    # on the null stream and on a side stream.
+    n, kappa = 64, 40.0
+    m = _gpu(synth.contrast(n), torch.float64)
+    ui = _gpu(synth.plane_wave(n, kappa, 0.9), torch.complex128)
+    monkeypatch.setenv("WSCONV_LS_GRAPHS", "0")
+    eager = api.ConvPlan(n=n, **plan_kwargs("helm40"))
+    monkeypatch.delenv("WSCONV_LS_GRAPHS")
+    graph = api.ConvPlan(n=n, **plan_kwargs("helm40"))
+    for mixed, prec in ((False, "fp64"), (True, "fp32")):
+        pe = eager if not mixed else None
+        if mixed:
+            monkeypatch.setenv("WSCONV_LS_GRAPHS", "0")
+            pe = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("helm40"))
+            monkeypatch.delenv("WSCONV_LS_GRAPHS")
+        pg = graph if not mixed else api.ConvPlan(n=n, precision="fp32", **plan_kwargs("helm40"))
+        ref, iref = pe.ls_solve(m, ui, tol=1e-10, restart=20, mixed=mixed)
+        work = pg.ls_workspace(20, mixed)
+        out = torch.empty_like(ui)
+        noise = api.ConvPlan(n=128, **plan_kwargs("log"))
+        side = torch.cuda.Stream()
+        for rep in range(4):
+            got, info = pg.ls_solve(m, ui, tol=1e-10, restart=20, mixed=mixed, out=out, work=work)
+            torch.cuda.synchronize()
+            assert torch.equal(got, ref), (prec, rep)
+            assert info.matvecs == iref.matvecs and info.status == 0
+            noise.apply(torch.randn((2, 128, 128), dtype=torch.float64, device="cuda"))   # eager work between
+            torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            got, info = pg.ls_solve(m, ui, tol=1e-10, restart=20, mixed=mixed, work=work,
+                                    stream=side)
+        side.synchronize()
+        assert torch.equal(got, ref), prec
