@@ -36,6 +36,8 @@ KERNELS = [
     ("|x|^-1/3", dict(family="power", scale=1.0, gamma=-1.0 / 3.0)),
 ]
 PASS_NAMES = ["k_rows_fwd_real", "k_cols", "k_rows_inv_real"]
+# Kernel symbol of each pass of a real-kernel apply (ws::k_pass1<T, pass kind, log2 n>).
+PASS_KINDS = [0, 1, 3]
 
 
 def log(msg):
@@ -66,10 +68,9 @@ def measured_traffic(kernel: str, precision: str, n: int, chunk: int):
     res = traffic.load_for_current_sources(TRAFFIC_SUMMARY)
     if res is None or res.get("densities_per_dispatch") != chunk:
         return None
-    for name, v in res["kernels"].items():
-        if name.startswith("ws::" + kernel + "<double"):
-            return v["traffic_bytes"]
-    return None
+    sym = f"ws::k_pass1<double, {PASS_KINDS[PASS_NAMES.index(kernel)]}, {n.bit_length() - 1}>"
+    v = res["kernels"].get(sym)
+    return None if v is None else v["traffic_bytes"]
 
 
 def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):

@@ -23,6 +23,11 @@ namespace ws {
 //  CHUNK: a batch is run through all three passes CHUNK_BYTES of intermediate at a
 //       time, so the intermediate of a chunk stays in the 256 MB Infinity Cache
 //       between the passes instead of round-tripping through HBM.
+// Shapes chosen by the autotuner (paper_2107_03958_amd/autotune.py) take
+// precedence over the defaults below; -D overrides take precedence over both.
+#if __has_include("tuned.hpp")
+#include "tuned.hpp"
+#endif
 #ifndef WS_CB64
 #define WS_CB64 2
 #endif

@@ -1,0 +1,40 @@
+// Tile shapes chosen by paper_2107_03958_amd/autotune.py on MI355X (gfx950),
+// timing the three apply passes at n = 2048; one parameter changed at a time
+// from the previous shapes, kept when more than 1% faster.
+#pragma once
+#ifndef WS_CB32
+#define WS_CB32 2
+#endif
+#ifndef WS_CB64
+#define WS_CB64 2
+#endif
+#ifndef WS_CHUNK_BYTES
+#define WS_CHUNK_BYTES (128u<<20)
+#endif
+#ifndef WS_CPB32
+#define WS_CPB32 1
+#endif
+#ifndef WS_CPB64
+#define WS_CPB64 1
+#endif
+#ifndef WS_EC32
+#define WS_EC32 16
+#endif
+#ifndef WS_EC64
+#define WS_EC64 16
+#endif
+#ifndef WS_ER32
+#define WS_ER32 16
+#endif
+#ifndef WS_ER64
+#define WS_ER64 8
+#endif
+#ifndef WS_MIN_BLOCK
+#define WS_MIN_BLOCK 64
+#endif
+#ifndef WS_RPB32
+#define WS_RPB32 2
+#endif
+#ifndef WS_RPB64
+#define WS_RPB64 2
+#endif
