@@ -323,7 +323,7 @@ def serve_summary(trace, infos, span, st0, st1):
 
 def run_serve_bench(torch, nreq, arena_gb):
     """Serving: one seeded Poisson trace replayed on the plain FP64 one-at-a-time engine and on the
-    batched FP32 + refinement engine (4 streams, batches of up to 16 applies)."""
+    batched FP32 + refinement engine (4 streams, batches of up to 16 applies, plans mixed per launch)."""
     from paper_2107_03958_amd import serve
     trace = make_trace(nreq)
     log(f"serve: building input pools for {nreq} requests ...")
@@ -360,9 +360,9 @@ def run_serve_bench(torch, nreq, arena_gb):
                calibration_service_ms=svc * 1e3, lambda_per_s=lam)
     outs = {}
     for name, prec, streams, mb in (("fp64_one_at_a_time", "fp64", 1, 1), ("fp32_batched", "fp32", 4, 16)):
-        eng = serve.Engine(prec, streams=streams, max_batch=mb, arena_bytes=arena)
+        eng = serve.Engine(prec, streams=streams, max_batch=mb, arena_bytes=arena, mix_plans=mb > 1)
         warm(eng)
-        res[name] = dict(config=dict(precision=prec, streams=streams, max_batch=mb))
+        res[name] = dict(config=dict(precision=prec, streams=streams, max_batch=mb, mix_plans=mb > 1))
         for mode, rate in (("poisson", lam), ("saturated", None)):
             st0 = eng.stats()
             infos, kept, span = replay(eng, inputs, trace, rate, keep if mode == "poisson" else None)

@@ -8,7 +8,9 @@
  * keeps `streams` device streams busy: whenever a stream's worker is free it
  * takes the next job (continuous batching), which is
  *   - an apply together with up to max_batch - 1 other pending applies that
- *     share its plan (kernel, n, precision), run as one conv_apply launch, or
+ *     share its plan (kernel, n, precision), run as one conv_apply launch
+ *     (with mix_plans, also applies of other grid sizes and kernels whose
+ *     plans are built, run as one conv_apply_multi launch), or
  *   - one LS solve, whose GMRES state stays on the device for the whole solve.
  * All device memory comes from one caller-owned arena: the built plans (kernel
  * moments and twiddles, cached and evicted least recently used first) and each
@@ -23,7 +25,8 @@
  * With precision WS_FP32 an apply runs in FP32 (twiddles as hi/lo pairs) and an
  * LS solve runs as FP32 GMRES with FP64 iterative refinement; with WS_FP64
  * both run in FP64.  Each result is the same whether its request ran alone or
- * batched with others (the kernels treat each density of a launch alike).
+ * batched with others: bitwise within one plan's launches, and to rounding
+ * (the same arithmetic in another kernel) when mix_plans joins plans.
  *
  * Calls that overlap on one engine are safe from several host threads.
  * Return codes are those of wsconv.h; conv_last_error() holds the message.
@@ -46,6 +49,8 @@ typedef struct {
     int max_batch;     /* applies sharing a plan merged into one launch, 1..1024 */
     int max_plans;     /* plans kept built in the arena, >= 1 */
     int max_skips;     /* times younger jobs may be admitted past the oldest blocked one, >= 0 */
+    int mix_plans;     /* 1: applies with different plans (all real-kernel, or all Helmholtz) whose
+                          plans are built share one conv_apply_multi launch; 0: same plan only */
 } ws_serve_config;
 
 typedef struct {

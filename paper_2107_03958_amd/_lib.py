@@ -46,7 +46,7 @@ WS_REQ_APPLY, WS_REQ_LS = 0, 1
 
 class WsServeConfig(ctypes.Structure):
     _fields_ = [("precision", c_int), ("streams", c_int), ("max_batch", c_int), ("max_plans", c_int),
-                ("max_skips", c_int)]
+                ("max_skips", c_int), ("mix_plans", c_int)]
 
 
 class WsRequest(ctypes.Structure):

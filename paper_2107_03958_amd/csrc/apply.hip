@@ -144,10 +144,17 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
     for (int reg = 0; reg < E; ++reg)
       x[reg] = (!GUARD || valid) ? src[p + P * slot_elem<E, R0>(reg)] : cx<T>{0, 0};
+    if constexpr (TwOf<T>::type::kPowers) {
+      cx<T> w[E];                                           // w_n^m, m = p + P s
+      if (l) tw_run<-1, E>(tw, 2 * p, 2 * P, w);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) {
-      const int m = p + P * slot_elem<E, R0>(reg);
-      v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
+      for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
+    } else {
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) {
+        const int m = p + P * slot_elem<E, R0>(reg);
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
+      }
     }
   }
   fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
@@ -156,9 +163,12 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   __syncthreads();
   if (GUARD && !valid) return;
   cx<T>* dst = sg.work + batch * (size_t)n * n;
-  for (int idx = tid; idx < RPB * n; idx += NT) {
-    const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
-    const int k = cb * CB + c;
+  // element idx = tid + it NT: the same (c, rr) on every iteration, k grows by NT / RPB
+  static_assert(NT % (CB * RPB) == 0 && (RPB * n) % NT == 0, "store loop shape");
+  constexpr int IT = RPB * n / NT, DK = NT / RPB;
+  const int c = tid % CB, rr = (tid / CB) % RPB, k0 = (tid / (CB * RPB)) * CB + c;
+  auto unpack = [&](int it, auto twiddle) {
+    const int k = k0 + it * DK, cb = (tid + it * NT) / (CB * RPB);
     const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
     cx<T> val;
     if (k == 0) {
@@ -168,10 +178,17 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
       const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
       const cx<T> a = cscale(zk + zm, (T)0.5);
       const cx<T> d = cscale(zk - zm, (T)0.5);
-      const cx<T> bdiff = {d.y, -d.x};              // -i d
-      val = a + tw.template mul<-1>(bdiff, k);      // + w_{2n}^k (-i d)
+      val = a + twiddle(cx<T>{d.y, -d.x}, k);        // + w_{2n}^k (-i d)
     }
     dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+  };
+  if constexpr (TwOf<T>::type::kPowers) {
+    cx<T> wk[IT];
+    tw_run<-1, IT>(tw, k0, DK, wk);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
+  } else {
+    for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int k) { return tw.template mul<-1>(x, k); });
   }
 }
 
@@ -212,10 +229,26 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
 #pragma unroll
     for (int reg = 0; reg < E; ++reg)
       x[reg] = (!GUARD || valid) ? col[(size_t)(p + P * slot_elem<E, R0>(reg)) * CB + c] : cx<T>{0, 0};
+    // the moments this thread multiplies by after the forward transform, loaded
+    // now so they arrive while it runs: row k1' = min(k1, 2n - k1) of the folded table
+    const G* gc = gtab + (size_t)cb * (n + 1) * CB + c;
+    G gk[E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) {
-      const int j = p + P * slot_elem<E, R0>(reg);
-      v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];   // odd frequencies: x w_{2n}^j
+      const int k1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
+      gk[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB] : G{};
+    }
+    if constexpr (TwOf<T>::type::kPowers) {
+      cx<T> w[E];                                          // w_{2n}^j, j = p + P s
+      if (l) tw_run<-1, E>(tw, p, P, w);
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
+    } else {
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) {
+        const int j = p + P * slot_elem<E, R0>(reg);
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];   // odd frequencies: x w_{2n}^j
+      }
     }
     fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
     // v[0][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
@@ -239,7 +272,7 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
             const int k1f = k1 <= n ? k1 : 2 * n - k1;
             const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
             const cx<T> ym = cconj(mine[LL::pad(partner)]);
-            const T g0 = (T)gtab[(size_t)k1f * CB];
+            const T g0 = (T)gk[reg];                 // column 0 of block-column 0: gtab[k1f * CB]
             const T gN = sg.gnyq[k1f];
             v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
           }
@@ -249,13 +282,10 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
       }
     }
     if (!done && (!GUARD || valid)) {
-      const G* gc = gtab + (size_t)cb * (n + 1) * CB + c;
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
-        const int k1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
-        const G g = gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB];
-        if constexpr (CPLX) v[0][reg] = cmul(v[0][reg], g);
-        else v[0][reg] = cscale(v[0][reg], g);
+        if constexpr (CPLX) v[0][reg] = cmul(v[0][reg], gk[reg]);
+        else v[0][reg] = cscale(v[0][reg], gk[reg]);
       }
     }
   } else {
@@ -280,10 +310,13 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
   if (GUARD && !valid) return;
   const cx<T>* l0 = lds + (2 * cc) * S;
   const cx<T>* l1 = l0 + S;
+  cx<T> w[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_{2n}^{-i}, i = p + P (l E/2 + t)
+  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, p + P * l * (E / 2), P, w);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int i = p + P * (l * (E / 2) + tt);
-    col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
+    if constexpr (TwOf<T>::type::kPowers) col[(size_t)i * CB + c] = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
+    else col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
   }
 }
 
@@ -319,6 +352,8 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   }
   __syncthreads();
   cx<T> v[1][E];
+  cx<T> wq[TwOf<T>::type::kPowers ? E : 1];                  // w_{2n}^{-k}, k = 2p + l + 2P s
+  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E>(tw, 2 * p + l, 2 * P, wq);
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) {
     const int q = p + P * slot_elem<E, R0>(reg);
@@ -330,7 +365,9 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
     } else {
       const cx<T> yk = mine[LL::pad(q)];
       const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
-      const cx<T> d = tw.template mul<+1>(yk - yk2, k);
+      cx<T> d;
+      if constexpr (TwOf<T>::type::kPowers) d = cmul(yk - yk2, wq[slot_elem<E, R0>(reg)]);
+      else d = tw.template mul<+1>(yk - yk2, k);
       z = (yk + yk2) + times_i(d);
     }
     v[0][reg] = z;
@@ -343,10 +380,14 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   if (GUARD && !valid) return;
   const int row = row0 + r;
   cx<T>* dst = reinterpret_cast<cx<T>*>(static_cast<T*>(sg.dst) + (batch * n + row) * n);
+  cx<T> wm[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_n^{-m}, m = p + P (l E/2 + t)
+  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, 2 * (p + P * l * (E / 2)), 2 * P, wm);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int m = p + P * (l * (E / 2) + tt);
-    cx<T> zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
+    cx<T> zz;
+    if constexpr (TwOf<T>::type::kPowers) zz = l0[LL::pad(m)] + cmul(l1[LL::pad(m)], wm[tt]);
+    else zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
     if constexpr (FS) {
       const T* utilde = static_cast<const T*>(sg.src);
       const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row) * n)[m];
@@ -387,10 +428,17 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
         if (!GUARD || valid) x[reg] = cscale(x[reg], sg.mcon[(size_t)row * n + j]);
       }
     }
+    if constexpr (TwOf<T>::type::kPowers) {
+      cx<T> w[E];                                          // w_{2n}^j, j = p + P s
+      if (l) tw_run<-1, E>(tw, p, P, w);
 #pragma unroll
-    for (int reg = 0; reg < E; ++reg) {
-      const int j = p + P * slot_elem<E, R0>(reg);
-      v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
+      for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
+    } else {
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) {
+        const int j = p + P * slot_elem<E, R0>(reg);
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
+      }
     }
   }
   fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
@@ -442,10 +490,14 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
   const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
   cx<T>* out = static_cast<cx<T>*>(sg.dst);
   const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
+  cx<T> w[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_{2n}^{-i}, i = p + P (l E/2 + t)
+  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, p + P * l * (E / 2), P, w);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int i = p + P * (l * (E / 2) + tt);
-    cx<T> y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
+    cx<T> y;
+    if constexpr (TwOf<T>::type::kPowers) y = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
+    else y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
     y = cscale(y, sg.alpha);
     if (sg.add) y = y + vin[roff + i];
     out[roff + i] = y;

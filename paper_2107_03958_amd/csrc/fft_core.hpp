@@ -71,6 +71,20 @@ struct TwF {
   }
 };
 
+// Twiddles of an arithmetic run of table indices, w[s] = w(SGN * (b + d s)),
+// s < K.  FP64 tables: two loads and K-1 products (the error grows by about
+// an ulp per step, far below the FP64 error of the transform).  FP32 tables:
+// one (hi, lo) pair per entry, read directly.
+template <int SGN, int K>
+__device__ __forceinline__ void tw_run(const TwD& tw, int b, int d, cx<double> (&w)[K]) {
+  w[0] = tw.template get<SGN>(b);
+  if constexpr (K > 1) {
+    const cx<double> step = tw.template get<SGN>(d);
+#pragma unroll
+    for (int s = 1; s < K; ++s) w[s] = cmul(w[s - 1], step);
+  }
+}
+
 template <typename T> struct TwOf;
 template <> struct TwOf<double> { using type = TwD; };
 template <> struct TwOf<float> { using type = TwF; };
@@ -216,9 +230,35 @@ struct LineLayout {
   }
 };
 
-// Butterflies of one stage on every line a thread holds.
+// FP64 tables: the base twiddle of every butterfly of every stage of a line,
+// loaded before the first stage so the loads overlap the first stages' work.
+template <int L, int E, int NS>
+constexpr int stage_bases() {
+  if constexpr (NS >= L) {
+    return 0;
+  } else {
+    constexpr int R = Radix<L, E, NS>::R;
+    return (NS > 1 ? E / R : 0) + stage_bases<L, E, NS * R>();
+  }
+}
+
+template <int L, int E, int SGN, int NS, typename T, typename TW>
+__device__ __forceinline__ void load_bases(cx<T>* wb, int p, const TW& tw, int twstep) {
+  if constexpr (NS < L) {
+    constexpr int R = Radix<L, E, NS>::R, P = L / E;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int q = 0; q < E / R; ++q) wb[q] = tw.template get<SGN>(((p + q * P) % NS) * ((L / (NS * R)) * twstep));
+    }
+    load_bases<L, E, SGN, NS * R>(wb + (NS > 1 ? E / R : 0), p, tw, twstep);
+  }
+}
+
+// Butterflies of one stage on every line a thread holds.  wb: the stage's
+// preloaded base twiddles (FP64 tables), else null.
 template <int L, int E, int NL, int R, int NS, int SGN, typename T, typename TW>
-__device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW& tw, int twstep) {
+__device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW& tw, int twstep,
+                                              const cx<T>* wb) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
@@ -227,7 +267,7 @@ __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW
       const int jm = j % NS;
       const int unit = (L / (NS * R)) * twstep;   // w_{NS R} in table units
       if constexpr (TW::kPowers) {
-        const cx<T> w1 = tw.template get<SGN>(jm * unit);
+        const cx<T> w1 = wb[q];
         cx<T> wr = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -286,13 +326,13 @@ __device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], cx<T>* const* lds, i
 
 template <int L, int E, int NL, int SGN, int NS, typename T, typename TW>
 __device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,
-                                           int twstep) {
+                                           int twstep, const cx<T>* wb) {
   constexpr int R = Radix<L, E, NS>::R;
-  stage_compute<L, E, NL, R, NS, SGN>(v, p, tw, twstep);
+  stage_compute<L, E, NL, R, NS, SGN>(v, p, tw, twstep, wb);
   if constexpr (NS * R < L) {
     constexpr int R2 = Radix<L, E, NS * R>::R;
     exchange<L, E, NL, R, NS, R2>(v, lds, p);
-    run_stages<L, E, NL, SGN, NS * R>(v, lds, p, tw, twstep);
+    run_stages<L, E, NL, SGN, NS * R>(v, lds, p, tw, twstep, wb + (NS > 1 ? E / R : 0));
   }
 }
 
@@ -303,7 +343,14 @@ __device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], cx<T>* const* lds,
 template <int L, int E, int NL, int SGN, typename T, typename TW>
 __device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,
                                           int twstep) {
-  run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep);
+  if constexpr (TW::kPowers) {
+    constexpr int NB = stage_bases<L, E, 1>();
+    cx<T> wb[NB > 0 ? NB : 1];
+    load_bases<L, E, SGN, 1>(wb, p, tw, twstep);
+    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, wb);
+  } else {
+    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, static_cast<const cx<T>*>(nullptr));
+  }
 }
 
 // Re-order registers from the last-stage layout (radix RA) to the first-stage

@@ -57,7 +57,7 @@ struct Engine {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   Engine(const ws_serve_config& c, size_t bytes)
-      : cfg(c), adm(bytes, c.max_batch, c.max_plans, c.max_skips) {}
+      : cfg(c), adm(bytes, c.max_batch, c.max_plans, c.max_skips, c.mix_plans != 0) {}
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -70,6 +70,7 @@ int check_config(const ws_serve_config* c) {
   if (c->max_batch < 1 || c->max_batch > 1024) return ws::set_last_error(WS_EINVAL, "max_batch must lie in [1, 1024]");
   if (c->max_plans < 1) return ws::set_last_error(WS_EINVAL, "max_plans must be >= 1");
   if (c->max_skips < 0) return ws::set_last_error(WS_EINVAL, "max_skips must be >= 0");
+  if (c->mix_plans != 0 && c->mix_plans != 1) return ws::set_last_error(WS_EINVAL, "mix_plans must be 0 or 1");
   return WS_OK;
 }
 
@@ -92,6 +93,7 @@ int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
   q.key.n = r->n;
   q.key.precision = cfg.precision;
   q.plan_bytes = plan_bytes;
+  q.batch_class = cplx ? 1 : 0;
   if (r->kind == WS_REQ_APPLY) {
     if (!r->input || !r->output) return ws::set_last_error(WS_EINVAL, "apply request needs input and output");
     const size_t e64 = cplx ? 16 : 8;
@@ -129,14 +131,13 @@ void convert(hipStream_t s, const float* a, double* b, size_t count) {
   k_widen<<<(unsigned)(blocks < kConvBlocks ? (blocks ? blocks : 1) : kConvBlocks), kConvThreads, 0, s>>>(a, b, count);
 }
 
-// Run one admitted job on stream s.  Returns WS_OK (per-request LS statuses in
-// ls[]) or a negative code with *err set.
-int run_job(Engine* E, const ws::Grant& g, const std::vector<ws_request>& rq, ws_plan_t plan, hipStream_t s,
-            std::vector<ws_ls_info>* ls, std::vector<int>* status, std::string* err) {
+// Run one admitted job on stream s.  Apply jobs: the densities of each plan
+// lie together ([in64 of every request][x32 (FP32)][scratch per plan]), and
+// one plan runs through conv_apply, several through conv_apply_multi.  Returns
+// WS_OK (per-request LS statuses in ls[]) or a negative code with *err set.
+int run_job(Engine* E, const ws::Grant& g, const std::vector<ws_request>& rq, const std::vector<ws_plan_t>& plans,
+            hipStream_t s, std::vector<ws_ls_info>* ls, std::vector<int>* status, std::string* err) {
   const ws_request& r0 = rq[0];
-  const int n = r0.n;
-  const size_t nn = (size_t)n * n;
-  const bool cplx = r0.kernel.family == WS_HELMHOLTZ;
   const bool fp32 = E->cfg.precision == WS_FP32;
   char* buf = E->base + g.buf_off;
   hipError_t e = hipSuccess;
@@ -145,35 +146,70 @@ int run_job(Engine* E, const ws::Grant& g, const std::vector<ws_request>& rq, ws
     return WS_EDEVICE;
   };
   if (g.reqs[0].kind == 0) {
-    const int B = (int)rq.size();
-    const size_t e64 = cplx ? 16 : 8, bytes64 = nn * e64;
-    char* in64 = buf;
-    char* x32 = buf + B * bytes64;
-    char* scratch = buf + B * (bytes64 + (fp32 ? bytes64 / 2 : 0));
-    for (int i = 0; i < B && e == hipSuccess; ++i)
-      e = hipMemcpyAsync(in64 + i * bytes64, rq[i].input, bytes64, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_err("serve: copy in");
-    int rc;
-    if (fp32) {
-      const size_t reals = (size_t)B * nn * (cplx ? 2 : 1);
-      convert(s, reinterpret_cast<const double*>(in64), reinterpret_cast<float*>(x32), reals);
-      rc = conv_apply(plan, B, x32, x32, scratch, nullptr, s);
-      if (rc == WS_OK) convert(s, reinterpret_cast<const float*>(x32), reinterpret_cast<double*>(in64), reals);
-    } else {
-      rc = conv_apply(plan, B, in64, in64, scratch, nullptr, s);
+    const int B = (int)rq.size(), K = (int)g.keys.size();
+    const bool cplx = r0.kernel.family == WS_HELMHOLTZ;
+    // requests grouped by plan, in the order of g.keys
+    std::vector<int> plan_of(B), order;
+    for (int i = 0; i < B; ++i)
+      for (int k = 0; k < K; ++k)
+        if (g.reqs[i].key == g.keys[k]) plan_of[i] = k;
+    for (int k = 0; k < K; ++k)
+      for (int i = 0; i < B; ++i)
+        if (plan_of[i] == k) order.push_back(i);
+    auto bytes64 = [&](int i) { return (size_t)rq[i].n * rq[i].n * (cplx ? 16 : 8); };
+    std::vector<size_t> off64(B), off32(B);
+    size_t total64 = 0, total32 = 0;
+    for (int i : order) {
+      off64[i] = total64;
+      off32[i] = total32;
+      total64 += bytes64(i);
+      total32 += bytes64(i) / 2;
     }
+    char* in64 = buf;
+    char* x32 = buf + total64;
+    char* scratch = x32 + (fp32 ? total32 : 0);
+    for (int i = 0; i < B && e == hipSuccess; ++i)
+      e = hipMemcpyAsync(in64 + off64[i], rq[i].input, bytes64(i), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err("serve: copy in");
+    const size_t reals = total64 / 8;
+    char* data = fp32 ? x32 : in64;
+    if (fp32) convert(s, reinterpret_cast<const double*>(in64), reinterpret_cast<float*>(x32), reals);
+    // per plan: first density, count, scratch
+    std::vector<int> cnt(K, 0), first(K, -1);
+    for (int i : order) {
+      if (first[plan_of[i]] < 0) first[plan_of[i]] = i;
+      cnt[plan_of[i]]++;
+    }
+    std::vector<const void*> dens(K);
+    std::vector<void*> outs(K), works(K);
+    size_t soff = 0;
+    for (int k = 0; k < K; ++k) {
+      const size_t off = fp32 ? off32[first[k]] : off64[first[k]];
+      dens[k] = data + off;
+      outs[k] = data + off;
+      works[k] = scratch + soff;
+      const ws::Pending& q = g.reqs[first[k]];
+      soff += std::min<size_t>(cnt[k], (size_t)std::max(1, q.chunk)) * q.scratch_each;
+    }
+    int rc;
+    if (K == 1) rc = conv_apply(plans[0], cnt[0], dens[0], outs[0], works[0], nullptr, s);
+    else rc = conv_apply_multi(K, plans.data(), cnt.data(), dens.data(), outs.data(), works.data(), s);
     if (rc != WS_OK) {
       *err = conv_last_error();
       return rc;
     }
+    if (fp32) convert(s, reinterpret_cast<const float*>(x32), reinterpret_cast<double*>(in64), reals);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err("serve: conversion kernels");
     for (int i = 0; i < B && e == hipSuccess; ++i)
-      e = hipMemcpyAsync(rq[i].output, in64 + i * bytes64, bytes64, hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(rq[i].output, in64 + off64[i], bytes64(i), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_err("serve: copy out");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err("serve: apply");
     status->assign(B, WS_OK);
     return WS_OK;
   }
+  const ws_plan_t plan = plans[0];
+  const int n = r0.n;
+  const size_t nn = (size_t)n * n;
   const ws_request& r = r0;
   char* m = buf;
   char* uinc = m + align256(nn * 8);
@@ -220,6 +256,8 @@ void worker(Engine* E, int w) {
       rq.push_back(en.req);
     }
     ws_plan_t plan = static_cast<ws_plan_t>(E->adm.plan_handle(g.key));
+    std::vector<ws_plan_t> plans;
+    for (const ws::PlanKey& k : g.keys) plans.push_back(static_cast<ws_plan_t>(E->adm.plan_handle(k)));
     lk.unlock();
 
     std::string err;
@@ -242,12 +280,13 @@ void worker(Engine* E, int w) {
       E->builds++;
       if (rc == WS_OK) E->adm.plan_ready(g.key, plan);
       else E->adm.plan_failed(g.key);
+      plans[0] = plan;
       E->cv_work.notify_all();
       lk.unlock();
     }
     std::vector<ws_ls_info> ls;
     std::vector<int> status;
-    if (rc == WS_OK) rc = run_job(E, g, rq, plan, s, &ls, &status, &err);
+    if (rc == WS_OK) rc = run_job(E, g, rq, plans, s, &ls, &status, &err);
     // After a failure part of the job may still be queued: let it drain before
     // its arena block is handed to another job.
     if (rc < 0) (void)hipStreamSynchronize(s);

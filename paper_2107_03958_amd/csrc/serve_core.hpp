@@ -104,6 +104,7 @@ struct Pending {
   int chunk = 1;             // apply: densities a launch takes through the passes at a time
   size_t plan_bytes = 0;     // device bytes of its plan
   int skipped = 0;           // times a younger request was admitted ahead of it
+  int batch_class = 0;       // applies of one class may share a launch across plans
   double t_submit = 0;
 };
 
@@ -118,7 +119,8 @@ struct PlanSlot {
 // A job: requests that run together on one stream, sharing one plan.
 struct Grant {
   std::vector<Pending> reqs;
-  PlanKey key;
+  PlanKey key;               // the first request's plan (the one built when build_plan)
+  std::vector<PlanKey> keys; // every plan the job holds, key first
   bool build_plan = false;   // the worker must build the plan into plan_off first
   size_t plan_off = 0, plan_bytes = 0;
   size_t buf_off = 0, buf_bytes = 0;   // one block: per-request buffers, then scratch
@@ -128,16 +130,17 @@ struct Grant {
 // Admission: whenever a worker is free it asks for the next job.  Requests
 // are considered oldest first; an apply takes along up to max_batch - 1 younger
 // pending applies with the same plan (continuous batching: work that arrives
-// while the device is busy joins the next launch).  A job is admitted only if
+// while the device is busy joins the next launch) and, with mix_plans, also
+// applies of the same class whose plans are built (one multi-plan launch).  A job is admitted only if
 // its plan (unless cached) and its buffers fit in the arena, after evicting
 // idle cached plans least recently used first; otherwise younger requests may
 // go ahead, but only max_skips times in a row past the oldest one.  A request
 // whose plan is being built waits until it is ready.
 class Admission {
  public:
-  Admission(size_t arena_bytes, int max_batch, int max_plans, int max_skips)
+  Admission(size_t arena_bytes, int max_batch, int max_plans, int max_skips, bool mix_plans = false)
       : arena_(arena_bytes), max_batch_(std::max(1, max_batch)), max_plans_(std::max(1, max_plans)),
-        max_skips_(std::max(0, max_skips)) {}
+        max_skips_(std::max(0, max_skips)), mix_plans_(mix_plans) {}
 
   // Largest footprint a single request may have (plan + buffers + scratch).
   static size_t request_bytes(const Pending& p) {
@@ -160,8 +163,17 @@ class Admission {
       if (ps != plans_.end() && !ps->second.ready) continue;        // being built by another job
       std::vector<size_t> group{i};
       if (c.kind == 0) {
-        for (size_t j = i + 1; j < pending_.size() && (int)group.size() < max_batch_; ++j)
-          if (pending_[j].kind == 0 && pending_[j].key == c.key) group.push_back(j);
+        const bool c_ready = ps != plans_.end() && ps->second.ready;
+        for (size_t j = i + 1; j < pending_.size() && (int)group.size() < max_batch_; ++j) {
+          const Pending& q = pending_[j];
+          if (q.kind != 0) continue;
+          if (q.key == c.key) {
+            group.push_back(j);
+          } else if (mix_plans_ && c_ready && q.batch_class == c.batch_class) {
+            auto pq = plans_.find(q.key);
+            if (pq != plans_.end() && pq->second.ready) group.push_back(j);
+          }
+        }
       }
       while (!group.empty()) {
         if (try_admit(group, g)) {
@@ -198,8 +210,10 @@ class Admission {
 
   void finish(const Grant& g) {
     arena_.release(g.buf_off, g.buf_bytes);
-    auto it = plans_.find(g.key);
-    if (it != plans_.end()) it->second.refs--;
+    for (const PlanKey& k : g.keys) {
+      auto it = plans_.find(k);
+      if (it != plans_.end()) it->second.refs--;
+    }
   }
 
   // Idle plans to destroy at shutdown (all of them once no job runs).
@@ -220,11 +234,30 @@ class Admission {
  private:
   bool try_admit(const std::vector<size_t>& group, Grant* g) {
     const Pending& c = pending_[group[0]];
+    // distinct plans of the group (c's first) and the requests of each
+    std::vector<PlanKey> keys;
+    std::vector<size_t> count;
+    std::vector<const Pending*> first;
     size_t own = 0;
-    for (size_t idx : group) own += pending_[idx].own_bytes;
-    const size_t b = group.size();
-    const size_t scratch = c.kind == 0 ? std::min<size_t>(b, (size_t)std::max(1, c.chunk)) * c.scratch_each
-                                       : c.scratch_each;
+    for (size_t idx : group) {
+      const Pending& q = pending_[idx];
+      own += q.own_bytes;
+      size_t k = 0;
+      while (k < keys.size() && !(keys[k] == q.key)) ++k;
+      if (k == keys.size()) {
+        keys.push_back(q.key);
+        count.push_back(0);
+        first.push_back(&q);
+      }
+      count[k]++;
+    }
+    size_t scratch = 0;
+    if (c.kind == 0) {
+      for (size_t k = 0; k < keys.size(); ++k)
+        scratch += std::min<size_t>(count[k], (size_t)std::max(1, first[k]->chunk)) * first[k]->scratch_each;
+    } else {
+      scratch = c.scratch_each;
+    }
     const size_t buf = own + scratch;
     std::vector<void*> evicted;
     auto ps = plans_.find(c.key);
@@ -239,7 +272,7 @@ class Admission {
       if (buf_off != Arena::npos) arena_.release(buf_off, buf), buf_off = Arena::npos;
       if (plan_off != Arena::npos) arena_.release(plan_off, c.plan_bytes), plan_off = Arena::npos;
       void* h = nullptr;
-      if (!evict_one(c.key, &h)) {
+      if (!evict_one(keys, &h)) {
         // could not make room: the evictions already done stay done (their
         // plans were idle); hand their handles back for destruction
         g->evicted.insert(g->evicted.end(), evicted.begin(), evicted.end());
@@ -250,6 +283,7 @@ class Admission {
     g->reqs.clear();
     for (size_t idx : group) g->reqs.push_back(pending_[idx]);
     g->key = c.key;
+    g->keys = keys;
     g->build_plan = need_plan;
     if (need_plan) {
       PlanSlot s;
@@ -258,8 +292,11 @@ class Admission {
       plans_[c.key] = s;
       ps = plans_.find(c.key);
     }
-    ps->second.refs++;
-    ps->second.last_use = ++clock_;
+    for (const PlanKey& k : keys) {
+      auto it = plans_.find(k);
+      it->second.refs++;
+      it->second.last_use = ++clock_;
+    }
     g->plan_off = ps->second.off;
     g->plan_bytes = ps->second.bytes;
     g->buf_off = buf_off;
@@ -268,10 +305,11 @@ class Admission {
     return true;
   }
 
-  bool evict_one(const PlanKey& keep, void** handle) {
+  bool evict_one(const std::vector<PlanKey>& keep, void** handle) {
     auto victim = plans_.end();
     for (auto it = plans_.begin(); it != plans_.end(); ++it) {
-      if (it->second.refs > 0 || !it->second.ready || it->first == keep) continue;
+      if (it->second.refs > 0 || !it->second.ready) continue;
+      if (std::find(keep.begin(), keep.end(), it->first) != keep.end()) continue;
       if (victim == plans_.end() || it->second.last_use < victim->second.last_use) victim = it;
     }
     if (victim == plans_.end()) return false;
@@ -286,6 +324,7 @@ class Admission {
   std::deque<Pending> pending_;
   std::map<PlanKey, PlanSlot> plans_;
   int max_batch_, max_plans_, max_skips_;
+  bool mix_plans_;
   uint64_t clock_ = 0, evictions_ = 0;
 };
 

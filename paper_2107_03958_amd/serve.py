@@ -38,12 +38,14 @@ def _host(t: torch.Tensor, dtype: torch.dtype, n: int, what: str) -> torch.Tenso
 
 class Engine:
     def __init__(self, precision: str = "fp64", streams: int = 1, max_batch: int = 1, max_plans: int = 32,
-                 max_skips: int = 8, arena_bytes: int = 4 << 30, device="cuda:0", pin_outputs: bool = True):
+                 max_skips: int = 8, arena_bytes: int = 4 << 30, device="cuda:0", pin_outputs: bool = True,
+                 mix_plans: bool = False):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.cfg = L.WsServeConfig(PRECISIONS[precision], streams, max_batch, max_plans, max_skips)
+        self.cfg = L.WsServeConfig(PRECISIONS[precision], streams, max_batch, max_plans, max_skips,
+                                   1 if mix_plans else 0)
         self.precision = precision
         self.pin_outputs = pin_outputs
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)

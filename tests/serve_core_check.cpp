@@ -177,11 +177,61 @@ static void batch_shrinks() {
   CHECK(adm.pending() == 6);
 }
 
+// With mix_plans, applies of one class whose plans are built share a job;
+// a plan not yet built still gets a job of its own (which builds it), and
+// the job's plans are not evicted while it runs.
+static void mixed_plans() {
+  Admission adm((size_t)1 << 30, 8, 8, 4, true);
+  Pending a = apply_req(1, 64, 0), b = apply_req(2, 128, 1), cx = apply_req(3, 64, 2);
+  cx.batch_class = 1;   // complex: never mixed with the real ones
+  adm.push(a);
+  Grant g0;
+  CHECK(adm.next(&g0) && g0.build_plan && g0.keys.size() == 1);
+  adm.plan_ready(g0.key, (void*)0x1);
+  adm.finish(g0);
+  adm.push(b);
+  Grant g1;
+  CHECK(adm.next(&g1) && g1.build_plan);
+  adm.plan_ready(g1.key, (void*)0x2);
+  adm.finish(g1);
+  // both plans built: a batch of (a, b, a) plus a complex apply
+  adm.push(apply_req(4, 64, 0));
+  adm.push(apply_req(5, 128, 1));
+  adm.push(cx);
+  adm.push(apply_req(6, 64, 0));
+  Grant g2;
+  CHECK(adm.next(&g2));
+  CHECK(g2.reqs.size() == 3 && g2.keys.size() == 2 && !g2.build_plan);
+  CHECK(g2.reqs[0].ticket == 4 && g2.reqs[1].ticket == 5 && g2.reqs[2].ticket == 6);
+  // scratch: one chunk per plan, own buffers for every request
+  const size_t own = 2 * apply_req(0, 64).own_bytes + apply_req(0, 128).own_bytes;
+  const size_t scr = 2 * apply_req(0, 64).scratch_each + apply_req(0, 128).scratch_each;
+  CHECK(g2.buf_bytes == own + scr);
+  Grant g3;
+  CHECK(adm.next(&g3) && g3.reqs.size() == 1 && g3.reqs[0].ticket == 3 && g3.build_plan);
+  adm.plan_ready(g3.key, (void*)0x3);
+  adm.finish(g2);
+  adm.finish(g3);
+  CHECK(adm.empty());
+  // a request whose plan is not built does not join a mixed job
+  adm.push(apply_req(7, 64, 0));
+  adm.push(apply_req(8, 256, 5));
+  Grant g4, g5;
+  CHECK(adm.next(&g4) && g4.reqs.size() == 1 && g4.reqs[0].ticket == 7);
+  CHECK(adm.next(&g5) && g5.reqs.size() == 1 && g5.reqs[0].ticket == 8 && g5.build_plan);
+  adm.finish(g4);
+  adm.plan_ready(g5.key, (void*)0x4);
+  adm.finish(g5);
+  (void)adm.drain_plans();
+  CHECK(adm.arena().used() == 0);
+}
+
 int main() {
   for (unsigned s = 1; s <= 5; ++s) arena_random(s);
   batching();
   admission();
   batch_shrinks();
+  mixed_plans();
   std::printf("serve_core checks passed\n");
   return 0;
 }

@@ -165,3 +165,24 @@ def test_admission_tight_arena_and_eviction(serve):
     for (out, _), k, u in zip(outs[3:], kn, us):
         ref = np.real(scheme.apply(u, oracle_table(k, 32), B))
         assert metrics.rel_linf(out.numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixed_plan_launches(serve, precision):
+    # With mix_plans, applies of different sizes and kernels share launches
+    # (conv_apply_multi).  Each result equals the request served alone to
+    # rounding: the same arithmetic, compiled into another kernel.
+    reqs = [r for r in _mix_requests() if r[0] == "apply"]
+    eng = serve.Engine(precision, streams=2, max_batch=8, arena_bytes=2 << 30, mix_plans=True)
+    # build every plan first, so the mixed batches below can form
+    _run(eng, [reqs[i] for i in range(0, len(reqs), 3)], together=False)
+    got = _run(eng, reqs, together=True)
+    eng.close()
+    alone_eng = serve.Engine(precision, streams=1, max_batch=1, arena_bytes=2 << 30)
+    alone = _run(alone_eng, reqs, together=False)
+    alone_eng.close()
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    for (a, ia), (b, _), r in zip(got, alone, reqs):
+        assert ia["status"] == 0
+        assert metrics.rel_linf(a, b) <= tol, r[:3]
+    assert max(info["batch"] for _, info in got) > 3       # launches mixed several plans
