@@ -188,7 +188,21 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
     for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
   } else {
-    for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int k) { return tw.template mul<-1>(x, k); });
+    for (int idx = tid; idx < RPB * n; idx += NT) {
+      const int cb = idx / (CB * RPB), k = cb * CB + c;
+      const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+      cx<T> val;
+      if (k == 0) {
+        val = {zk.x + zk.y, zk.x - zk.y};
+      } else {
+        const int kk = n - k;
+        const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
+        const cx<T> a = cscale(zk + zm, (T)0.5);
+        const cx<T> d = cscale(zk - zm, (T)0.5);
+        val = a + tw.template mul<-1>(cx<T>{d.y, -d.x}, k);
+      }
+      dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+    }
   }
 }
 
