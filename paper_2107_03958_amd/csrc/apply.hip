@@ -136,17 +136,35 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   cx<T>* line[1] = {mine};
   const size_t batch = t / TPD;
   const int row0 = (t % TPD) * RPB;
+  using TW = typename TwOf<T>::type;
+  constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
+  // element idx = tid + it NT of the unpack: the same (c, rr) on every iteration, k grows by NT / RPB
+  static_assert(NT % (CB * RPB) == 0 && (RPB * n) % NT == 0, "store loop shape");
+  constexpr int IT = RPB * n / NT, DK = NT / RPB;
+  const int c = tid % CB, rr = (tid / CB) % RPB, k0 = (tid / (CB * RPB)) * CB + c;
+  // FP64: every twiddle load of the tile first (pre-twiddle run w_n^{p + P s},
+  // stage bases, unpack run w_{2n}^{k0 + DK it}), so that no later wait is
+  // ordered behind the row loads
+  cx<T> wpre{}, wpstep{}, wu{}, wustep{}, wb[NB > 0 ? NB : 1];
+  if constexpr (TW::kPowers) {
+    if (l) {
+      wpre = tw.template get<-1>(2 * p);
+      wpstep = tw.template get<-1>(2 * P);
+    }
+    load_bases<L, E, -1, 1>(wb, p, tw, 2 * n / L);
+    wu = tw.template get<-1>(k0);
+    wustep = tw.template get<-1>(DK);
+  }
   cx<T> v[1][E];
   {
-    // all loads first (they overlap in flight), then the twiddles of the odd half
     const cx<T>* src = reinterpret_cast<const cx<T>*>(static_cast<const T*>(sg.src) + (batch * n + row0 + r) * n);
     cx<T> x[E];
 #pragma unroll
     for (int reg = 0; reg < E; ++reg)
       x[reg] = (!GUARD || valid) ? src[p + P * slot_elem<E, R0>(reg)] : cx<T>{0, 0};
-    if constexpr (TwOf<T>::type::kPowers) {
+    if constexpr (TW::kPowers) {
       cx<T> w[E];                                           // w_n^m, m = p + P s
-      if (l) tw_run<-1, E>(tw, 2 * p, 2 * P, w);
+      if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
     } else {
@@ -157,16 +175,12 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
       }
     }
   }
-  fft_lines<L, E, 1, -1>(v, line, p, tw, 2 * n / L);
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2 * n / L, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
   cx<T>* dst = sg.work + batch * (size_t)n * n;
-  // element idx = tid + it NT: the same (c, rr) on every iteration, k grows by NT / RPB
-  static_assert(NT % (CB * RPB) == 0 && (RPB * n) % NT == 0, "store loop shape");
-  constexpr int IT = RPB * n / NT, DK = NT / RPB;
-  const int c = tid % CB, rr = (tid / CB) % RPB, k0 = (tid / (CB * RPB)) * CB + c;
   auto unpack = [&](int it, auto twiddle) {
     const int k = k0 + it * DK, cb = (tid + it * NT) / (CB * RPB);
     const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
@@ -182,9 +196,9 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
     }
     dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
   };
-  if constexpr (TwOf<T>::type::kPowers) {
+  if constexpr (TW::kPowers) {
     cx<T> wk[IT];
-    tw_run<-1, IT>(tw, k0, DK, wk);
+    run_from<IT>(wu, wustep, wk);
 #pragma unroll
     for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
   } else {
@@ -216,45 +230,100 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 // (Fourier smoothing pre-pass).  A tile holds CPB columns of one density.
 // dc_block: the block holds the tile of block-column 0 (packed DC/Nyquist
 // column of the real path), whose extra exchange every thread of the block joins.
-template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD>
-__device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
-                                          bool dc_block) {
+//
+// The tile's global loads are issued in the order their data is needed:
+// column data, twiddles, moments.
+template <typename T, int LOGN, bool CPLX>
+struct ColGeo {
+  using C = Cfg<T, LOGN>;
+  static constexpr int n = C::n, P = C::PF, CB = C::CB, CPB = C::CPB;
+  static constexpr int NCOLS = CPLX ? 2 * n : n, NCT = NCOLS / CPB, GC = CB / CPB;
+  int cc, p, l, cb, csub, c;
+  size_t batch;
+  __device__ __forceinline__ ColGeo(int t, int tid) {
+    col_thread<CPB, P>(tid, cc, p, l);
+    const int ct = t % NCT;
+    batch = t / NCT;
+    cb = ct / GC;
+    csub = ct % GC;
+    c = csub * CPB + cc;                                 // column within the block-column cb
+  }
+  __device__ __forceinline__ cx<T>* col(cx<T>* work) const {
+    return work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
+  }
+};
+
+// Column data of tile t: slot reg holds row p + P slot_elem<E,R0>(reg).
+template <typename T, int LOGN, bool CPLX, bool GUARD>
+__device__ __forceinline__ void cols_load_data(const Seg<T>& sg, int t, bool valid, int tid,
+                                               cx<T> (&x)[Cfg<T, LOGN>::EF]) {
+  using C = Cfg<T, LOGN>;
+  constexpr int E = C::EF, P = C::PF, CB = C::CB, R0 = FirstLast<C::LF, E>::R0;
+  const ColGeo<T, LOGN, CPLX> g(t, tid);
+  const cx<T>* col = g.col(sg.work);
+#pragma unroll
+  for (int reg = 0; reg < E; ++reg)
+    x[reg] = (!GUARD || valid) ? col[(size_t)(g.p + P * slot_elem<E, R0>(reg)) * CB + g.c] : cx<T>{0, 0};
+}
+
+// Moments tile t multiplies by after its forward transform: slot reg is
+// frequency k1 = 2q + l, q = p + P slot_elem<E,RL>(reg), read from row
+// k1' = min(k1, 2n - k1) of the folded table.
+template <typename T, typename G, int LOGN, bool CPLX, bool GUARD>
+__device__ __forceinline__ void cols_load_moments(const Seg<T>& sg, int t, bool valid, int tid,
+                                                  G (&gk)[Cfg<T, LOGN>::EF]) {
+  using C = Cfg<T, LOGN>;
+  constexpr int n = C::n, E = C::EF, P = C::PF, CB = C::CB, RL = FirstLast<C::LF, E>::RL;
+  const ColGeo<T, LOGN, CPLX> g(t, tid);
+  const G* gc = static_cast<const G*>(sg.gtab) + (size_t)g.cb * (n + 1) * CB + g.c;
+#pragma unroll
+  for (int reg = 0; reg < E; ++reg) {
+    const int k1 = 2 * (g.p + P * slot_elem<E, RL>(reg)) + g.l;
+    gk[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB] : G{};
+  }
+}
+
+// Everything of tile t after its column data has been loaded.  Global loads
+// retire in order (a wait for one waits for every load issued before it), so
+// the twiddles (FP64: run seeds and stage bases) are loaded before the
+// moments (load_g fills gk): the pre-twiddle and the first stages then do not
+// wait for the moments.
+template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, typename LG>
+__device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
+                                             bool dc_block, const cx<T> (&x)[Cfg<T, LOGN>::EF],
+                                             G (&gk)[Cfg<T, LOGN>::EF], LG load_g) {
   using C = Cfg<T, LOGN>;
   using LL = LineLayout<C::LF, C::EF>;
-  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB, CPB = C::CPB;
+  using TW = typename TwOf<T>::type;
+  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
-  constexpr int NCOLS = CPLX ? 2 * n : n, NCT = NCOLS / CPB, GC = CB / CPB;
-  int cc, p, l;
-  col_thread<CPB, P>(tid, cc, p, l);
-  const int ct = t % NCT;
-  const size_t batch = t / NCT;
-  const int cb = ct / GC, csub = ct % GC;
-  const int c = csub * CPB + cc;                       // column within the block-column cb
-  const auto tw = sg.tw;
-  cx<T>* col = sg.work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
+  constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
+  const ColGeo<T, LOGN, CPLX> g(t, tid);
+  const int cc = g.cc, p = g.p, l = g.l, cb = g.cb, csub = g.csub, c = g.c;
+  const TW tw = sg.tw;
+  cx<T>* col = g.col(sg.work);
   cx<T>* mine = lds + (2 * cc + l) * S;
   cx<T>* line[1] = {mine};
   cx<T> v[1][E];
   const int k2 = cb * CB + c;                          // FFT bin of this column
 
+  // FP64 twiddles of the tile: w_{2n}^{p} and w_{2n}^{P} seed the odd line's
+  // pre-twiddle run w_{2n}^{p + P s}; w_{2n}^{-(p + P l E/2)} and the conjugate
+  // step seed the combine's run; the forward stage bases, conjugated, are the
+  // inverse transform's.
+  cx<T> wstep{}, wpre{}, wcomb{};
+  cx<T> wb[NB > 0 ? NB : 1], wbi[NB > 0 ? NB : 1];
+  if constexpr (TW::kPowers) {
+    wstep = tw.template get<-1>(P);
+    if (l) wpre = tw.template get<-1>(p);
+    wcomb = tw.template get<+1>(p + P * l * (E / 2));
+    load_bases<L, E, -1, 1>(wb, p, tw, 2);
+  }
   if constexpr (!GEN) {
-    const G* gtab = static_cast<const G*>(sg.gtab);
-    cx<T> x[E];
-#pragma unroll
-    for (int reg = 0; reg < E; ++reg)
-      x[reg] = (!GUARD || valid) ? col[(size_t)(p + P * slot_elem<E, R0>(reg)) * CB + c] : cx<T>{0, 0};
-    // the moments this thread multiplies by after the forward transform, loaded
-    // now so they arrive while it runs: row k1' = min(k1, 2n - k1) of the folded table
-    const G* gc = gtab + (size_t)cb * (n + 1) * CB + c;
-    G gk[E];
-#pragma unroll
-    for (int reg = 0; reg < E; ++reg) {
-      const int k1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
-      gk[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB] : G{};
-    }
-    if constexpr (TwOf<T>::type::kPowers) {
+    load_g();
+    if constexpr (TW::kPowers) {
       cx<T> w[E];                                          // w_{2n}^j, j = p + P s
-      if (l) tw_run<-1, E>(tw, p, P, w);
+      if (l) run_from<E>(wpre, wstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
     } else {
@@ -264,7 +333,7 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
         v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];   // odd frequencies: x w_{2n}^j
       }
     }
-    fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
+    run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
     // v[0][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {
@@ -317,21 +386,37 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
     }
   }
   relayout<E, RL, R0>(v);
-  fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
+  if constexpr (TW::kPowers) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) wbi[q] = cconj(wb[q]);
+  }
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wbi));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
   const cx<T>* l0 = lds + (2 * cc) * S;
   const cx<T>* l1 = l0 + S;
-  cx<T> w[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_{2n}^{-i}, i = p + P (l E/2 + t)
-  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, p + P * l * (E / 2), P, w);
+  cx<T> w[TW::kPowers ? E / 2 : 1];                         // w_{2n}^{-i}, i = p + P (l E/2 + t)
+  if constexpr (TW::kPowers) run_from<E / 2>(wcomb, cconj(wstep), w);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int i = p + P * (l * (E / 2) + tt);
-    if constexpr (TwOf<T>::type::kPowers) col[(size_t)i * CB + c] = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
+    if constexpr (TW::kPowers) col[(size_t)i * CB + c] = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
     else col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
   }
+}
+
+template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD>
+__device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
+                                          bool dc_block) {
+  constexpr int E = Cfg<T, LOGN>::EF;
+  cx<T> x[E];
+  G gk[E];
+  if constexpr (!GEN) cols_load_data<T, LOGN, CPLX, GUARD>(sg, t, valid, tid, x);
+  cols_compute<T, G, LOGN, CPLX, GEN, GUARD>(
+      sg, t, valid, tid, lds, dc_block, x, gk,
+      [&] { cols_load_moments<T, G, LOGN, CPLX, GUARD>(sg, t, valid, tid, gk); });
 }
 
 // ----------------------------------------------------------------------------
@@ -355,6 +440,17 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   const cx<T>* l1 = l0 + S;
   const size_t batch = t / TPD;
   const int row0 = (t % TPD) * RPB;
+  using TW = typename TwOf<T>::type;
+  constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
+  // FP64: every twiddle load of the tile first (run w_{2n}^{-(2p + l + 2P s)},
+  // stage bases, combine run w_n^{-m}; both runs step by w_{2n}^{-2P})
+  cx<T> wq0{}, wstep{}, wm0{}, wb[NB > 0 ? NB : 1];
+  if constexpr (TW::kPowers) {
+    wq0 = tw.template get<+1>(2 * p + l);
+    wstep = tw.template get<+1>(2 * P);
+    load_bases<L, E, +1, 1>(wb, p, tw, 2 * n / L);
+    wm0 = tw.template get<+1>(2 * (p + P * l * (E / 2)));
+  }
   {
     const cx<T>* src = sg.work + batch * n * n;
     for (int idx = tid; idx < RPB * n; idx += NT) {
@@ -366,8 +462,8 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   }
   __syncthreads();
   cx<T> v[1][E];
-  cx<T> wq[TwOf<T>::type::kPowers ? E : 1];                  // w_{2n}^{-k}, k = 2p + l + 2P s
-  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E>(tw, 2 * p + l, 2 * P, wq);
+  cx<T> wq[TW::kPowers ? E : 1];                             // w_{2n}^{-k}, k = 2p + l + 2P s
+  if constexpr (TW::kPowers) run_from<E>(wq0, wstep, wq);
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) {
     const int q = p + P * slot_elem<E, R0>(reg);
@@ -380,27 +476,27 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
       const cx<T> yk = mine[LL::pad(q)];
       const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
       cx<T> d;
-      if constexpr (TwOf<T>::type::kPowers) d = cmul(yk - yk2, wq[slot_elem<E, R0>(reg)]);
+      if constexpr (TW::kPowers) d = cmul(yk - yk2, wq[slot_elem<E, R0>(reg)]);
       else d = tw.template mul<+1>(yk - yk2, k);
       z = (yk + yk2) + times_i(d);
     }
     v[0][reg] = z;
   }
   __syncthreads();
-  fft_lines<L, E, 1, +1>(v, line, p, tw, 2 * n / L);
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2 * n / L, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
   const int row = row0 + r;
   cx<T>* dst = reinterpret_cast<cx<T>*>(static_cast<T*>(sg.dst) + (batch * n + row) * n);
-  cx<T> wm[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_n^{-m}, m = p + P (l E/2 + t)
-  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, 2 * (p + P * l * (E / 2)), 2 * P, wm);
+  cx<T> wm[TW::kPowers ? E / 2 : 1];                         // w_n^{-m}, m = p + P (l E/2 + t)
+  if constexpr (TW::kPowers) run_from<E / 2>(wm0, wstep, wm);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int m = p + P * (l * (E / 2) + tt);
     cx<T> zz;
-    if constexpr (TwOf<T>::type::kPowers) zz = l0[LL::pad(m)] + cmul(l1[LL::pad(m)], wm[tt]);
+    if constexpr (TW::kPowers) zz = l0[LL::pad(m)] + cmul(l1[LL::pad(m)], wm[tt]);
     else zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
     if constexpr (FS) {
       const T* utilde = static_cast<const T*>(sg.src);
@@ -428,6 +524,17 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
   cx<T>* mine = lds + (2 * r + l) * S;
   cx<T>* line[1] = {mine};
   const int row0 = (t % TPD) * RPB;
+  using TW = typename TwOf<T>::type;
+  constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
+  // FP64: the twiddle loads first (pre-twiddle run w_{2n}^{p + P s}, stage bases)
+  cx<T> wpre{}, wpstep{}, wb[NB > 0 ? NB : 1];
+  if constexpr (TW::kPowers) {
+    if (l) {
+      wpre = tw.template get<-1>(p);
+      wpstep = tw.template get<-1>(P);
+    }
+    load_bases<L, E, -1, 1>(wb, p, tw, 2);
+  }
   cx<T> v[1][E];
   {
     const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
@@ -442,9 +549,9 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
         if (!GUARD || valid) x[reg] = cscale(x[reg], sg.mcon[(size_t)row * n + j]);
       }
     }
-    if constexpr (TwOf<T>::type::kPowers) {
+    if constexpr (TW::kPowers) {
       cx<T> w[E];                                          // w_{2n}^j, j = p + P s
-      if (l) tw_run<-1, E>(tw, p, P, w);
+      if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
     } else {
@@ -455,7 +562,7 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
       }
     }
   }
-  fft_lines<L, E, 1, -1>(v, line, p, tw, 2);
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -481,6 +588,15 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
   cx<T>* line[1] = {mine};
   const cx<T>* l0 = lds + (2 * r) * S;
   const cx<T>* l1 = l0 + S;
+  using TW = typename TwOf<T>::type;
+  constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
+  // FP64: the twiddle loads first (stage bases, combine run w_{2n}^{-(p + P (l E/2 + t))})
+  cx<T> wc0{}, wcstep{}, wb[NB > 0 ? NB : 1];
+  if constexpr (TW::kPowers) {
+    load_bases<L, E, +1, 1>(wb, p, tw, 2);
+    wc0 = tw.template get<+1>(p + P * l * (E / 2));
+    wcstep = tw.template get<+1>(P);
+  }
   {
     const cx<T>* src = sg.work + (size_t)(t / TPD) * n * 2 * n;
     const int row0 = (t % TPD) * RPB;
@@ -496,7 +612,7 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
   __syncthreads();
-  fft_lines<L, E, 1, +1>(v, line, p, tw, 2);
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -504,13 +620,13 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
   const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
   cx<T>* out = static_cast<cx<T>*>(sg.dst);
   const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
-  cx<T> w[TwOf<T>::type::kPowers ? E / 2 : 1];              // w_{2n}^{-i}, i = p + P (l E/2 + t)
-  if constexpr (TwOf<T>::type::kPowers) tw_run<+1, E / 2>(tw, p + P * l * (E / 2), P, w);
+  cx<T> w[TW::kPowers ? E / 2 : 1];                         // w_{2n}^{-i}, i = p + P (l E/2 + t)
+  if constexpr (TW::kPowers) run_from<E / 2>(wc0, wcstep, w);
 #pragma unroll
   for (int tt = 0; tt < E / 2; ++tt) {
     const int i = p + P * (l * (E / 2) + tt);
     cx<T> y;
-    if constexpr (TwOf<T>::type::kPowers) y = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
+    if constexpr (TW::kPowers) y = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
     else y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
     y = cscale(y, sg.alpha);
     if (sg.add) y = y + vin[roff + i];

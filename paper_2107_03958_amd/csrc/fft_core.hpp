@@ -74,15 +74,19 @@ struct TwF {
 // Twiddles of an arithmetic run of table indices, w[s] = w(SGN * (b + d s)),
 // s < K.  FP64 tables: two loads and K-1 products (the error grows by about
 // an ulp per step, far below the FP64 error of the transform).  FP32 tables:
-// one (hi, lo) pair per entry, read directly.
+// one (hi, lo) pair per entry, read directly.  run_from forms the run from
+// its two loaded entries (w(SGN b), w(SGN d)), which lets a kernel issue those
+// loads early.
+template <int K, typename T>
+__device__ __forceinline__ void run_from(cx<T> w0, cx<T> step, cx<T> (&w)[K]) {
+  w[0] = w0;
+#pragma unroll
+  for (int s = 1; s < K; ++s) w[s] = cmul(w[s - 1], step);
+}
+
 template <int SGN, int K>
 __device__ __forceinline__ void tw_run(const TwD& tw, int b, int d, cx<double> (&w)[K]) {
-  w[0] = tw.template get<SGN>(b);
-  if constexpr (K > 1) {
-    const cx<double> step = tw.template get<SGN>(d);
-#pragma unroll
-    for (int s = 1; s < K; ++s) w[s] = cmul(w[s - 1], step);
-  }
+  run_from<K>(tw.template get<SGN>(b), K > 1 ? tw.template get<SGN>(d) : cx<double>{1, 0}, w);
 }
 
 template <typename T> struct TwOf;
