@@ -139,7 +139,8 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
   // element idx = tid + it NT of the unpack: the same (c, rr) on every iteration, k grows by NT / RPB
-  static_assert(NT % (CB * RPB) == 0 && (RPB * n) % NT == 0, "store loop shape");
+  // (FP64 when the tile's shape allows: its twiddles are then one run per thread)
+  constexpr bool RUN = TW::kPowers && NT % (CB * RPB) == 0 && (RPB * n) % NT == 0;
   constexpr int IT = RPB * n / NT, DK = NT / RPB;
   const int c = tid % CB, rr = (tid / CB) % RPB, k0 = (tid / (CB * RPB)) * CB + c;
   // FP64: every twiddle load of the tile first (pre-twiddle run w_n^{p + P s},
@@ -152,8 +153,10 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
       wpstep = tw.template get<-1>(2 * P);
     }
     load_bases<L, E, -1, 1>(wb, p, tw, 2 * n / L);
-    wu = tw.template get<-1>(k0);
-    wustep = tw.template get<-1>(DK);
+    if constexpr (RUN) {
+      wu = tw.template get<-1>(k0);
+      wustep = tw.template get<-1>(DK);
+    }
   }
   cx<T> v[1][E];
   {
@@ -196,26 +199,28 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
     }
     dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
   };
-  if constexpr (TW::kPowers) {
+  if constexpr (RUN) {
     cx<T> wk[IT];
     run_from<IT>(wu, wustep, wk);
 #pragma unroll
     for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
   } else {
     for (int idx = tid; idx < RPB * n; idx += NT) {
-      const int cb = idx / (CB * RPB), k = cb * CB + c;
-      const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+      constexpr bool SAME = NT % (CB * RPB) == 0;   // (c, rr) of idx are those of tid
+      const int ci = SAME ? c : idx % CB, ri = SAME ? rr : (idx / CB) % RPB;
+      const int cb = idx / (CB * RPB), k = cb * CB + ci;
+      const cx<T> zk = lds[(2 * ri + (k & 1)) * S + LL::pad(k >> 1)];
       cx<T> val;
       if (k == 0) {
         val = {zk.x + zk.y, zk.x - zk.y};
       } else {
         const int kk = n - k;
-        const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
+        const cx<T> zm = cconj(lds[(2 * ri + (kk & 1)) * S + LL::pad(kk >> 1)]);
         const cx<T> a = cscale(zk + zm, (T)0.5);
         const cx<T> d = cscale(zk - zm, (T)0.5);
         val = a + tw.template mul<-1>(cx<T>{d.y, -d.x}, k);
       }
-      dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+      dst[((size_t)cb * n + row0 + ri) * CB + ci] = val;
     }
   }
 }
