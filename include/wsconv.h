@@ -73,7 +73,11 @@ typedef struct {
 
 typedef struct {
     int    n;               /* grid points per side on D; power of two, 16 <= n <= 2048 */
-    int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1); must be 2 */
+    int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1): 2, or 3 for
+                               densities supported on all of D (b >= 1 + sqrt 2, Section 2.1).
+                               b = 3 needs WS_FP64 and n <= 1024, and is not taken by
+                               conv_apply_multi, Fourier smoothing or mixed-precision ls_solve
+                               (WS_EUNSUPPORTED) */
     double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
                                the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the window
                                [rho + sqrt(2)/2, b - 1/2 - rho] for a density supported in a disc of
@@ -154,8 +158,8 @@ int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, vo
  * Every pass of the apply is one launch shared by all items (up to 8 items per
  * launch), so densities of different grid sizes and kernels run together;
  * each result equals what conv_apply gives for that item alone.  All plans
- * must have the same precision and be all real-kernel (WS_LOG / WS_POWER) or
- * all WS_HELMHOLTZ (else WS_EUNSUPPORTED); no Fourier smoothing.  Items must
+ * must have the same precision, period b = 2, and be all real-kernel (WS_LOG /
+ * WS_POWER) or all WS_HELMHOLTZ (else WS_EUNSUPPORTED); no Fourier smoothing.  Items must
  * not share work buffers.  count = 0 is a no-op. */
 int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const void* const* density,
                      void* const* out, void* const* work, void* stream);

@@ -48,7 +48,8 @@ int check_grid(const ws_grid* g, double* a_out, int* logn) {
   if (g->n <= 0 || (g->n & (g->n - 1))) return fail(WS_EUNSUPPORTED, "n must be a power of two");
   if (g->n < 16 || g->n > 2048) return fail(WS_EUNSUPPORTED, "n must lie in [16, 2048]");
   if (g->b < 1) return fail(WS_EINVAL, "period b must be a positive integer");
-  if (g->b != 2) return fail(WS_EUNSUPPORTED, "only period b = 2 (FFT length 2n) is implemented");
+  if (g->b != 2 && g->b != 3) return fail(WS_EUNSUPPORTED, "period b must be 2 or 3 (FFT length 2n or 3n)");
+  if (g->b == 3 && g->n > 1024) return fail(WS_EUNSUPPORTED, "period b = 3 supports n <= 1024");
   double a = g->a;
   if (!(a > 0.0)) a = (g->b + std::sqrt(2.0) / 2.0 - 0.5) / 2.0;
   if (!(a < g->b) || !std::isfinite(a)) return fail(WS_EINVAL, "truncation radius must satisfy 0 < a < b");
@@ -63,19 +64,19 @@ struct Sizes {
   size_t tw64, tw32, g64, nyq64, g32, nyq32, total, work;
 };
 
-Sizes sizes_for(int n, bool cplx, int precision) {
+Sizes sizes_for(int n, int b, bool cplx, int precision) {
   Sizes s{};
-  const size_t nb = 2 * (size_t)n;
-  const size_t te = ws::table_elems(n, cplx);
+  const size_t nb = (size_t)b * n;
+  const size_t te = ws::table_elems(n, b, cplx);
   s.tw64 = align_up(nb * 16);
   s.tw32 = precision == WS_FP32 ? align_up(nb * 16) : 0;  // (hi, lo) float pairs
   s.g64 = align_up(te * (cplx ? 16 : 8));
-  s.nyq64 = cplx ? 0 : align_up((size_t)(n + 1) * 8);
+  s.nyq64 = cplx ? 0 : align_up((nb / 2 + 1) * 8);
   s.g32 = precision == WS_FP32 ? align_up(te * (cplx ? 8 : 4)) : 0;
-  s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((size_t)(n + 1) * 4) : 0;
+  s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((nb / 2 + 1) * 4) : 0;
   s.total = s.tw64 + s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
   const size_t elem = precision == WS_FP32 ? 8 : 16;
-  s.work = (size_t)n * (cplx ? 2 * n : n) * elem;
+  s.work = (size_t)n * ws::inter_cols(n, b, cplx) * elem;
   return s;
 }
 
@@ -112,7 +113,8 @@ int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
   int logn;
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
-  const Sizes s = sizes_for(grid->n, kernel->family == WS_HELMHOLTZ, precision);
+  if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
+  const Sizes s = sizes_for(grid->n, grid->b, kernel->family == WS_HELMHOLTZ, precision);
   if (plan_bytes) *plan_bytes = s.total;
   if (work_bytes_per_density) *work_bytes_per_density = s.work;
   return WS_OK;
@@ -129,10 +131,11 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   int logn;
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
+  if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
   if (!plan_buf) return fail(WS_EINVAL, "plan buffer is NULL");
   if (reinterpret_cast<uintptr_t>(plan_buf) % 256) return fail(WS_EINVAL, "plan buffer must be 256-byte aligned");
   const bool cplx = kernel->family == WS_HELMHOLTZ;
-  const Sizes s = sizes_for(grid->n, cplx, precision);
+  const Sizes s = sizes_for(grid->n, grid->b, cplx, precision);
   auto* p = new ws_plan();
   p->kern = *kernel;
   p->n = grid->n;
@@ -216,6 +219,7 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
     }
   }
   if (any_fs && p.cplx) return fail(WS_EUNSUPPORTED, "Fourier smoothing is implemented for real kernels only");
+  if (any_fs && p.b != 2) return fail(WS_EUNSUPPORTED, "Fourier smoothing is implemented for period b = 2");
   hipError_t e = hipSuccess;
   if (!p.cplx) {
     const size_t esz = p.precision == WS_FP64 ? 8 : 4;
@@ -308,6 +312,7 @@ int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const 
       return fail(WS_EINVAL, "device buffers must be 16-byte aligned");
     if (precision < 0) precision = p->precision;
     if (cplx < 0) cplx = p->cplx ? 1 : 0;
+    if (p->b != 2) return fail(WS_EUNSUPPORTED, "conv_apply_multi takes plans of period b = 2");
     if (p->precision != precision) return fail(WS_EUNSUPPORTED, "all plans must have the same precision");
     if ((p->cplx ? 1 : 0) != cplx)
       return fail(WS_EUNSUPPORTED, "real-kernel and Helmholtz plans cannot share one call");
@@ -359,7 +364,7 @@ int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, d
   if (!plan) return fail(WS_EINVAL, "plan is NULL");
   if (count < 0 || (count > 0 && (!k1 || !k2 || !out))) return fail(WS_EINVAL, "bad moment request");
   const ws::Plan& p = *plan;
-  const int n = p.n, nb = p.nb, CB = ws::Layout<double>::CB;
+  const int nb = p.nb, N = nb / 2, CB = ws::Layout<double>::CB;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "conv_plan_moments");
@@ -370,12 +375,12 @@ int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, d
     const int a1 = std::abs(k1[i]), a2 = std::abs(k2[i]);   // the moments are radial
     double v[2] = {0.0, 0.0};
     if (p.cplx) {
-      const size_t idx = ((size_t)(a2 / CB) * (n + 1) + a1) * CB + a2 % CB;
+      const size_t idx = ((size_t)(a2 / CB) * (N + 1) + a1) * CB + a2 % CB;
       e = hipMemcpy(v, static_cast<const char*>(p.g64) + idx * 16, 16, hipMemcpyDeviceToHost);
-    } else if (a2 == n) {
+    } else if (a2 == N) {
       e = hipMemcpy(v, p.gnyq64 + a1, 8, hipMemcpyDeviceToHost);
     } else {
-      const size_t idx = ((size_t)(a2 / CB) * (n + 1) + a1) * CB + a2 % CB;
+      const size_t idx = ((size_t)(a2 / CB) * (N + 1) + a1) * CB + a2 % CB;
       e = hipMemcpy(v, static_cast<const char*>(p.g64) + idx * 8, 8, hipMemcpyDeviceToHost);
     }
     if (e != hipSuccess) return hip_fail(e, "conv_plan_moments");

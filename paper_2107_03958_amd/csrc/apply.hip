@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -116,23 +117,37 @@ __device__ __forceinline__ int find_seg(const Segs<T>& tab, int b) {
 #define WS_FOR_EACH_LOGN(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
 
 // ----------------------------------------------------------------------------
+// Bins of the B lines: bin k lives in line k mod B at position k / B.
+template <int B>
+__device__ __forceinline__ int line_of(int k) {
+  if constexpr (B == 2) return k & 1;
+  else return (int)((unsigned)k % (unsigned)B);
+}
+template <int B>
+__device__ __forceinline__ int pos_of(int k) {
+  if constexpr (B == 2) return k >> 1;
+  else return (int)((unsigned)k / (unsigned)B);
+}
+
+// ----------------------------------------------------------------------------
 // Real path, forward row pass: rows j1 < n of a real density -> half spectrum
-// X(j1, k2), k2 in [0, n), with column 0 holding X(j1,0) + i X(j1,n).
-// A real row x of length 2n (n nonzero) is transformed through the complex
-// sequence z_m = x_{2m} + i x_{2m+1} (n/2 nonzero of n): Z = DFT_n(z) splits
-// into DFT_{n/2}(z) (even k) and DFT_{n/2}(z w_n^m) (odd k), and
-// X_k = (Z_k + conj Z_{n-k})/2 - i w_{2n}^k (Z_k - conj Z_{n-k})/2.
-// Threads: (row r, line l, p); line 0 carries the even, line 1 the odd half.
-// LDS line (r, l) holds Z_{2q+l} at q.  Tile = RPB rows of one density.
-template <typename T, int LOGN, bool GUARD>
+// X(j1, k2), k2 in [0, N), N = nb/2, with column 0 holding X(j1,0) + i X(j1,N).
+// A real row x of length nb (n nonzero) is transformed through the complex
+// sequence z_m = x_{2m} + i x_{2m+1} (n/2 nonzero of N): Z = DFT_N(z) splits
+// into B transforms DFT_{n/2}(z w_N^{l m}) giving the bins k = B q + l, and
+// X_k = (Z_k + conj Z_{N-k})/2 - i w_nb^k (Z_k - conj Z_{N-k})/2.
+// Threads: (row r, line l, p).  LDS line (r, l) holds Z_{Bq+l} at q.
+// Tile = RPB rows of one density.
+template <typename T, int LOGN, bool GUARD, int B = 2>
 __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
-  using C = Cfg<T, LOGN>;
+  using C = Cfg<T, LOGN, B>;
   using LL = LineLayout<C::LH, C::EH>;
-  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  constexpr int n = C::n, N = C::NCOLS_R, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB;
+  constexpr int NT = C::NT_RH, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
+  constexpr int TPD = n / RPB, TWS = C::nb / L;
+  const int p = tid % P, l = (tid / P) % B, r = tid / (B * P);
   const auto tw = sg.tw;
-  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* mine = lds + (B * r + l) * S;
   cx<T>* line[1] = {mine};
   const size_t batch = t / TPD;
   const int row0 = (t % TPD) * RPB;
@@ -140,19 +155,19 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
   // element idx = tid + it NT of the unpack: the same (c, rr) on every iteration, k grows by NT / RPB
   // (FP64 when the tile's shape allows: its twiddles are then one run per thread)
-  constexpr bool RUN = TW::kPowers && NT % (CB * RPB) == 0 && (RPB * n) % NT == 0;
-  constexpr int IT = RPB * n / NT, DK = NT / RPB;
+  constexpr bool RUN = TW::kPowers && NT % (CB * RPB) == 0 && (RPB * N) % NT == 0;
+  constexpr int IT = RPB * N / NT, DK = NT / RPB;
   const int c = tid % CB, rr = (tid / CB) % RPB, k0 = (tid / (CB * RPB)) * CB + c;
-  // FP64: every twiddle load of the tile first (pre-twiddle run w_n^{p + P s},
-  // stage bases, unpack run w_{2n}^{k0 + DK it}), so that no later wait is
+  // FP64: every twiddle load of the tile first (pre-twiddle run w_N^{l (p + P s)},
+  // stage bases, unpack run w_nb^{k0 + DK it}), so that no later wait is
   // ordered behind the row loads
   cx<T> wpre{}, wpstep{}, wu{}, wustep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     if (l) {
-      wpre = tw.template get<-1>(2 * p);
-      wpstep = tw.template get<-1>(2 * P);
+      wpre = tw.template get<-1>(2 * p * l);
+      wpstep = tw.template get<-1>(2 * P * l);
     }
-    load_bases<L, E, -1, 1>(wb, p, tw, 2 * n / L);
+    load_bases<L, E, -1, 1>(wb, p, tw, TWS);
     if constexpr (RUN) {
       wu = tw.template get<-1>(k0);
       wustep = tw.template get<-1>(DK);
@@ -166,7 +181,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
     for (int reg = 0; reg < E; ++reg)
       x[reg] = (!GUARD || valid) ? src[p + P * slot_elem<E, R0>(reg)] : cx<T>{0, 0};
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                           // w_n^m, m = p + P s
+      cx<T> w[E];                                           // w_N^{l m}, m = p + P s
       if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -174,28 +189,28 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
         const int m = p + P * slot_elem<E, R0>(reg);
-        v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m) : x[reg];   // odd half: z w_n^m
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], 2 * m * l) : x[reg];   // line l: z w_N^{l m}
       }
     }
   }
-  run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2 * n / L, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, TWS, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
-  cx<T>* dst = sg.work + batch * (size_t)n * n;
+  cx<T>* dst = sg.work + batch * (size_t)n * N;
   auto unpack = [&](int it, auto twiddle) {
     const int k = k0 + it * DK, cb = (tid + it * NT) / (CB * RPB);
-    const cx<T> zk = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+    const cx<T> zk = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
     cx<T> val;
     if (k == 0) {
       val = {zk.x + zk.y, zk.x - zk.y};
     } else {
-      const int kk = n - k;
-      const cx<T> zm = cconj(lds[(2 * rr + (kk & 1)) * S + LL::pad(kk >> 1)]);
+      const int kk = N - k;
+      const cx<T> zm = cconj(lds[(B * rr + line_of<B>(kk)) * S + LL::pad(pos_of<B>(kk))]);
       const cx<T> a = cscale(zk + zm, (T)0.5);
       const cx<T> d = cscale(zk - zm, (T)0.5);
-      val = a + twiddle(cx<T>{d.y, -d.x}, k);        // + w_{2n}^k (-i d)
+      val = a + twiddle(cx<T>{d.y, -d.x}, k);        // + w_nb^k (-i d)
     }
     dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
   };
@@ -205,17 +220,17 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
     for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
   } else {
-    for (int idx = tid; idx < RPB * n; idx += NT) {
+    for (int idx = tid; idx < RPB * N; idx += NT) {
       constexpr bool SAME = NT % (CB * RPB) == 0;   // (c, rr) of idx are those of tid
       const int ci = SAME ? c : idx % CB, ri = SAME ? rr : (idx / CB) % RPB;
       const int cb = idx / (CB * RPB), k = cb * CB + ci;
-      const cx<T> zk = lds[(2 * ri + (k & 1)) * S + LL::pad(k >> 1)];
+      const cx<T> zk = lds[(B * ri + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
       cx<T> val;
       if (k == 0) {
         val = {zk.x + zk.y, zk.x - zk.y};
       } else {
-        const int kk = n - k;
-        const cx<T> zm = cconj(lds[(2 * ri + (kk & 1)) * S + LL::pad(kk >> 1)]);
+        const int kk = N - k;
+        const cx<T> zm = cconj(lds[(B * ri + line_of<B>(kk)) * S + LL::pad(pos_of<B>(kk))]);
         const cx<T> a = cscale(zk + zm, (T)0.5);
         const cx<T> d = cscale(zk - zm, (T)0.5);
         val = a + tw.template mul<-1>(cx<T>{d.y, -d.x}, k);
@@ -226,11 +241,54 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 }
 
 // ----------------------------------------------------------------------------
-// Column pass shared by the real (NCOLS = n) and complex (NCOLS = 2n) paths:
-// forward length-nb transform of n nonzero rows, multiply by the moments,
-// inverse transform keeping rows i1 < n.  Threads (column c, line l, p): line 0
-// transforms x (even frequencies k1 = 2q), line 1 transforms x w_{2n}^j (odd
-// k1 = 2q + 1); out_i = even_i + w_{2n}^{-i} odd_i is combined through LDS.
+// Combination of B inverse-transformed lines (length L, LDS lines base + l S):
+// out_i = sum_l w_nb^{-u l i} line_l[i], i < L, with u = 1 (columns and
+// complex rows: the length-nb inverse keeping n outputs) or u = 2 (real rows:
+// the length-N inverse of the c2r).  B = 2: thread group l forms
+// the outputs i = p + P (l E/2 + t), t < E/2; B = 3: i = p + P (l + 3 t).
+// emit(i, value) stores one output.  FP64 twiddles come from run seeds the
+// caller loaded early: w0 = w_nb^{-u (p + P l E/2)} (B = 2) or
+// w_nb^{-u (p + P l)} (B = 3), and step = w_nb^{-u P} (B = 2) or w_nb^{-3 u P}.
+template <int B, int L, int E, int U, typename T, typename TW, typename EMIT>
+__device__ __forceinline__ void combine_lines(const cx<T>* base, int S, int p, int l, const TW& tw, cx<T> w0,
+                                              cx<T> step, EMIT emit) {
+  using LL = LineLayout<L, E>;
+  constexpr int P = L / E;
+  const cx<T>* l0 = base;
+  const cx<T>* l1 = l0 + S;
+  if constexpr (B == 2) {
+    cx<T> w[TW::kPowers ? E / 2 : 1];                        // w_nb^{-u i}, i = p + P (l E/2 + t)
+    if constexpr (TW::kPowers) run_from<E / 2>(w0, step, w);
+#pragma unroll
+    for (int tt = 0; tt < E / 2; ++tt) {
+      const int i = p + P * (l * (E / 2) + tt);
+      if constexpr (TW::kPowers) emit(i, l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]));
+      else emit(i, l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], U * i));
+    }
+  } else {
+    static_assert(B == 3 && TW::kPowers, "period 3: FP64 only");
+    const cx<T>* l2 = l1 + S;
+    constexpr int TMAX = (E + B - 1) / B;
+    cx<T> w[TMAX];                                           // w_nb^{-u i}, i = p + P (l + 3 t)
+    run_from<TMAX>(w0, step, w);
+#pragma unroll
+    for (int tt = 0; tt < TMAX; ++tt) {
+      const int s = l + B * tt;
+      if (s < E) {
+        const int i = p + P * s;
+        const cx<T> w2 = cmul(w[tt], w[tt]);
+        emit(i, l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]) + cmul(l2[LL::pad(i)], w2));
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Column pass shared by the real (NCOLS = nb/2) and complex (NCOLS = nb)
+// paths: forward length-nb transform of n nonzero rows, multiply by the
+// moments, inverse transform keeping rows i1 < n.  Threads (column c, line l,
+// p): line l transforms x w_nb^{l j} (frequencies k1 = B q + l); the outputs
+// out_i = sum_l w_nb^{-l i} line_l(i) are combined through LDS.
 // GEN: synthesise the spectrum chihat instead of loading and transforming
 // (Fourier smoothing pre-pass).  A tile holds CPB columns of one density.
 // dc_block: the block holds the tile of block-column 0 (packed DC/Nyquist
@@ -238,11 +296,11 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 //
 // The tile's global loads are issued in the order their data is needed:
 // column data, twiddles, moments.
-template <typename T, int LOGN, bool CPLX>
+template <typename T, int LOGN, bool CPLX, int B = 2>
 struct ColGeo {
-  using C = Cfg<T, LOGN>;
+  using C = Cfg<T, LOGN, B>;
   static constexpr int n = C::n, P = C::PF, CB = C::CB, CPB = C::CPB;
-  static constexpr int NCOLS = CPLX ? 2 * n : n, NCT = NCOLS / CPB, GC = CB / CPB;
+  static constexpr int NCOLS = CPLX ? C::NCOLS_C : C::NCOLS_R, NCT = NCOLS / CPB, GC = CB / CPB;
   int cc, p, l, cb, csub, c;
   size_t batch;
   __device__ __forceinline__ ColGeo(int t, int tid) {
@@ -259,12 +317,12 @@ struct ColGeo {
 };
 
 // Column data of tile t: slot reg holds row p + P slot_elem<E,R0>(reg).
-template <typename T, int LOGN, bool CPLX, bool GUARD>
+template <typename T, int LOGN, bool CPLX, bool GUARD, int B = 2>
 __device__ __forceinline__ void cols_load_data(const Seg<T>& sg, int t, bool valid, int tid,
-                                               cx<T> (&x)[Cfg<T, LOGN>::EF]) {
-  using C = Cfg<T, LOGN>;
+                                               cx<T> (&x)[Cfg<T, LOGN, B>::EF]) {
+  using C = Cfg<T, LOGN, B>;
   constexpr int E = C::EF, P = C::PF, CB = C::CB, R0 = FirstLast<C::LF, E>::R0;
-  const ColGeo<T, LOGN, CPLX> g(t, tid);
+  const ColGeo<T, LOGN, CPLX, B> g(t, tid);
   const cx<T>* col = g.col(sg.work);
 #pragma unroll
   for (int reg = 0; reg < E; ++reg)
@@ -272,19 +330,19 @@ __device__ __forceinline__ void cols_load_data(const Seg<T>& sg, int t, bool val
 }
 
 // Moments tile t multiplies by after its forward transform: slot reg is
-// frequency k1 = 2q + l, q = p + P slot_elem<E,RL>(reg), read from row
-// k1' = min(k1, 2n - k1) of the folded table.
-template <typename T, typename G, int LOGN, bool CPLX, bool GUARD>
+// frequency k1 = B q + l, q = p + P slot_elem<E,RL>(reg), read from row
+// k1' = min(k1, nb - k1) of the folded table (nb/2 + 1 rows).
+template <typename T, typename G, int LOGN, bool CPLX, bool GUARD, int B = 2>
 __device__ __forceinline__ void cols_load_moments(const Seg<T>& sg, int t, bool valid, int tid,
-                                                  G (&gk)[Cfg<T, LOGN>::EF]) {
-  using C = Cfg<T, LOGN>;
-  constexpr int n = C::n, E = C::EF, P = C::PF, CB = C::CB, RL = FirstLast<C::LF, E>::RL;
-  const ColGeo<T, LOGN, CPLX> g(t, tid);
-  const G* gc = static_cast<const G*>(sg.gtab) + (size_t)g.cb * (n + 1) * CB + g.c;
+                                                  G (&gk)[Cfg<T, LOGN, B>::EF]) {
+  using C = Cfg<T, LOGN, B>;
+  constexpr int nb = C::nb, N = C::NCOLS_R, E = C::EF, P = C::PF, CB = C::CB, RL = FirstLast<C::LF, E>::RL;
+  const ColGeo<T, LOGN, CPLX, B> g(t, tid);
+  const G* gc = static_cast<const G*>(sg.gtab) + (size_t)g.cb * (N + 1) * CB + g.c;
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) {
-    const int k1 = 2 * (g.p + P * slot_elem<E, RL>(reg)) + g.l;
-    gk[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= n ? k1 : 2 * n - k1) * CB] : G{};
+    const int k1 = B * (g.p + P * slot_elem<E, RL>(reg)) + g.l;
+    gk[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= N ? k1 : nb - k1) * CB] : G{};
   }
 }
 
@@ -293,41 +351,51 @@ __device__ __forceinline__ void cols_load_moments(const Seg<T>& sg, int t, bool 
 // the twiddles (FP64: run seeds and stage bases) are loaded before the
 // moments (load_g fills gk): the pre-twiddle and the first stages then do not
 // wait for the moments.
-template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, typename LG>
+template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, int B, typename LG>
 __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
-                                             bool dc_block, const cx<T> (&x)[Cfg<T, LOGN>::EF],
-                                             G (&gk)[Cfg<T, LOGN>::EF], LG load_g) {
-  using C = Cfg<T, LOGN>;
+                                             bool dc_block, const cx<T> (&x)[Cfg<T, LOGN, B>::EF],
+                                             G (&gk)[Cfg<T, LOGN, B>::EF], LG load_g) {
+  using C = Cfg<T, LOGN, B>;
   using LL = LineLayout<C::LF, C::EF>;
   using TW = typename TwOf<T>::type;
-  constexpr int n = C::n, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
+  constexpr int n = C::n, nb = C::nb, N = C::NCOLS_R, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
   constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
-  const ColGeo<T, LOGN, CPLX> g(t, tid);
+  static_assert(!GEN || B == 2, "smoothing pre-pass: period 2");
+  const ColGeo<T, LOGN, CPLX, B> g(t, tid);
   const int cc = g.cc, p = g.p, l = g.l, cb = g.cb, csub = g.csub, c = g.c;
   const TW tw = sg.tw;
   cx<T>* col = g.col(sg.work);
-  cx<T>* mine = lds + (2 * cc + l) * S;
+  cx<T>* mine = lds + (B * cc + l) * S;
   cx<T>* line[1] = {mine};
   cx<T> v[1][E];
   const int k2 = cb * CB + c;                          // FFT bin of this column
 
-  // FP64 twiddles of the tile: w_{2n}^{p} and w_{2n}^{P} seed the odd line's
-  // pre-twiddle run w_{2n}^{p + P s}; w_{2n}^{-(p + P l E/2)} and the conjugate
-  // step seed the combine's run; the forward stage bases, conjugated, are the
-  // inverse transform's.
-  cx<T> wstep{}, wpre{}, wcomb{};
+  // FP64 twiddles of the tile: the run w_nb^{l (p + P s)} of line l's
+  // pre-twiddle; the combine's run seeds; the forward stage bases, whose
+  // conjugates are the inverse transform's.  B = 2: both runs step by
+  // w_nb^{P} (conjugated for the combine).
+  cx<T> wstep{}, wpre{}, wcomb{}, wcstep{};
   cx<T> wb[NB > 0 ? NB : 1], wbi[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
-    wstep = tw.template get<-1>(P);
-    if (l) wpre = tw.template get<-1>(p);
-    wcomb = tw.template get<+1>(p + P * l * (E / 2));
-    load_bases<L, E, -1, 1>(wb, p, tw, 2);
+    if constexpr (B == 2) {
+      wstep = tw.template get<-1>(P);
+      if (l) wpre = tw.template get<-1>(p);
+      wcomb = tw.template get<+1>(p + P * l * (E / 2));
+    } else {
+      if (l) {
+        wpre = tw.template get<-1>(p * l);
+        wstep = tw.template get<-1>(P * l);
+      }
+      wcomb = tw.template get<+1>(p + P * l);
+      wcstep = tw.template get<+1>(P * B);
+    }
+    load_bases<L, E, -1, 1>(wb, p, tw, B);
   }
   if constexpr (!GEN) {
     load_g();
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                          // w_{2n}^j, j = p + P s
+      cx<T> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -335,17 +403,19 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
         const int j = p + P * slot_elem<E, R0>(reg);
-        v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];   // odd frequencies: x w_{2n}^j
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], j * l) : x[reg];   // line l: x w_nb^{l j}
       }
     }
-    run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
-    // v[0][reg] = Y(k1 = 2q + l), q = p + P slot_elem<E,RL>(reg)
+    run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
+    // v[0][reg] = Y(k1 = B q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {
       if (dc_block) {
-        // Column 0 packs the real columns k2 = 0 (D) and k2 = n (N):
+        // Column 0 packs the real columns k2 = 0 (D) and k2 = N (Nyquist):
         // Y = D^ + i N^ with D^, N^ Hermitian.  New value
-        // g0 D^ + i gN N^ = (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k); -k stays in the same half.
+        // g0 D^ + i gN N^ = (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k).
+        // -k1 = B (n - q) - l lies in line (B - l) mod B at (n - q) mod n
+        // (l = 0) or n - q - 1.
         const bool dc = (!GUARD || valid) && cb == 0 && csub == 0;
         if (dc) {
 #pragma unroll
@@ -353,13 +423,14 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
         }
         __syncthreads();
         if (dc && c == 0) {
+          const cx<T>* pl = lds + (B * cc + (l == 0 ? 0 : B - l)) * S;
 #pragma unroll
           for (int reg = 0; reg < E; ++reg) {
             const int q = p + P * slot_elem<E, RL>(reg);
-            const int k1 = 2 * q + l;
-            const int k1f = k1 <= n ? k1 : 2 * n - k1;
+            const int k1 = B * q + l;
+            const int k1f = k1 <= N ? k1 : nb - k1;
             const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
-            const cx<T> ym = cconj(mine[LL::pad(partner)]);
+            const cx<T> ym = cconj(pl[LL::pad(partner)]);
             const T g0 = (T)gk[reg];                 // column 0 of block-column 0: gtab[k1f * CB]
             const T gN = sg.gnyq[k1f];
             v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
@@ -395,91 +466,94 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
 #pragma unroll
     for (int q = 0; q < NB; ++q) wbi[q] = cconj(wb[q]);
   }
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wbi));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wbi));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
-  const cx<T>* l0 = lds + (2 * cc) * S;
-  const cx<T>* l1 = l0 + S;
-  cx<T> w[TW::kPowers ? E / 2 : 1];                         // w_{2n}^{-i}, i = p + P (l E/2 + t)
-  if constexpr (TW::kPowers) run_from<E / 2>(wcomb, cconj(wstep), w);
-#pragma unroll
-  for (int tt = 0; tt < E / 2; ++tt) {
-    const int i = p + P * (l * (E / 2) + tt);
-    if constexpr (TW::kPowers) col[(size_t)i * CB + c] = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
-    else col[(size_t)i * CB + c] = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
-  }
+  combine_lines<B, L, E, 1>(lds + (B * cc) * S, S, p, l, tw, wcomb, B == 2 ? cconj(wstep) : wcstep,
+                            [&](int i, cx<T> y) { col[(size_t)i * CB + c] = y; });
 }
 
-template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD>
+template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, int B = 2>
 __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
                                           bool dc_block) {
-  constexpr int E = Cfg<T, LOGN>::EF;
+  constexpr int E = Cfg<T, LOGN, B>::EF;
   cx<T> x[E];
   G gk[E];
-  if constexpr (!GEN) cols_load_data<T, LOGN, CPLX, GUARD>(sg, t, valid, tid, x);
-  cols_compute<T, G, LOGN, CPLX, GEN, GUARD>(
+  if constexpr (!GEN) cols_load_data<T, LOGN, CPLX, GUARD, B>(sg, t, valid, tid, x);
+  cols_compute<T, G, LOGN, CPLX, GEN, GUARD, B>(
       sg, t, valid, tid, lds, dc_block, x, gk,
-      [&] { cols_load_moments<T, G, LOGN, CPLX, GUARD>(sg, t, valid, tid, gk); });
+      [&] { cols_load_moments<T, G, LOGN, CPLX, GUARD, B>(sg, t, valid, tid, gk); });
 }
 
 // ----------------------------------------------------------------------------
 // Real path, inverse row pass: half spectrum rows -> n real outputs.
-// Y(k + n) = conj Y(n - k); with Z_k = (Y_k + Y_{k+n}) + i w_{2n}^{-k} (Y_k - Y_{k+n}),
-// z = IDFT_n(Z) gives out_{2m} + i out_{2m+1}, m < n/2, computed as
-// IDFT_{n/2}(Z_even)_m + w_n^{-m} IDFT_{n/2}(Z_odd)_m.
+// With N = nb/2, Y(k + N) = conj Y(N - k) and
+// Z_k = (Y_k + Y_{k+N}) + i w_nb^{-k} (Y_k - Y_{k+N}), z = IDFT_N(Z) gives
+// out_{2m} + i out_{2m+1}, m < n/2, as sum_l w_N^{-l m} IDFT_{n/2}(Z_{B.+l})_m.
 // FS: out = u_tilde * out * psi (the Fourier-smoothed density, Section 2.4).
-// LDS line (r, l) first holds Y_{2q+l} at q, then the inverse transform of line l.
-template <typename T, int LOGN, bool FS, bool GUARD>
+// LDS line (r, l) first holds Y_{Bq+l} at q, then the inverse transform of line l.
+template <typename T, int LOGN, bool FS, bool GUARD, int B = 2>
 __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
-  using C = Cfg<T, LOGN>;
+  using C = Cfg<T, LOGN, B>;
   using LL = LineLayout<C::LH, C::EH>;
-  constexpr int n = C::n, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB, NT = C::NT_RH;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  constexpr int n = C::n, N = C::NCOLS_R, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB;
+  constexpr int NT = C::NT_RH, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
+  constexpr int TPD = n / RPB, TWS = C::nb / L;
+  static_assert(!FS || B == 2, "smoothing pre-pass: period 2");
+  const int p = tid % P, l = (tid / P) % B, r = tid / (B * P);
   const auto tw = sg.tw;
-  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* mine = lds + (B * r + l) * S;
   cx<T>* line[1] = {mine};
-  const cx<T>* l0 = lds + (2 * r) * S;
-  const cx<T>* l1 = l0 + S;
   const size_t batch = t / TPD;
   const int row0 = (t % TPD) * RPB;
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
-  // FP64: every twiddle load of the tile first (run w_{2n}^{-(2p + l + 2P s)},
-  // stage bases, combine run w_n^{-m}; both runs step by w_{2n}^{-2P})
-  cx<T> wq0{}, wstep{}, wm0{}, wb[NB > 0 ? NB : 1];
+  // FP64: every twiddle load of the tile first (run w_nb^{-(B p + l + B P s)},
+  // stage bases, combine run seeds)
+  cx<T> wq0{}, wstep{}, wm0{}, wmstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
-    wq0 = tw.template get<+1>(2 * p + l);
-    wstep = tw.template get<+1>(2 * P);
-    load_bases<L, E, +1, 1>(wb, p, tw, 2 * n / L);
-    wm0 = tw.template get<+1>(2 * (p + P * l * (E / 2)));
+    wq0 = tw.template get<+1>(B * p + l);
+    wstep = tw.template get<+1>(B * P);
+    load_bases<L, E, +1, 1>(wb, p, tw, TWS);
+    if constexpr (B == 2) {
+      wm0 = tw.template get<+1>(2 * (p + P * l * (E / 2)));
+    } else {
+      wm0 = tw.template get<+1>(2 * (p + P * l));
+      wmstep = tw.template get<+1>(2 * P * B);
+    }
   }
   {
-    const cx<T>* src = sg.work + batch * n * n;
-    for (int idx = tid; idx < RPB * n; idx += NT) {
+    const cx<T>* src = sg.work + batch * n * N;
+    for (int idx = tid; idx < RPB * N; idx += NT) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
-      lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] =
+      lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
           (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
     }
   }
   __syncthreads();
   cx<T> v[1][E];
-  cx<T> wq[TW::kPowers ? E : 1];                             // w_{2n}^{-k}, k = 2p + l + 2P s
+  cx<T> wq[TW::kPowers ? E : 1];                             // w_nb^{-k}, k = B p + l + B P s
   if constexpr (TW::kPowers) run_from<E>(wq0, wstep, wq);
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) {
     const int q = p + P * slot_elem<E, R0>(reg);
-    const int k = 2 * q + l;
+    const int k = B * q + l;
     cx<T> z;
     if (k == 0) {
       const cx<T> y0 = mine[0];
       z = {y0.x + y0.y, y0.x - y0.y};
     } else {
       const cx<T> yk = mine[LL::pad(q)];
-      const cx<T> yk2 = cconj(mine[LL::pad((n - k) >> 1)]);   // n - k has the parity of k
+      cx<T> yk2;
+      if constexpr (B == 2) {
+        yk2 = cconj(mine[LL::pad((n - k) >> 1)]);           // n - k has the parity of k
+      } else {
+        const int kp = N - k;
+        yk2 = cconj(lds[(B * r + line_of<B>(kp)) * S + LL::pad(pos_of<B>(kp))]);
+      }
       cx<T> d;
       if constexpr (TW::kPowers) d = cmul(yk - yk2, wq[slot_elem<E, R0>(reg)]);
       else d = tw.template mul<+1>(yk - yk2, k);
@@ -488,21 +562,14 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
     v[0][reg] = z;
   }
   __syncthreads();
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2 * n / L, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, TWS, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
   const int row = row0 + r;
   cx<T>* dst = reinterpret_cast<cx<T>*>(static_cast<T*>(sg.dst) + (batch * n + row) * n);
-  cx<T> wm[TW::kPowers ? E / 2 : 1];                         // w_n^{-m}, m = p + P (l E/2 + t)
-  if constexpr (TW::kPowers) run_from<E / 2>(wm0, wstep, wm);
-#pragma unroll
-  for (int tt = 0; tt < E / 2; ++tt) {
-    const int m = p + P * (l * (E / 2) + tt);
-    cx<T> zz;
-    if constexpr (TW::kPowers) zz = l0[LL::pad(m)] + cmul(l1[LL::pad(m)], wm[tt]);
-    else zz = l0[LL::pad(m)] + tw.template mul<+1>(l1[LL::pad(m)], 2 * m);
+  combine_lines<B, L, E, 2>(lds + (B * r) * S, S, p, l, tw, wm0, B == 2 ? wstep : wmstep, [&](int m, cx<T> zz) {
     if constexpr (FS) {
       const T* utilde = static_cast<const T*>(sg.src);
       const cx<T> ut = reinterpret_cast<const cx<T>*>(utilde + (batch * n + row) * n)[m];
@@ -512,33 +579,33 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
       zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
     }
     dst[m] = zz;
-  }
+  });
 }
 
 // ----------------------------------------------------------------------------
-// Complex path, forward row pass: X(j1, k2), k2 in [0, 2n), natural order,
-// from rows of (m .* v); even k2 from DFT_n(x), odd k2 from DFT_n(x w_{2n}^j).
-template <typename T, int LOGN, bool MUL, bool GUARD>
+// Complex path, forward row pass: X(j1, k2), k2 in [0, nb), natural order,
+// from rows of (m .* v); bins k2 = B q + l from DFT_n(x w_nb^{l j}).
+template <typename T, int LOGN, bool MUL, bool GUARD, int B = 2>
 __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
-  using C = Cfg<T, LOGN>;
+  using C = Cfg<T, LOGN, B>;
   using LL = LineLayout<C::LF, C::EFR>;
-  constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  constexpr int n = C::n, nb = C::nb, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB;
+  constexpr int NT = C::NT_RC, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  const int p = tid % P, l = (tid / P) % B, r = tid / (B * P);
   const auto tw = sg.tw;
-  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* mine = lds + (B * r + l) * S;
   cx<T>* line[1] = {mine};
   const int row0 = (t % TPD) * RPB;
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
-  // FP64: the twiddle loads first (pre-twiddle run w_{2n}^{p + P s}, stage bases)
+  // FP64: the twiddle loads first (pre-twiddle run w_nb^{l (p + P s)}, stage bases)
   cx<T> wpre{}, wpstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     if (l) {
-      wpre = tw.template get<-1>(p);
-      wpstep = tw.template get<-1>(P);
+      wpre = tw.template get<-1>(p * l);
+      wpstep = tw.template get<-1>(P * l);
     }
-    load_bases<L, E, -1, 1>(wb, p, tw, 2);
+    load_bases<L, E, -1, 1>(wb, p, tw, B);
   }
   cx<T> v[1][E];
   {
@@ -555,7 +622,7 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
       }
     }
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                          // w_{2n}^j, j = p + P s
+      cx<T> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -563,52 +630,55 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) {
         const int j = p + P * slot_elem<E, R0>(reg);
-        v[0][reg] = l ? tw.template mul<-1>(x[reg], j) : x[reg];
+        v[0][reg] = l ? tw.template mul<-1>(x[reg], j * l) : x[reg];
       }
     }
   }
-  run_stages<L, E, 1, -1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
-  cx<T>* dst = sg.work + (size_t)(t / TPD) * n * 2 * n;
-  for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+  cx<T>* dst = sg.work + (size_t)(t / TPD) * n * nb;
+  for (int idx = tid; idx < RPB * nb; idx += NT) {
     const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
     const int k = cb * CB + c;
-    dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)];
+    dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
   }
 }
 
 // Complex path, inverse row pass keeping i2 < n, fused out = [v] + alpha * result.
-template <typename T, int LOGN, bool GUARD>
+template <typename T, int LOGN, bool GUARD, int B = 2>
 __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
-  using C = Cfg<T, LOGN>;
+  using C = Cfg<T, LOGN, B>;
   using LL = LineLayout<C::LF, C::EFR>;
-  constexpr int n = C::n, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB, NT = C::NT_RC;
-  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
-  const int p = tid % P, l = (tid / P) & 1, r = tid / (2 * P);
+  constexpr int n = C::n, nb = C::nb, L = C::LF, E = C::EFR, P = C::PFR, RPB = C::RPBC, CB = C::CB;
+  constexpr int NT = C::NT_RC, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE, TPD = n / RPB;
+  const int p = tid % P, l = (tid / P) % B, r = tid / (B * P);
   const auto tw = sg.tw;
-  cx<T>* mine = lds + (2 * r + l) * S;
+  cx<T>* mine = lds + (B * r + l) * S;
   cx<T>* line[1] = {mine};
-  const cx<T>* l0 = lds + (2 * r) * S;
-  const cx<T>* l1 = l0 + S;
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
-  // FP64: the twiddle loads first (stage bases, combine run w_{2n}^{-(p + P (l E/2 + t))})
+  // FP64: the twiddle loads first (stage bases, combine run seeds)
   cx<T> wc0{}, wcstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
-    load_bases<L, E, +1, 1>(wb, p, tw, 2);
-    wc0 = tw.template get<+1>(p + P * l * (E / 2));
-    wcstep = tw.template get<+1>(P);
+    load_bases<L, E, +1, 1>(wb, p, tw, B);
+    if constexpr (B == 2) {
+      wc0 = tw.template get<+1>(p + P * l * (E / 2));
+      wcstep = tw.template get<+1>(P);
+    } else {
+      wc0 = tw.template get<+1>(p + P * l);
+      wcstep = tw.template get<+1>(P * B);
+    }
   }
   {
-    const cx<T>* src = sg.work + (size_t)(t / TPD) * n * 2 * n;
+    const cx<T>* src = sg.work + (size_t)(t / TPD) * n * nb;
     const int row0 = (t % TPD) * RPB;
-    for (int idx = tid; idx < RPB * 2 * n; idx += NT) {
+    for (int idx = tid; idx < RPB * nb; idx += NT) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
-      lds[(2 * rr + (k & 1)) * S + LL::pad(k >> 1)] =
+      lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
           (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
     }
   }
@@ -617,7 +687,7 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
   __syncthreads();
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, 2, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -625,32 +695,22 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
   const cx<T>* vin = static_cast<const cx<T>*>(sg.src);
   cx<T>* out = static_cast<cx<T>*>(sg.dst);
   const size_t roff = ((size_t)(t / TPD) * n + (t % TPD) * RPB + r) * n;
-  cx<T> w[TW::kPowers ? E / 2 : 1];                         // w_{2n}^{-i}, i = p + P (l E/2 + t)
-  if constexpr (TW::kPowers) run_from<E / 2>(wc0, wcstep, w);
-#pragma unroll
-  for (int tt = 0; tt < E / 2; ++tt) {
-    const int i = p + P * (l * (E / 2) + tt);
-    cx<T> y;
-    if constexpr (TW::kPowers) y = l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]);
-    else y = l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], i);
+  combine_lines<B, L, E, 1>(lds + (B * r) * S, S, p, l, tw, wc0, wcstep, [&](int i, cx<T> y) {
     y = cscale(y, sg.alpha);
     if (sg.add) y = y + vin[roff + i];
     out[roff + i] = y;
-  }
+  });
 }
 
 // ----------------------------------------------------------------------------
-// Tile groups: a block runs BLK / NT tiles of one segment side by side.
-// Tiles past the segment's end run with valid = false: they read and write
-// nothing outside LDS but join every barrier.
 // Tile groups: a block of BLOCK threads runs BLOCK / NT tiles of one segment
 // side by side.  In a block whose group runs past the segment's end
 // (GUARD), the tiles past it read and write nothing outside LDS but join every
 // barrier.
-template <typename T, int LOGN, int K, int BLOCK, bool GUARD>
+template <typename T, int LOGN, int K, int BLOCK, bool GUARD, int B = 2>
 __device__ __forceinline__ void run_tiles(const Seg<T>& sg, int b, cx<T>* lds) {
-  using C = Cfg<T, LOGN>;
-  using KO = KindOf<T, K>;
+  using C = Cfg<T, LOGN, B>;
+  using KO = KindOf<T, K, B>;
   constexpr int NT = KO::template nt<LOGN>();
   constexpr int TPB = BLOCK / NT;
   constexpr int LDS = KO::template lds_tile<LOGN>();
@@ -659,37 +719,39 @@ __device__ __forceinline__ void run_tiles(const Seg<T>& sg, int b, cx<T>* lds) {
   const bool valid = !GUARD || t < sg.ntiles;
   const int tt = valid ? t : 0;
   cx<T>* mylds = lds + sub * LDS;
-  if constexpr (K == kRowsFwdReal) rows_fwd_real_tile<T, LOGN, GUARD>(sg, tt, valid, tid, mylds);
-  if constexpr (K == kRowsInvReal) rows_inv_real_tile<T, LOGN, false, GUARD>(sg, tt, valid, tid, mylds);
-  if constexpr (K == kRowsInvFs) rows_inv_real_tile<T, LOGN, true, GUARD>(sg, tt, valid, tid, mylds);
-  if constexpr (K == kRowsFwdCplx) rows_fwd_cplx_tile<T, LOGN, false, GUARD>(sg, tt, valid, tid, mylds);
-  if constexpr (K == kRowsFwdCplxMul) rows_fwd_cplx_tile<T, LOGN, true, GUARD>(sg, tt, valid, tid, mylds);
-  if constexpr (K == kRowsInvCplx) rows_inv_cplx_tile<T, LOGN, GUARD>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsFwdReal) rows_fwd_real_tile<T, LOGN, GUARD, B>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvReal) rows_inv_real_tile<T, LOGN, false, GUARD, B>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvFs) rows_inv_real_tile<T, LOGN, true, GUARD, B>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsFwdCplx) rows_fwd_cplx_tile<T, LOGN, false, GUARD, B>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsFwdCplxMul) rows_fwd_cplx_tile<T, LOGN, true, GUARD, B>(sg, tt, valid, tid, mylds);
+  if constexpr (K == kRowsInvCplx) rows_inv_cplx_tile<T, LOGN, GUARD, B>(sg, tt, valid, tid, mylds);
   if constexpr (K == kColsReal || K == kColsGen || K == kColsCplx) {
     constexpr bool CPLX = K == kColsCplx;
-    constexpr int NCT = (CPLX ? 2 * C::n : C::n) / C::CPB;
+    constexpr int NCT = (CPLX ? C::NCOLS_C : C::NCOLS_R) / C::CPB;
     // does this block hold a tile of block-column 0 (first column of a density)?
     const int first = b * TPB;
     const int last = std::min(first + TPB, sg.ntiles) - 1;
     const bool dc_block = first % NCT == 0 || first / NCT != last / NCT;
-    if constexpr (K == kColsReal) cols_tile<T, T, LOGN, false, false, GUARD>(sg, tt, valid, tid, mylds, dc_block);
-    if constexpr (K == kColsGen) cols_tile<T, T, LOGN, false, true, GUARD>(sg, tt, valid, tid, mylds, false);
-    if constexpr (K == kColsCplx) cols_tile<T, cx<T>, LOGN, true, false, GUARD>(sg, tt, valid, tid, mylds, false);
+    if constexpr (K == kColsReal)
+      cols_tile<T, T, LOGN, false, false, GUARD, B>(sg, tt, valid, tid, mylds, dc_block);
+    if constexpr (K == kColsGen) cols_tile<T, T, LOGN, false, true, GUARD, B>(sg, tt, valid, tid, mylds, false);
+    if constexpr (K == kColsCplx)
+      cols_tile<T, cx<T>, LOGN, true, false, GUARD, B>(sg, tt, valid, tid, mylds, false);
   }
 }
 
-template <typename T, int LOGN, int K, int BLOCK>
+template <typename T, int LOGN, int K, int BLOCK, int B = 2>
 __device__ __forceinline__ void run_group(const Seg<T>& sg, int blk, cx<T>* lds) {
-  using KO = KindOf<T, K>;
+  using KO = KindOf<T, K, B>;
   constexpr int TPB = BLOCK / KO::template nt<LOGN>();
   constexpr int G = KO::template line_group<LOGN>();
   constexpr int GB = G / TPB > 1 ? G / TPB : 1;
   const int b = xcd_tile<GB>(blk, sg.nblocks);
   if constexpr (TPB == 1) {
-    run_tiles<T, LOGN, K, BLOCK, false>(sg, b, lds);
+    run_tiles<T, LOGN, K, BLOCK, false, B>(sg, b, lds);
   } else {
-    if ((b + 1) * TPB <= sg.ntiles) run_tiles<T, LOGN, K, BLOCK, false>(sg, b, lds);
-    else run_tiles<T, LOGN, K, BLOCK, true>(sg, b, lds);
+    if ((b + 1) * TPB <= sg.ntiles) run_tiles<T, LOGN, K, BLOCK, false, B>(sg, b, lds);
+    else run_tiles<T, LOGN, K, BLOCK, true, B>(sg, b, lds);
   }
 }
 
@@ -697,7 +759,7 @@ __device__ __forceinline__ void run_group(const Seg<T>& sg, int blk, cx<T>* lds)
 // Every pointer comes in as its own argument; all but the density and result
 // of the smoothing pre-pass (which may be the same array) are restrict, which
 // lets the compiler move loads past stores and barriers.
-template <typename T, int K, int LOGN>
+template <typename T, int K, int LOGN, int B>
 __device__ __forceinline__ void pass1_body(const void* src, void* dst, cx<T>* work, const void* gtab,
                                            const T* gnyq, const T* mcon, typename TwOf<T>::type tw, int ntiles,
                                            int nblocks, T alpha, int add, const FsArgs& fs, cx<T>* lds) {
@@ -716,17 +778,17 @@ __device__ __forceinline__ void pass1_body(const void* src, void* dst, cx<T>* wo
   sg.alpha = alpha;
   sg.add = add;
   sg.fs = fs;
-  run_group<T, LOGN, K, Single<T, K, LOGN>::BLOCK>(sg, blockIdx.x, lds);
+  run_group<T, LOGN, K, Single<T, K, LOGN, B>::BLOCK, B>(sg, blockIdx.x, lds);
 }
 
-template <typename T, int K, int LOGN>
-__global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::WAVES)) void k_pass1(
+template <typename T, int K, int LOGN, int B = 2>
+__global__ __launch_bounds__((Single<T, K, LOGN, B>::BLOCK), (Single<T, K, LOGN, B>::WAVES)) void k_pass1(
     const void* __restrict__ src, void* __restrict__ dst, cx<T>* __restrict__ work, const void* __restrict__ gtab,
     const T* __restrict__ gnyq, const T* __restrict__ mcon, typename TwOf<T>::type tw, int ntiles, int nblocks,
     T alpha, int add, FsArgs fs, const int* skip) {
   if (skip && *skip) return;
-  __shared__ cx<T> lds[Single<T, K, LOGN>::LDS];
-  pass1_body<T, K, LOGN>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+  __shared__ cx<T> lds[Single<T, K, LOGN, B>::LDS];
+  pass1_body<T, K, LOGN, B>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
 }
 
 template <typename T, int K, int LOGN>
@@ -736,7 +798,7 @@ __global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::W
     T alpha, int add, FsArgs fs, const int* skip) {
   if (skip && *skip) return;
   __shared__ cx<T> lds[Single<T, K, LOGN>::LDS];
-  pass1_body<T, K, LOGN>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+  pass1_body<T, K, LOGN, 2>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
 }
 
 // Launches over several segments of any sizes: one block size for all.
@@ -776,16 +838,36 @@ template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
 struct Geo {
   int tiles_per_density, nt, block_single;
 };
-template <typename T, int LOGN, int K>
+template <typename T, int LOGN, int K, int B>
 Geo geo_of() {
-  using KO = KindOf<T, K>;
-  return Geo{KO::template tiles_per_density<LOGN>(), KO::template nt<LOGN>(), Single<T, K, LOGN>::BLOCK};
+  using KO = KindOf<T, K, B>;
+  return Geo{KO::template tiles_per_density<LOGN>(), KO::template nt<LOGN>(), Single<T, K, LOGN, B>::BLOCK};
 }
+// Period-3 kernels exist for FP64 plans of n <= 2^kMaxLognB3, without the
+// smoothing pre-pass.
 template <typename T, int K>
-Geo geo(int logn) {
+constexpr bool has_b3() {
+  return std::is_same_v<T, double> && K != kRowsInvFs && K != kColsGen;
+}
+#define WS_FOR_EACH_LOGN_B3(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
+static_assert(kMaxLognB3 == 10, "WS_FOR_EACH_LOGN_B3 lists 4..kMaxLognB3");
+template <typename T, int K>
+Geo geo(int logn, int b) {
+  if (b == 3) {
+    if constexpr (has_b3<T, K>()) {
+      switch (logn) {
+#define WS_CASE(L) \
+  case L: return geo_of<T, L, K, 3>();
+        WS_FOR_EACH_LOGN_B3(WS_CASE)
+#undef WS_CASE
+        default: break;
+      }
+    }
+    return Geo{0, 1, 1};
+  }
   switch (logn) {
 #define WS_CASE(L) \
-  case L: return geo_of<T, L, K>();
+  case L: return geo_of<T, L, K, 2>();
     WS_FOR_EACH_LOGN(WS_CASE)
 #undef WS_CASE
     default: return Geo{0, 1, 1};
@@ -805,7 +887,7 @@ Seg<T> make_seg(const Plan& p, int batch, const void* src, void* dst, cx<T>* wor
   s.gtab = gtab_of<T>(p);
   s.gnyq = gnyq_of<T>(p);
   s.alpha = (T)1;
-  const Geo g = geo<T, K>(p.logn);
+  const Geo g = geo<T, K>(p.logn, p.b);
   s.ntiles = batch * g.tiles_per_density;
   const int tpb = (multi ? KindOf<T, K>::BLK : g.block_single) / g.nt;
   s.nblocks = (s.ntiles + tpb - 1) / tpb;
@@ -836,6 +918,24 @@ hipError_t launch_one(const Plan& p, int batch, const void* src, void* dst, cx<T
   sg.add = add ? 1 : 0;
   if (fs) sg.fs = *fs;
   if (sg.nblocks == 0) return hipSuccess;
+  if (p.b == 3) {
+    if constexpr (has_b3<T, K>()) {
+      switch (p.logn) {
+#define WS_CASE(L)                                                                          \
+  case L:                                                                                   \
+    k_pass1<T, K, L, 3><<<sg.nblocks, Single<T, K, L, 3>::BLOCK, 0, st>>>(                   \
+        sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,    \
+        sg.alpha, sg.add, sg.fs, skip);                                                      \
+    return hipGetLastError();
+        WS_FOR_EACH_LOGN_B3(WS_CASE)
+#undef WS_CASE
+        default:
+          break;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
+  if (p.b != 2) return hipErrorInvalidValue;
   switch (p.logn) {
 #define WS_CASE(L)                                                                          \
   case L:                                                                                   \
@@ -880,7 +980,7 @@ hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>
 
 template <typename T>
 hipError_t launch_fs_real(const Plan& p, const T* ut, T* out, cx<T>* work, const ws_fs_desc& d, hipStream_t s) {
-  if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+  if (p.logn < kMinLogn || p.logn > kMaxLogn || p.b != 2) return hipErrorInvalidValue;
   FsArgs f{d.shape, d.c1, d.c2, d.size, d.psi_r1, d.psi_r2};
   hipError_t e = launch_one<T, kColsGen>(p, 1, nullptr, nullptr, work, s, nullptr, nullptr, (T)1, false, &f);
   if (e != hipSuccess) return e;
@@ -929,7 +1029,7 @@ hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipS
     std::vector<Seg<T>> seg[3];
     for (int i = 0; i < count; ++i) {
       const Plan& p = *items[i].plan;
-      if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+      if (p.logn < kMinLogn || p.logn > kMaxLogn || p.b != 2) return hipErrorInvalidValue;
       const int left = items[i].batch - done[i];
       if (left <= 0) continue;
       const int nb = std::min(left, apply_chunk(p));

@@ -11,50 +11,61 @@
 
 namespace ws {
 
-template <typename T, int LOGN>
+// B is the period b of the extension (nb = B n): a length-nb transform of n
+// nonzero samples is B length-n transforms ("lines") of pre-twiddled samples,
+// interleaved in frequency (line l holds the bins B q + l).
+template <typename T, int LOGN, int B = 2>
 struct Cfg {
+  static_assert(B == 2 || B == 3, "period b must be 2 or 3");
   static constexpr int n = 1 << LOGN;
+  static constexpr int nb = B * n;
   static constexpr int CB = Layout<T>::CB;
   static constexpr int RPB = Layout<T>::RPB;
   static constexpr int cap(int e, int lines, int L) {         // keep lines * L / e <= 1024 threads
     while (lines * (L / e) > 1024) e *= 2;
     return e < L ? e : L;
   }
-  // Real row passes: two half-length lines (even/odd spectrum) per row, one line per thread group.
+  // Columns of the intermediate: real path nb/2 (half spectrum, column 0
+  // packing the DC and Nyquist columns), complex path nb.
+  static constexpr int NCOLS_R = nb / 2, NCOLS_C = nb;
+  // Real row passes: B half-length lines per row (the length-nb/2 complex
+  // transform of z_m = x_2m + i x_2m+1), one line per thread group.
   static constexpr int LH = n / 2;
-  static constexpr int EH = cap(Layout<T>::ER, 2 * RPB, LH);
+  static constexpr int EH = cap(Layout<T>::ER, B * RPB, LH);
   static constexpr int PH = LH / EH;
-  static constexpr int NT_RH = 2 * RPB * PH;
+  static constexpr int NT_RH = B * RPB * PH;
   static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
-  static constexpr int LDS_RH = 2 * RPB * SH_;               // LDS elements per real row tile
-  // Column passes: two full-length lines (even/odd frequencies) per column,
-  // CPB columns per tile (CPB = CB, or 1 with XCD-paired tiles).
+  static constexpr int LDS_RH = B * RPB * SH_;               // LDS elements per real row tile
+  // Column passes: B full-length lines per column, CPB columns per tile
+  // (CPB = CB, or 1 with XCD-paired tiles).
   static constexpr int CPB = Layout<T>::CPB1 ? 1 : CB;
   static constexpr int LF = n;
-  static constexpr int EF = cap(Layout<T>::EC, 2 * CPB, LF);
+  static constexpr int EF = cap(Layout<T>::EC, B * CPB, LF);
   static constexpr int PF = LF / EF;
-  static constexpr int NT_C = 2 * CPB * PF;
+  static constexpr int NT_C = B * CPB * PF;
   static constexpr int SF = LineLayout<LF, EF>::STRIDE;
-  static constexpr int LDS_C = 2 * CPB * SF;
-  // Complex row passes: two full-length lines per row, rows per tile limited by LDS.
+  static constexpr int LDS_C = B * CPB * SF;
+  // Complex row passes: B full-length lines per row, rows per tile limited by LDS.
   template <int ROWS>
   static constexpr bool fits() {
-    constexpr int e = cap(Layout<T>::ER, 2 * ROWS, LF);
-    return ROWS * 2 * LineLayout<LF, e>::STRIDE * (int)sizeof(cx<T>) <= 81920;
+    constexpr int e = cap(Layout<T>::ER, B * ROWS, LF);
+    return ROWS * B * LineLayout<LF, e>::STRIDE * (int)sizeof(cx<T>) <= 81920;
   }
   static constexpr int R2_ = RPB / 2 > 1 ? RPB / 2 : 1, R4_ = RPB / 4 > 1 ? RPB / 4 : 1;
   static constexpr int RPBC = fits<RPB>() ? RPB : fits<R2_>() ? R2_ : fits<R4_>() ? R4_ : 1;
-  static constexpr int EFR = cap(Layout<T>::ER, 2 * RPBC, LF);
+  static constexpr int EFR = cap(Layout<T>::ER, B * RPBC, LF);
   static constexpr int PFR = LF / EFR;
-  static constexpr int NT_RC = 2 * RPBC * PFR;
+  static constexpr int NT_RC = B * RPBC * PFR;
   static constexpr int SFR = LineLayout<LF, EFR>::STRIDE;
-  static constexpr int LDS_RC = 2 * RPBC * SFR;
+  static constexpr int LDS_RC = B * RPBC * SFR;
   // Row tiles sharing 128-byte lines of the intermediate (real and complex row passes).
   static constexpr int RG = 128 / (RPB * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPB * CB * (int)sizeof(cx<T>)) : 1;
   static constexpr int RGC = 128 / (RPBC * CB * (int)sizeof(cx<T>)) > 1 ? 128 / (RPBC * CB * (int)sizeof(cx<T>)) : 1;
 };
 
 constexpr int kMinLogn = 4, kMaxLogn = 11;
+// Period b = 3 (nb = 3n): FP64 plans up to n = 1024, single-plan launches.
+constexpr int kMaxLognB3 = 10;
 constexpr int kMaxSegs = 8;
 
 // Block size and LDS of each kind of pass: the largest over all sizes.
@@ -137,7 +148,7 @@ __host__ __device__ inline int xcd_tile(int b, int nblocks) {
 enum PassKind { kRowsFwdReal, kColsReal, kColsGen, kRowsInvReal, kRowsInvFs, kRowsFwdCplx, kRowsFwdCplxMul,
                 kColsCplx, kRowsInvCplx };
 
-template <typename T, int K>
+template <typename T, int K, int B = 2>
 struct KindOf {
   static constexpr bool ROWS_R = K == kRowsFwdReal || K == kRowsInvReal || K == kRowsInvFs;
   static constexpr bool ROWS_C = K == kRowsFwdCplx || K == kRowsFwdCplxMul || K == kRowsInvCplx;
@@ -148,21 +159,23 @@ struct KindOf {
   static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : Blk<T>::WAVES_C;
   template <int LOGN>
   static constexpr int nt() {
-    return ROWS_R ? Cfg<T, LOGN>::NT_RH : ROWS_C ? Cfg<T, LOGN>::NT_RC : Cfg<T, LOGN>::NT_C;
+    using C = Cfg<T, LOGN, B>;
+    return ROWS_R ? C::NT_RH : ROWS_C ? C::NT_RC : C::NT_C;
   }
   template <int LOGN>
   static constexpr int lds_tile() {
-    return ROWS_R ? Cfg<T, LOGN>::LDS_RH : ROWS_C ? Cfg<T, LOGN>::LDS_RC : Cfg<T, LOGN>::LDS_C;
+    using C = Cfg<T, LOGN, B>;
+    return ROWS_R ? C::LDS_RH : ROWS_C ? C::LDS_RC : C::LDS_C;
   }
   // tiles of a density, and consecutive tiles that share 128-byte lines of the intermediate
   template <int LOGN>
   static constexpr int tiles_per_density() {
-    using C = Cfg<T, LOGN>;
-    return ROWS_R ? C::n / C::RPB : ROWS_C ? C::n / C::RPBC : (CPLX_COLS ? 2 * C::n : C::n) / C::CPB;
+    using C = Cfg<T, LOGN, B>;
+    return ROWS_R ? C::n / C::RPB : ROWS_C ? C::n / C::RPBC : (CPLX_COLS ? C::NCOLS_C : C::NCOLS_R) / C::CPB;
   }
   template <int LOGN>
   static constexpr int line_group() {
-    using C = Cfg<T, LOGN>;
+    using C = Cfg<T, LOGN, B>;
     return ROWS_R ? C::RG : ROWS_C ? C::RGC : C::CB / C::CPB;
   }
 };
@@ -172,12 +185,13 @@ struct KindOf {
 #ifndef WS_MIN_BLOCK
 #define WS_MIN_BLOCK 64
 #endif
-template <typename T, int K, int LOGN>
+template <typename T, int K, int LOGN, int B = 2>
 struct Single {
-  static constexpr int NT = KindOf<T, K>::template nt<LOGN>();
-  static constexpr int BLOCK = NT > WS_MIN_BLOCK ? NT : WS_MIN_BLOCK;
+  static constexpr int NT = KindOf<T, K, B>::template nt<LOGN>();
+  // the smallest multiple of NT of at least WS_MIN_BLOCK threads
+  static constexpr int BLOCK = NT >= WS_MIN_BLOCK ? NT : NT * ((WS_MIN_BLOCK + NT - 1) / NT);
   static constexpr int TPB = BLOCK / NT;
-  static constexpr int LDS = TPB * KindOf<T, K>::template lds_tile<LOGN>();
+  static constexpr int LDS = TPB * KindOf<T, K, B>::template lds_tile<LOGN>();
   // Waves per SIMD the registers are sized for.  Row kernels: as many blocks
   // as the LDS admits (at most 8 waves per SIMD).  Column kernels: at most two
   // blocks per CU (their butterflies need the registers).

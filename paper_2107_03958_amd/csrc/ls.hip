@@ -353,18 +353,18 @@ struct Krylov {
   cx<T>* V = nullptr;        // restart + 1 vectors
   cx<T>* r = nullptr;
   cx<T>* t = nullptr;
-  cx<T>* awork = nullptr;    // apply intermediate (n x 2n)
+  cx<T>* awork = nullptr;    // apply intermediate (n x nb)
 
-  static size_t bytes(int restart, size_t N, int n) {
+  static size_t bytes(int restart, size_t N, int n, int nb) {
     size_t b = align_up(sizeof(GState));
     b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * restart);
     b += 3 * align_up(sizeof(cx<double>) * (size_t)(restart + 1)) + 2 * align_up(sizeof(cx<double>) * restart);
     b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks) + align_up(sizeof(double) * kBlocks);
     b += align_up(sizeof(cx<T>) * (size_t)(restart + 1) * N) + 2 * align_up(sizeof(cx<T>) * N);
-    b += align_up(sizeof(cx<T>) * (size_t)n * 2 * n);
+    b += align_up(sizeof(cx<T>) * (size_t)n * nb);
     return b;
   }
-  char* carve(char* base, int rs, size_t n_elems, int n) {
+  char* carve(char* base, int rs, size_t n_elems, int n, int nb) {
     restart = rs;
     N = n_elems;
     auto take = [&](size_t sz) {
@@ -384,7 +384,7 @@ struct Krylov {
     V = (cx<T>*)take(sizeof(cx<T>) * (size_t)(rs + 1) * N);
     r = (cx<T>*)take(sizeof(cx<T>) * N);
     t = (cx<T>*)take(sizeof(cx<T>) * N);
-    awork = (cx<T>*)take(sizeof(cx<T>) * (size_t)n * 2 * n);
+    awork = (cx<T>*)take(sizeof(cx<T>) * (size_t)n * nb);
     return base;
   }
 };
@@ -602,11 +602,11 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
 
 size_t ls_work_bytes(const Plan& p, int restart, bool mixed) {
   const size_t N = (size_t)p.n * p.n;
-  if (!mixed) return Krylov<double>::bytes(restart, N, p.n);
-  size_t b = Krylov<float>::bytes(restart, N, p.n);
+  if (!mixed) return Krylov<double>::bytes(restart, N, p.n, p.nb);
+  size_t b = Krylov<float>::bytes(restart, N, p.n, p.nb);
   b += align_up(sizeof(float) * N);                           // FP32 contrast
   b += 2 * align_up(sizeof(cx<float>) * N);                   // correction, inner right-hand side
-  b += Krylov<double>::bytes(1, N, p.n);                      // FP64 residual machinery
+  b += Krylov<double>::bytes(1, N, p.n, p.nb);                      // FP64 residual machinery
   return b;
 }
 
@@ -672,7 +672,7 @@ int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, do
   char* base = static_cast<char*>(work);
   if (!mixed) {
     Krylov<double> K;
-    K.carve(base, restart, N, p.n);
+    K.carve(base, restart, N, p.n, p.nb);
     auto op = [&](const cx<double>* in, cx<double>* out, const int* skip) {
       return launch_apply_cplx<double>(p, 1, in, contrast, k2, true, out, K.awork, s, skip);
     };
@@ -681,7 +681,7 @@ int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, do
     if (status < 0) goto device_error;
   } else {
     Krylov<float> K32;
-    char* nxt = K32.carve(base, restart, N, p.n);
+    char* nxt = K32.carve(base, restart, N, p.n, p.nb);
     float* m32 = (float*)nxt;
     nxt += align_up(sizeof(float) * N);
     cx<float>* delta = (cx<float>*)nxt;
@@ -689,7 +689,7 @@ int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, do
     cx<float>* rhs32 = (cx<float>*)nxt;
     nxt += align_up(sizeof(cx<float>) * N);
     Krylov<double> K64;
-    K64.carve(nxt, 1, N, p.n);
+    K64.carve(nxt, 1, N, p.n, p.nb);
     k_real_to_float<<<grid_for(N), kThreads, 0, s>>>(contrast, m32, N);
     auto op32 = [&](const cx<float>* in, cx<float>* out, const int* skip) {
       return launch_apply_cplx<float>(p, 1, in, m32, (float)k2, true, out, K32.awork, s, skip);

@@ -152,19 +152,20 @@ __device__ inline cx<double> moment(double kabs, const KernelArgs& K, double inv
   return {K.scale * h.x * inv, K.scale * h.y * inv};
 }
 
-// Blocked table: entry (cb, k1f, c) <-> column bin k2 = cb*CB + c, folded row k1f in [0, n].
+// Blocked table: entry (cb, k1f, c) <-> column bin k2 = cb*CB + c, folded row
+// k1f in [0, N], N = nb/2.
 template <int CB>
-__global__ void k_table(int n, int ncols, KernelArgs K, double inv, int cplx, double* g64, float* g32,
+__global__ void k_table(int nb, int ncols, KernelArgs K, double inv, int cplx, double* g64, float* g32,
                         double* nyq64, float* nyq32) {
-  const size_t total = (size_t)ncols * (n + 1);
+  const int N = nb / 2;
+  const size_t total = (size_t)ncols * (N + 1);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int c = (int)(e % CB);
     const size_t rest = e / CB;
-    const int k1f = (int)(rest % (n + 1));
-    const int cb = (int)(rest / (n + 1));
+    const int k1f = (int)(rest % (N + 1));
+    const int cb = (int)(rest / (N + 1));
     int k2 = cb * CB + c;
-    const int nb = 2 * n;
-    if (k2 > n) k2 = nb - k2;                        // |k2| of bin k2
+    if (k2 > N) k2 = nb - k2;                        // |k2| of bin k2
     const double kabs = sqrt((double)k1f * k1f + (double)k2 * k2);
     const cx<double> v = moment(kabs, K, inv);
     if (cplx) {
@@ -175,10 +176,10 @@ __global__ void k_table(int n, int ncols, KernelArgs K, double inv, int cplx, do
       if (g32) g32[e] = (float)v.x;
     }
   }
-  // Nyquist column k2 = n of the real path.
+  // Nyquist column k2 = N of the real path.
   if (nyq64 || nyq32) {
-    for (int k1f = blockIdx.x * blockDim.x + threadIdx.x; k1f <= n; k1f += gridDim.x * blockDim.x) {
-      const double kabs = sqrt((double)k1f * k1f + (double)n * n);
+    for (int k1f = blockIdx.x * blockDim.x + threadIdx.x; k1f <= N; k1f += gridDim.x * blockDim.x) {
+      const double kabs = sqrt((double)k1f * k1f + (double)N * N);
       const double v = moment(kabs, K, inv).x;
       if (nyq64) nyq64[k1f] = v;
       if (nyq32) nyq32[k1f] = (float)v;
@@ -230,15 +231,15 @@ hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
   const double inv = 1.0 / ((double)nb * nb);
   const int threads = 256;
   k_twiddles<<<(nb + threads - 1) / threads, threads, 0, s>>>(nb, pl.tw64, pl.tw32);
-  const int ncols = pl.cplx ? 2 * n : n;
-  const size_t total = (size_t)ncols * (n + 1);
+  const int ncols = (int)inter_cols(n, pl.b, pl.cplx);
+  const size_t total = (size_t)ncols * (nb / 2 + 1);
   const int blocks = (int)std::min<size_t>((total + threads - 1) / threads, 65536);
   const int cp = pl.cplx ? 1 : 0;
   // FP64 table (every plan: FP64 applies, the refinement residual of mixed solves).
-  k_table<Layout<double>::CB><<<blocks, threads, 0, s>>>(n, ncols, K, inv, cp, (double*)pl.g64, nullptr,
+  k_table<Layout<double>::CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, nullptr,
                                                          pl.cplx ? nullptr : pl.gnyq64, nullptr);
   if (pl.precision == WS_FP32)
-    k_table<Layout<float>::CB><<<blocks, threads, 0, s>>>(n, ncols, K, inv, cp, nullptr, (float*)pl.g32,
+    k_table<Layout<float>::CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, nullptr, (float*)pl.g32,
                                                           nullptr, pl.cplx ? nullptr : pl.gnyq32);
   return hipGetLastError();
 }

@@ -72,7 +72,7 @@ template <> struct Layout<float> {
 
 struct Plan {
   ws_kernel kern;
-  int n = 0, b = 2, nb = 0, logn = 0;
+  int n = 0, b = 2, nb = 0, logn = 0;   // nb = b n; b = 2, or 3 (FP64, n <= 1024, single-plan launches)
   double a = 0;
   int precision = WS_FP64;
   bool cplx = false;          // Helmholtz: complex densities, c2c path
@@ -93,17 +93,19 @@ struct Plan {
 // Record `msg` as this host thread's conv_last_error() message; returns `code`.
 int set_last_error(int code, const std::string& msg);
 
+// Columns of the intermediate: nb/2 on the real path (half spectrum, the DC
+// and Nyquist columns packed into one), nb on the complex path.
+inline size_t inter_cols(int n, int b, bool cplx) { return cplx ? (size_t)b * n : (size_t)b * n / 2; }
+
 inline int apply_chunk(const Plan& p) {
-  const size_t per = (size_t)p.n * (p.cplx ? 2 * p.n : p.n) * (p.precision == WS_FP64 ? 16 : 8);
+  const size_t per = (size_t)p.n * inter_cols(p.n, p.b, p.cplx) * (p.precision == WS_FP64 ? 16 : 8);
   const size_t c = (size_t)WS_CHUNK_BYTES / per;
   return c < 1 ? 1 : (c > 65535 ? 65535 : (int)c);
 }
 
-// Sizes (in elements) of the moment tables for a plan.
-inline size_t table_elems(int n, bool cplx) {
-  // real path: n columns + a Nyquist column stored apart; complex path: 2n columns.
-  return (size_t)(n + 1) * (cplx ? 2 * n : n);
-}
+// Sizes (in elements) of the moment tables for a plan: nb/2 + 1 folded rows
+// per intermediate column (the real path's Nyquist column is stored apart).
+inline size_t table_elems(int n, int b, bool cplx) { return ((size_t)b * n / 2 + 1) * inter_cols(n, b, cplx); }
 
 // Launchers (apply.hip).  Each returns the hipError_t of its launches.
 // Real path (WS_LOG / WS_POWER): out = A_n u for `batch` real densities.

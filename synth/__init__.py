@@ -80,6 +80,31 @@ def smooth_density(n: int, seed: int) -> np.ndarray:
     return acc * cutoff(n)
 
 
+def full_support_density(n: int, seed: int, power: int = 3) -> np.ndarray:
+    """Density supported on all of D: (x1(1-x1) x2(1-x2))^power times a seeded smooth factor.
+
+    The polynomial is the one of Table globconv1 (power 3); it vanishes on the
+    boundary of D only, so the zero extension needs a period b >= 1 + sqrt 2.
+    Draw order: m ~ U{1..4}; then per term: frequencies f1, f2 ~ U[0.5, 3]
+    (f1 then f2), phase p ~ U[0, 2 pi), amplitude A ~ N(0, 1).
+    u = poly * (1 + 0.5 sum_i A_i cos(2 pi (f1 x1 + f2 x2) + p)).
+    """
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(1, 5))
+    terms = []
+    for _ in range(m):
+        f1 = rng.uniform(0.5, 3.0)
+        f2 = rng.uniform(0.5, 3.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        a = rng.normal()
+        terms.append((f1, f2, ph, a))
+    x1, x2 = grid(n)
+    fac = np.ones((n, n))
+    for f1, f2, ph, a in terms:
+        fac += 0.5 * a * np.cos(2.0 * math.pi * (f1 * x1 + f2 * x2) + ph)
+    return (x1 * (1.0 - x1) * x2 * (1.0 - x2)) ** power * fac
+
+
 def disc_radius(seed: int) -> float:
     """Radius R ~ U[0.15, 0.35] of a piecewise-constant disc density (centre (0.5, 0.5))."""
     rng = np.random.default_rng(seed)
@@ -116,3 +141,4 @@ SEED_DISC_BATCH = 1100        # disc density i uses 1100 + i
 SEED_PRECISION = 2000         # 2048^2 precision study: 2000 + i
 SEED_LS_ANGLE = 3000          # plane-wave angle: 3000 + kappa
 SEED_TRACE = 4000             # serving arrival trace
+SEED_FULL_SUPPORT = 5000      # period-3 densities on all of D: 5000 + i

@@ -3,7 +3,8 @@
 // tile-group map is a bijection, every tile of a segment is covered exactly
 // once, the thread -> (p, line, row/column) map of a tile is a bijection onto
 // its ranges, tiles' LDS slices and lines stay inside the block's LDS, and the
-// XCD grouping puts line-sharing tile groups on blocks 8 apart.  Built with
+// XCD grouping puts line-sharing tile groups on blocks 8 apart; the same for
+// the period-3 kernels (three lines per row or column).  Built with
 // hipcc by tests/test_apply_geometry.py; runs on the host only.
 #include <cstdio>
 #include <cstdlib>
@@ -146,7 +147,94 @@ void check_all() {
   if constexpr (LOGN < kMaxLogn) check_all<T, LOGN + 1>();
 }
 
+// Period-3 (B = 3) single-size kernels: block shapes, tile coverage, the
+// thread -> (p, line, row/column) maps onto B lines, LDS bounds, the bin ->
+// (line, position) map, and the combine's slot split over the B line groups.
+template <typename T, int LOGN, int K>
+void check_single_b3(int batch) {
+  const char* tname = "double/b3";
+  constexpr int KIND = -100 - K;
+  constexpr int B = 3;
+  using C = Cfg<T, LOGN, B>;
+  using S = Single<T, K, LOGN, B>;
+  using KO = KindOf<T, K, B>;
+  CHECK(S::BLOCK % S::NT == 0 && S::TPB * S::NT == S::BLOCK && S::BLOCK <= 1024 && S::BLOCK >= WS_MIN_BLOCK);
+  CHECK(S::LDS * (int)sizeof(cx<T>) <= 163840);
+  const int ntiles = batch * KO::template tiles_per_density<LOGN>();
+  const int nblocks = (ntiles + S::TPB - 1) / S::TPB;
+  constexpr int G = KO::template line_group<LOGN>();
+  constexpr int GB = G / S::TPB > 1 ? G / S::TPB : 1;
+  std::vector<int> tseen(ntiles, 0);
+  for (int blk = 0; blk < nblocks; ++blk) {
+    const int b = xcd_tile<GB>(blk, nblocks);
+    CHECK(b >= 0 && b < nblocks);
+    for (int sub = 0; sub < S::TPB; ++sub)
+      if (b * S::TPB + sub < ntiles) tseen[b * S::TPB + sub]++;
+  }
+  for (int v : tseen) CHECK(v == 1);
+  constexpr bool ROWS_R = KO::ROWS_R, ROWS_C = KO::ROWS_C;
+  constexpr int P = ROWS_R ? C::PH : ROWS_C ? C::PFR : C::PF;
+  constexpr int L = ROWS_R ? C::LH : C::LF;
+  constexpr int E = ROWS_R ? C::EH : ROWS_C ? C::EFR : C::EF;
+  constexpr int UNITS = ROWS_R ? C::RPB : ROWS_C ? C::RPBC : C::CPB;
+  using LL = LineLayout<L, E>;
+  CHECK(P * E == L && S::NT == B * UNITS * P);
+  std::set<std::tuple<int, int, int>> seen;
+  for (int tid = 0; tid < S::NT; ++tid) {
+    int p, l, u;
+    if constexpr (ROWS_R || ROWS_C) {
+      p = tid % P;
+      l = (tid / P) % B;
+      u = tid / (B * P);
+    } else {
+      col_thread<C::CPB, P>(tid, u, p, l);
+    }
+    CHECK(p >= 0 && p < P && l >= 0 && l < B && u >= 0 && u < UNITS);
+    seen.insert({p, l, u});
+    CHECK((B * u + l) * LL::STRIDE + LL::LEN <= KO::template lds_tile<LOGN>());
+    for (int s = 0; s < E; ++s) CHECK(LL::pad_ps(p, s) < LL::LEN && LL::pad_ps(p, s) == LL::pad(p + P * s));
+  }
+  CHECK((int)seen.size() == S::NT);
+  // bins k in [0, B L) <-> (line k mod B, position k / B < L)
+  std::set<std::pair<int, int>> bins;
+  for (int k = 0; k < B * L; ++k) {
+    CHECK(k / B < L);
+    bins.insert({k % B, k / B});
+  }
+  CHECK((int)bins.size() == B * L);
+  // combine: line group l takes slots l, l + B, ... < E; together every slot once
+  std::vector<int> slots(E, 0);
+  for (int l = 0; l < B; ++l)
+    for (int t = 0; t < (E + B - 1) / B; ++t)
+      if (l + B * t < E) slots[l + B * t]++;
+  for (int v : slots) CHECK(v == 1);
+  // column tiles stay inside the intermediate's columns
+  if constexpr (!ROWS_R && !ROWS_C) {
+    constexpr int NCOLS = K == kColsCplx ? C::NCOLS_C : C::NCOLS_R;
+    CHECK(NCOLS % C::CB == 0);
+    for (int t = 0; t < NCOLS / C::CPB; ++t) {
+      const int cb = t / (C::CB / C::CPB), csub = t % (C::CB / C::CPB);
+      CHECK(cb * C::CB + csub * C::CPB + C::CPB - 1 < NCOLS);
+    }
+  }
+}
+
+template <int LOGN>
+void check_b3() {
+  for (int batch : {1, 2, 3, 7}) {
+    check_single_b3<double, LOGN, ws::kRowsFwdReal>(batch);
+    check_single_b3<double, LOGN, ws::kColsReal>(batch);
+    check_single_b3<double, LOGN, ws::kRowsInvReal>(batch);
+    check_single_b3<double, LOGN, ws::kRowsFwdCplx>(batch);
+    check_single_b3<double, LOGN, ws::kRowsFwdCplxMul>(batch);
+    check_single_b3<double, LOGN, ws::kColsCplx>(batch);
+    check_single_b3<double, LOGN, ws::kRowsInvCplx>(batch);
+  }
+  if constexpr (LOGN < kMaxLognB3) check_b3<LOGN + 1>();
+}
+
 int main() {
+  check_b3<kMinLogn>();
   check_all<double, kMinLogn>();
   check_all<float, kMinLogn>();
   std::printf("apply geometry checks passed (block sizes: double %d/%d/%d, float %d/%d/%d)\n", Blk<double>::RH,

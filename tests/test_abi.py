@@ -57,11 +57,24 @@ def test_plan_query_sizes(lib):
     assert rc == 0 and wbh == 1024 * 2048 * 16
 
 
+def test_plan_query_sizes_period3(lib):
+    # b = 3: nb = 3n; real half spectrum n x 3n/2, complex n x 3n; moment
+    # tables of (3n/2 + 1) folded rows per intermediate column
+    rc, pb, wb = _query(lib, n=1024, b=3)
+    assert rc == L.WS_OK and wb == 1024 * 1536 * 16
+    assert pb >= 1537 * 1536 * 8 + 1537 * 8 + 3072 * 16
+    rc, pbh, wbh = _query(lib, family=L.WS_HELMHOLTZ, kappa=20.0, n=512, b=3)
+    assert rc == L.WS_OK and wbh == 512 * 1536 * 16
+    assert pbh >= 769 * 1536 * 16
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(n=100), L.WS_EUNSUPPORTED),
     (dict(n=8), L.WS_EUNSUPPORTED),
     (dict(n=4096), L.WS_EUNSUPPORTED),
-    (dict(b=3), L.WS_EUNSUPPORTED),
+    (dict(b=4), L.WS_EUNSUPPORTED),
+    (dict(b=3, n=2048), L.WS_EUNSUPPORTED),
+    (dict(b=3, prec=L.WS_FP32), L.WS_EUNSUPPORTED),
     (dict(b=0), L.WS_EINVAL),
     (dict(a=2.5), L.WS_EINVAL),
     (dict(family=L.WS_POWER, gamma=0.5), L.WS_EINVAL),

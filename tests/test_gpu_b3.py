@@ -1,0 +1,145 @@
+"""Period b = 3 (nb = 3n; densities supported on all of D, Section 2.1) on the
+GPU vs the CPU oracle, element by element, through the C-ABI.
+
+Bar: FP64 relative L-infinity <= 1e-12 (the apply), as for b = 2.  Inputs:
+synth.full_support_density (the polynomial of Table globconv1 times a seeded
+smooth factor), seeds SEED_FULL_SUPPORT + i.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ls as ols
+from oracle import metrics, moments, scheme
+from tests.gpu_common import oracle_kernel, plan_kwargs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+B3 = 3
+A3 = (B3 + math.sqrt(2) / 2 - 0.5) / 2
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2107_03958_amd import api as _api
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return _api
+
+
+@functools.lru_cache(maxsize=16)
+def table3(name: str, n: int) -> np.ndarray:
+    return moments.ghat_table(oracle_kernel(name), n, B3, A3)
+
+
+def _gpu(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def _densities(n, count):
+    return np.stack([synth.full_support_density(n, synth.SEED_FULL_SUPPORT + i) for i in range(count)])
+
+
+@pytest.mark.parametrize("kname", ["log", "pow-1/2"])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+def test_b3_real_apply(api, kname, n):
+    us = _densities(n, 3)
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs(kname))
+    assert abs(plan.a - A3) < 1e-15
+    got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    for i in range(3):
+        ref = np.real(scheme.apply(us[i], table3(kname, n), B3))
+        assert metrics.rel_linf(got[i], ref) <= FP64_TOL, (kname, n, i)
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_b3_real_apply_large(api, n):
+    # n = 1024 is the largest period-3 size; batch 2 at n = 512 and 1024
+    us = _densities(n, 2)
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("log"))
+    got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
+    for i in range(2):
+        ref = np.real(scheme.apply(us[i], table3("log", n), B3))
+        assert metrics.rel_linf(got[i], ref) <= FP64_TOL, (n, i)
+
+
+def test_b3_passes_match_apply(api):
+    n = 64
+    us = _gpu(_densities(n, 2), torch.float64)
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("pow-1/2"))
+    ref = plan.apply(us).clone()
+    out = torch.empty_like(us)
+    work = plan.workspace(2)
+    for ps in range(3):
+        plan.apply_pass(ps, us, out, work)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_b3_complex_apply(api, n):
+    rng = np.random.default_rng(synth.SEED_FULL_SUPPORT + n)
+    base = synth.full_support_density(n, synth.SEED_FULL_SUPPORT)
+    v = base * (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("helm20"))
+    got = plan.apply(_gpu(v[None], torch.complex128)).cpu().numpy()[0]
+    ref = scheme.apply(v, table3("helm20", n), B3)
+    assert metrics.rel_linf(got, ref) <= FP64_TOL
+
+
+def test_b3_moments_sampled(api):
+    # the table's frequency range is F_n with nb = 3n, including the Nyquist
+    # row and column |k| = 3n/2
+    n = 256
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("log"))
+    N = 3 * n // 2
+    rng = np.random.default_rng(7)
+    k1 = np.concatenate([[0, 1, -N, -N, N - 1, 300], rng.integers(-N, N, 40)])
+    k2 = np.concatenate([[0, 0, 0, -N, N - 1, -N], rng.integers(-N, N, 40)])
+    got = plan.moments(k1, k2)
+    kabs = np.sqrt((k1.astype(np.int64) ** 2 + k2.astype(np.int64) ** 2).astype(np.float64))
+    ref = moments.ghat(oracle_kernel("log"), kabs, A3, B3)
+    scale = abs(moments.ghat(oracle_kernel("log"), np.zeros(1), A3, B3)[0])
+    assert np.max(np.abs(got - ref)) <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_b3_ls_solve_vs_dense(api, n):
+    # contrast supported on all of D (the full-support polynomial), plane wave
+    kappa = 20.0
+    x1, x2 = synth.grid(n)
+    m = 0.5 * (16.0 * x1 * (1.0 - x1) * x2 * (1.0 - x2)) ** 3
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + 20))
+    plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("helm20"))
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-12, restart=30)
+    assert info.status == 0, info
+    g = table3("helm20", n)
+    ref = ols.dense_solve(m, ui, g, B3, kappa)
+    got = u.cpu().numpy()
+    assert metrics.rel_linf(got, ref) <= 1e-10
+    res = ui - ols.matvec(got, m, g, B3, kappa)
+    assert np.linalg.norm(res) / np.linalg.norm(ui) <= 1e-11
+
+
+def test_b3_unsupported_uses(api):
+    from paper_2107_03958_amd import _lib as L
+    with pytest.raises(L.WsError) as e:
+        api.ConvPlan(n=64, b=B3, precision="fp32", **plan_kwargs("log"))
+    assert e.value.code == L.WS_EUNSUPPORTED
+    with pytest.raises(L.WsError) as e:
+        api.ConvPlan(n=2048, b=B3, **plan_kwargs("log"))
+    assert e.value.code == L.WS_EUNSUPPORTED
+    p3 = api.ConvPlan(n=64, b=B3, **plan_kwargs("log"))
+    p2 = api.ConvPlan(n=64, **plan_kwargs("log"))
+    u = _gpu(_densities(64, 1), torch.float64)
+    with pytest.raises(L.WsError) as e:
+        api.apply_multi([p2, p3], [u, u.clone()])
+    assert e.value.code == L.WS_EUNSUPPORTED
+    with pytest.raises(L.WsError) as e:
+        p3.apply(u, fs=[api.FsDesc("disc", 0.5, 0.5, 0.2, 0.2, 0.39)])
+    assert e.value.code == L.WS_EUNSUPPORTED
