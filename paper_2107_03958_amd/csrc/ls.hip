@@ -602,11 +602,12 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
 
 size_t ls_work_bytes(const Plan& p, int restart, bool mixed) {
   const size_t N = (size_t)p.n * p.n;
-  if (!mixed) return Krylov<double>::bytes(restart, N, p.n, p.nb);
-  size_t b = Krylov<float>::bytes(restart, N, p.n, p.nb);
+  const int nb = p.b * p.n;                                   // the plan's period (also for unbuilt plans)
+  if (!mixed) return Krylov<double>::bytes(restart, N, p.n, nb);
+  size_t b = Krylov<float>::bytes(restart, N, p.n, nb);
   b += align_up(sizeof(float) * N);                           // FP32 contrast
   b += 2 * align_up(sizeof(cx<float>) * N);                   // correction, inner right-hand side
-  b += Krylov<double>::bytes(1, N, p.n, p.nb);                      // FP64 residual machinery
+  b += Krylov<double>::bytes(1, N, p.n, nb);                  // FP64 residual machinery
   return b;
 }
 

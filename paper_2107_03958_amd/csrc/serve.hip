@@ -99,8 +99,10 @@ int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
     const size_t e64 = cplx ? 16 : 8;
     q.own_bytes = nn * e64 + (cfg.precision == WS_FP32 ? nn * e64 / 2 : 0);   // multiples of 256 for n >= 16
     q.scratch_each = align256(work);
-    ws::Plan stub;
+    ws::Plan stub;                        // the served plans have period b = 2
     stub.n = r->n;
+    stub.b = 2;
+    stub.nb = 2 * r->n;
     stub.cplx = cplx;
     stub.precision = cfg.precision;
     q.chunk = ws::apply_chunk(stub);
@@ -114,6 +116,8 @@ int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
     q.own_bytes = align256(nn * 8) + 2 * align256(nn * 16);
     ws::Plan stub;
     stub.n = r->n;
+    stub.b = 2;
+    stub.nb = 2 * r->n;
     stub.cplx = true;
     stub.precision = cfg.precision;
     q.scratch_each = align256(ws::ls_work_bytes(stub, r->restart, cfg.precision == WS_FP32));

@@ -112,3 +112,25 @@ def test_binding_fails_loudly_without_library(tmp_path):
             L.load(str(tmp_path / "missing.so"))
         finally:
             L._lib = L._lib_backup
+
+
+@pytest.mark.parametrize("precision", [L.WS_FP64, L.WS_FP32])
+def test_serve_footprint_covers_ls_workspace(lib, precision):
+    # serve_footprint is host-only.  An LS request's device footprint must hold
+    # its Krylov basis (restart + 1 vectors), the residual and work vectors and
+    # the apply intermediate of its matvec (n x 2n complex at period 2).
+    n, restart = 256, 50
+    cfg = L.WsServeConfig(precision, 1, 1, 4, 4, 0)
+    buf = ctypes.c_int(0)   # any non-NULL host address: only the pointers' presence is checked
+    req = L.WsRequest(L.WS_REQ_LS, L.WsKernel(L.WS_HELMHOLTZ, 1.0, 0.0, 20.0), n,
+                      ctypes.addressof(buf), ctypes.addressof(buf), ctypes.addressof(buf), 1e-8, restart, 1000)
+    fp = ctypes.c_size_t()
+    assert lib.serve_footprint(ctypes.byref(cfg), ctypes.byref(req), ctypes.byref(fp)) == L.WS_OK
+    rc, plan_bytes, _ = _query(lib, family=L.WS_HELMHOLTZ, kappa=20.0, n=n, prec=precision)
+    assert rc == L.WS_OK
+    esz = 16 if precision == L.WS_FP64 else 8
+    N = n * n
+    own = N * 8 + 2 * N * 16                         # contrast, incident field, solution (staged)
+    krylov = (restart + 3) * N * esz                 # V (restart + 1), r, t
+    apply_work = n * 2 * n * esz                     # the matvec's intermediate
+    assert fp.value - plan_bytes - own >= krylov + apply_work
