@@ -36,7 +36,7 @@ KERNELS = [
     ("|x|^-1/3", dict(family="power", scale=1.0, gamma=-1.0 / 3.0)),
 ]
 PASS_NAMES = ["k_rows_fwd_real", "k_cols", "k_rows_inv_real"]
-# Kernel symbol of each pass of a real-kernel apply (ws::k_pass1<T, pass kind, log2 n>).
+# Kernel symbol of each pass of a real-kernel apply (ws::k_pass1<T, pass kind, log2 n, period b>).
 PASS_KINDS = [0, 1, 3]
 
 
@@ -44,15 +44,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def pass_bytes(n: int, s: int) -> list[float]:
-    """Algorithmic HBM bytes of the three passes for one real density (s = bytes per real).
+def pass_bytes(n: int, s: int, b: int = 2) -> list[float]:
+    """Algorithmic HBM bytes of the three passes for one real density (s = bytes per real, period b).
 
-    pass 0 reads the n x n samples and writes the n x n complex half spectrum;
-    pass 1 reads and writes that intermediate and reads the n(n+1) moments plus
-    the n+1 of the packed Nyquist column; pass 2 reads the intermediate and writes
-    n x n samples.  Their sum is the 11 n^2 s pass model of the apply.
+    The intermediate is the n x (bn/2) complex half spectrum, b n^2 s bytes.
+    pass 0 reads the n x n samples and writes the intermediate; pass 1 reads and
+    writes it and reads the (bn/2 + 1) x bn/2 moments plus the bn/2 + 1 of the
+    packed Nyquist column; pass 2 reads the intermediate and writes n x n
+    samples.  At b = 2 their sum is the 11 n^2 s pass model of the apply.
     """
-    return [3.0 * n * n * s, 4.0 * n * n * s + (n + 1) * (n + 1) * s, 3.0 * n * n * s]
+    inter = b * n * n * s
+    half = b * n // 2
+    return [n * n * s + inter, 2.0 * inter + (half + 1) * (half + 1) * s, inter + n * n * s]
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_fp64_2048_traffic.json")
@@ -68,21 +71,22 @@ def measured_traffic(kernel: str, precision: str, n: int, chunk: int):
     res = traffic.load_for_current_sources(TRAFFIC_SUMMARY)
     if res is None or res.get("densities_per_dispatch") != chunk:
         return None
-    sym = f"ws::k_pass1<double, {PASS_KINDS[PASS_NAMES.index(kernel)]}, {n.bit_length() - 1}>"
+    sym = f"ws::k_pass1<double, {PASS_KINDS[PASS_NAMES.index(kernel)]}, {n.bit_length() - 1}, 2>"
     v = res["kernels"].get(sym)
     return None if v is None else v["traffic_bytes"]
 
 
-def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
+def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host, b=2, kernels=None):
+    kernels = KERNELS if kernels is None else kernels
     dt = torch.float64 if precision == "fp64" else torch.float32
     s = 8 if precision == "fp64" else 4
     stream = torch.cuda.current_stream()
     t_plan = []
     plans = []
-    for name, kw in KERNELS:
+    for name, kw in kernels:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plans.append(api.ConvPlan(n=n, precision=precision, **kw))
+        plans.append(api.ConvPlan(n=n, b=b, precision=precision, **kw))
         torch.cuda.synchronize()
         t_plan.append(time.perf_counter() - t0)
     u = u_host.to(dt).cuda()
@@ -123,7 +127,7 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
     launches = steps * nk * ng
     avg_pass_ms = pass_ms / launches       # per launch of `chunk` densities
     applies = steps * nk * batch
-    pb = pass_bytes(n, s)
+    pb = pass_bytes(n, s, b)
     res = dict(
         applies_per_s=applies / elapsed,
         ms_per_step=elapsed / steps * 1e3,
@@ -131,14 +135,14 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host):
         pass_avg_ms={PASS_NAMES[i]: float(avg_pass_ms[i]) for i in range(3)},
         pass_gbps={PASS_NAMES[i]: float(pb[i] * batch * steps * nk / (pass_ms[i] * 1e-3) / 1e9) for i in range(3)},
         densities_per_launch=chunk,
-        plan_build_s={KERNELS[i][0]: t_plan[i] for i in range(nk)},
+        plan_build_s={kernels[i][0]: t_plan[i] for i in range(nk)},
     )
     dom = int(np.argmax(avg_pass_ms))
     per_launch = pb[dom] * batch / ng                  # algorithmic bytes of one launch (average group)
     achieved = per_launch / (avg_pass_ms[dom] * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=achieved, peak=PEAK_HBM_GBPS,
                            unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
-                           traffic=measured_traffic(PASS_NAMES[dom], precision, n, chunk),
+                           traffic=measured_traffic(PASS_NAMES[dom], precision, n, chunk) if b == 2 else None,
                            bytes_per_launch=per_launch, launch_avg_ms=float(avg_pass_ms[dom]))
     # Keep the last outputs of the first kernel for the FP32-vs-FP64 comparison.
     plans[0].apply(u, out=out, work=work)
@@ -417,6 +421,9 @@ def main(argv=None):
     ap.add_argument("--ls-kappa", type=float, nargs="*", default=[20.0, 40.0, 80.0])
     ap.add_argument("--ls-repeats", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-period3", action="store_true")
+    ap.add_argument("--period3-n", type=int, default=1024)
+    ap.add_argument("--period3-batch", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-arena-gb", type=float, default=8.0)
     args = ap.parse_args(argv)
@@ -454,6 +461,21 @@ def main(argv=None):
         r32["rel_linf_vs_fp64_gpu"] = float(np.max(np.abs(diff)) / np.max(np.abs(out64)))
         r32["rel_l2_vs_fp64_gpu"] = float(np.linalg.norm(diff) / np.linalg.norm(out64))
         log(f"fp32: {r32['applies_per_s']:.1f} applies/s, pass model {r32['pass_model_gbps']:.0f} GB/s")
+    p3 = None
+    if not args.no_period3:
+        n3, b3 = args.period3_n, args.period3_batch
+        log(f"period b=3 FP64 apply bench (n={n3}, {b3} full-support densities) ...")
+        u3 = torch.as_tensor(np.stack([synth.full_support_density(n3, synth.SEED_FULL_SUPPORT + i)
+                                       for i in range(b3)]))
+        r3 = run_apply_bench(api, torch, n3, b3, "fp64", args.steps, args.warmup, u3, b=3, kernels=KERNELS[:2])
+        r3.pop("_out_first_kernel")
+        r3["hbm_frac_pass_model"] = r3["pass_model_gbps"] / PEAK_HBM_GBPS
+        p3 = dict(workload=f"A_n apply, {n3}x{n3} grid on D, period b=3 ({3 * n3}^2 FFT), {b3} densities "
+                           f"supported on all of D x {len(KERNELS[:2])} kernels per step, FP64",
+                  **{k: r3[k] for k in ("applies_per_s", "ms_per_step", "pass_model_gbps", "hbm_frac_pass_model",
+                                        "pass_avg_ms", "pass_gbps", "densities_per_launch", "roofline")})
+        log(f"period3: {r3['applies_per_s']:.1f} applies/s, pass model {r3['pass_model_gbps']:.0f} GB/s, "
+            f"passes {r3['pass_avg_ms']}")
     ls = None
     if not args.no_ls:
         log("LS latency bench ...")
@@ -500,6 +522,8 @@ def main(argv=None):
         line["fp32"] = {k: r32[k] for k in ("applies_per_s", "ms_per_step", "pass_model_gbps", "pass_avg_ms",
                                             "pass_gbps", "rel_linf_vs_fp64_gpu", "rel_l2_vs_fp64_gpu",
                                             "roofline")}
+    if p3 is not None:
+        line["period3"] = p3
     if ls is not None:
         line["ls_latency"] = ls
     if srv is not None:
