@@ -201,6 +201,27 @@ int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol
              int restart, int max_matvecs, int mixed_precision, void* u_out, void* work,
              ws_ls_info* info, void* stream);
 
+/* Device scratch needed by ls_solve_fs (the smoothed contrast and its
+ * pre-pass intermediate, then ls_solve's scratch).  WS_EUNSUPPORTED for
+ * plans of period b != 2; fs is checked as in conv_apply and must name a
+ * disc or a square. */
+int ls_solve_fs_query(ws_plan_t plan, const ws_fs_desc* fs, int restart, int mixed_precision,
+                      size_t* work_bytes);
+
+/* ls_solve for a contrast with a jump across the boundary of a disc or square
+ * Omega (Section 2.4 applied to the Lippmann-Schwinger density m u of
+ * Section 3.3; Example 9 with m = -1 in a disc).  The caller passes a smooth
+ * extension m_tilde of the contrast on Omega (device [n][n] float64,
+ * 16-byte aligned) and the descriptor of Omega and of the window psi; the
+ * operator uses the smoothed contrast m_s = m_tilde chi^n_Omega psi (eqs. ls1,
+ * tfs), computed on the device into `work` (256-byte aligned,
+ * ls_solve_fs_query bytes), and the solve proceeds as ls_solve with
+ * contrast m_s.  Every other argument, the return value and the stream
+ * behaviour are as for ls_solve. */
+int ls_solve_fs(ws_plan_t plan, const void* contrast_tilde, const ws_fs_desc* fs, const void* u_inc,
+                double tol, int restart, int max_matvecs, int mixed_precision, void* u_out, void* work,
+                ws_ls_info* info, void* stream);
+
 /* Read back `count` moments ghat(k) (Section 2.2, eq. ghat) of a built plan,
  * for the integer frequencies (k1[i], k2[i]) in F_n, as computed on the device
  * (FP64, without the (nb)^-2 factor).  out: host array of 2*count doubles

@@ -79,6 +79,9 @@ EXPORTS = {
     "ls_solve_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
     "ls_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int, c_int, c_void_p, c_void_p,
                          POINTER(WsLsInfo), c_void_p]),
+    "ls_solve_fs_query": (c_int, [c_void_p, POINTER(WsFsDesc), c_int, c_int, POINTER(c_size_t)]),
+    "ls_solve_fs": (c_int, [c_void_p, c_void_p, POINTER(WsFsDesc), c_void_p, c_double, c_int, c_int, c_int,
+                            c_void_p, c_void_p, POINTER(WsLsInfo), c_void_p]),
     "conv_plan_moments": (c_int, [c_void_p, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_double), c_void_p]),
     "conv_destroy": (None, [c_void_p]),
     "serve_footprint": (c_int, [POINTER(WsServeConfig), POINTER(WsRequest), POINTER(c_size_t)]),

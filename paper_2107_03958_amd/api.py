@@ -136,27 +136,42 @@ class ConvPlan:
             L.check(self.lib.conv_apply_pass(self.handle, pass_index, density.shape[0], _dev_ptr(density),
                                              _dev_ptr(out), _dev_ptr(work), _stream_ptr(stream)))
 
-    def ls_workspace(self, restart: int, mixed: bool) -> torch.Tensor:
+    def ls_workspace(self, restart: int, mixed: bool, fs: "FsDesc | None" = None) -> torch.Tensor:
         nbytes = ctypes.c_size_t()
-        L.check(self.lib.ls_solve_query(self.handle, restart, int(mixed), ctypes.byref(nbytes)))
+        if fs is None:
+            L.check(self.lib.ls_solve_query(self.handle, restart, int(mixed), ctypes.byref(nbytes)))
+        else:
+            d = fs.to_c()
+            L.check(self.lib.ls_solve_fs_query(self.handle, ctypes.byref(d), restart, int(mixed),
+                                               ctypes.byref(nbytes)))
         return torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
 
     def ls_solve(self, contrast: torch.Tensor, u_inc: torch.Tensor, tol: float = 1e-8, restart: int = 50,
                  max_matvecs: int = 5000, mixed: bool = False, out: torch.Tensor | None = None,
-                 work: torch.Tensor | None = None, stream=None):
-        """Solve u + kappa^2 A_n(m u) = u_inc (ls_solve); returns (u, LsInfo)."""
+                 work: torch.Tensor | None = None, stream=None, fs: "FsDesc | None" = None):
+        """Solve u + kappa^2 A_n(m u) = u_inc (ls_solve); returns (u, LsInfo).
+
+        With fs (a disc or square Omega and the window psi), `contrast` is a
+        smooth extension m_tilde of a contrast that jumps across the boundary of
+        Omega, and the operator uses m_tilde chi^n psi (ls_solve_fs)."""
         if contrast.dtype != torch.float64 or u_inc.dtype != torch.complex128:
             raise ValueError("contrast must be float64 and u_inc complex128")
         for t in (contrast, u_inc):
             if t.device != self.device or not t.is_contiguous() or t.shape != (self.n, self.n):
                 raise ValueError(f"inputs must be contiguous ({self.n}, {self.n}) tensors on {self.device}")
         u = out if out is not None else torch.empty_like(u_inc)
-        w = work if work is not None else self.ls_workspace(restart, mixed)
+        w = work if work is not None else self.ls_workspace(restart, mixed, fs)
         info = L.WsLsInfo()
         with torch.cuda.device(self.device):
-            L.check(self.lib.ls_solve(self.handle, _dev_ptr(contrast), _dev_ptr(u_inc), tol, restart,
-                                      max_matvecs, int(mixed), _dev_ptr(u), _dev_ptr(w), ctypes.byref(info),
-                                      _stream_ptr(stream)))
+            if fs is None:
+                L.check(self.lib.ls_solve(self.handle, _dev_ptr(contrast), _dev_ptr(u_inc), tol, restart,
+                                          max_matvecs, int(mixed), _dev_ptr(u), _dev_ptr(w), ctypes.byref(info),
+                                          _stream_ptr(stream)))
+            else:
+                d = fs.to_c()
+                L.check(self.lib.ls_solve_fs(self.handle, _dev_ptr(contrast), ctypes.byref(d), _dev_ptr(u_inc),
+                                             tol, restart, max_matvecs, int(mixed), _dev_ptr(u), _dev_ptr(w),
+                                             ctypes.byref(info), _stream_ptr(stream)))
         return u, LsInfo(info.status, info.iterations, info.matvecs, info.refinements, info.rel_residual)
 
     def moments(self, k1, k2):

@@ -359,6 +359,59 @@ int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol
   return rc;
 }
 
+// Workspace of ls_solve_fs: the smoothed contrast m_s (n x n float64), the
+// smoothing pre-pass intermediate (n x n complex128), then ls_solve's.
+static size_t fs_contrast_bytes(const ws::Plan& p) {
+  const size_t nn = (size_t)p.n * p.n;
+  return align_up(nn * sizeof(double)) + align_up(nn * sizeof(ws::cx<double>));
+}
+
+int ls_solve_fs_query(ws_plan_t plan, const ws_fs_desc* fs, int restart, int mixed_precision,
+                      size_t* work_bytes) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (!fs) return fail(WS_EINVAL, "smoothing descriptor is NULL");
+  if (plan->b != 2) return fail(WS_EUNSUPPORTED, "Fourier smoothing is implemented for period b = 2");
+  if (fs->shape == WS_FS_NONE) return fail(WS_EINVAL, "ls_solve_fs needs a disc or square");
+  int rc = check_fs(*fs, plan->n);
+  if (rc) return rc;
+  size_t ls = 0;
+  if ((rc = ls_solve_query(plan, restart, mixed_precision, &ls))) return rc;
+  if (work_bytes) *work_bytes = fs_contrast_bytes(*plan) + ls;
+  return WS_OK;
+}
+
+int ls_solve_fs(ws_plan_t plan, const void* contrast_tilde, const ws_fs_desc* fs, const void* u_inc, double tol,
+                int restart, int max_matvecs, int mixed_precision, void* u_out, void* work, ws_ls_info* info,
+                void* stream) {
+  g_err.clear();
+  if (info) std::memset(info, 0, sizeof(*info));
+  size_t need = 0;
+  int rc = ls_solve_fs_query(plan, fs, restart, mixed_precision, &need);
+  if (rc) return rc;
+  if (!contrast_tilde || !u_inc || !u_out || !work || !info) return fail(WS_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(contrast_tilde) % 16 || reinterpret_cast<uintptr_t>(work) % 256)
+    return fail(WS_EINVAL, "contrast must be 16-byte and work 256-byte aligned");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WS_EINVAL, "tol must be positive");
+  if (max_matvecs < 1) return fail(WS_EINVAL, "max_matvecs must be >= 1");
+  const ws::Plan& p = *plan;
+  const size_t nn = (size_t)p.n * p.n;
+  char* w = static_cast<char*>(work);
+  double* ms = reinterpret_cast<double*>(w);
+  ws::cx<double>* fsw = reinterpret_cast<ws::cx<double>*>(w + align_up(nn * sizeof(double)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // m_s = m_tilde * chi^n_Omega * psi (Section 2.4, eqs. ls1, tfs), on the caller's stream; ls_run orders
+  // its own work after it.
+  const hipError_t e = ws::launch_fs_real<double>(p, static_cast<const double*>(contrast_tilde), ms, fsw, *fs, s);
+  if (e != hipSuccess) return hip_fail(e, "ls_solve_fs: smoothing pre-pass");
+  std::string err;
+  rc = ws::ls_run(p, ms, static_cast<const ws::cx<double>*>(u_inc), tol, restart, max_matvecs,
+                  mixed_precision != 0, static_cast<ws::cx<double>*>(u_out), w + fs_contrast_bytes(p), info, s,
+                  &err);
+  if (rc < 0) return fail(rc, err);
+  return rc;
+}
+
 int conv_plan_moments(ws_plan_t plan, int count, const int* k1, const int* k2, double* out, void* stream) {
   g_err.clear();
   if (!plan) return fail(WS_EINVAL, "plan is NULL");
