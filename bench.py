@@ -150,6 +150,34 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host, b=2,
     return res
 
 
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+
+def run_eval_bench(api, torch, n, count, repeats=10):
+    """conv_eval: (A_n u)(x) at `count` scattered targets, one density, log|x| kernel, FP64.
+
+    The series sum costs (nb)^2 complex multiply-adds (8 flops) per target; the
+    roofline puts that rate against the FP64 vector peak (the sum is ALU work)."""
+    import synth
+    plan = api.ConvPlan("log", n=n)
+    u = torch.as_tensor(synth.smooth_density(n, synth.SEED_PRECISION)).cuda()
+    pts = torch.as_tensor(np.random.default_rng(synth.SEED_PRECISION).uniform(0.0, 1.0, size=(count, 2))).cuda()
+    out = plan.eval(u, pts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        plan.eval(u, pts, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / repeats
+    nb = 2 * n
+    tflops = 8.0 * nb * nb * count / dt / 1e12
+    return dict(workload=f"(A_n u)(x) at {count} uniform random points of D, {n}x{n} grid, log|x|, FP64",
+                targets_per_s=count / dt, ms_per_call=dt * 1e3,
+                roofline=dict(bound="alu", achieved=tflops, peak=PEAK_FP64_VECTOR_TFLOPS, unit="TFLOP/s",
+                              frac=tflops / PEAK_FP64_VECTOR_TFLOPS, traffic=None,
+                              note="whole call (spectrum pass + series sum), series flops only"))
+
+
 def run_ls_bench(api, torch, ns, kappas, repeats):
     import synth
     lat = {"fp64": [], "fp32+ir": []}
@@ -446,6 +474,7 @@ def main(argv=None):
     ap.add_argument("--ls-repeats", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-period3", action="store_true")
+    ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--period3-n", type=int, default=1024)
     ap.add_argument("--period3-batch", type=int, default=16)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -500,6 +529,11 @@ def main(argv=None):
                                         "pass_avg_ms", "pass_gbps", "densities_per_launch", "roofline")})
         log(f"period3: {r3['applies_per_s']:.1f} applies/s, pass model {r3['pass_model_gbps']:.0f} GB/s, "
             f"passes {r3['pass_avg_ms']}")
+    ev = None
+    if not args.no_eval:
+        log("off-grid evaluation bench (n=512, 4096 targets) ...")
+        ev = run_eval_bench(api, torch, 512, 4096)
+        log(f"eval: {ev['targets_per_s']:.0f} targets/s, {ev['roofline']['achieved']:.2f} TFLOP/s")
     ls = None
     if not args.no_ls:
         log("LS latency bench ...")
@@ -548,6 +582,8 @@ def main(argv=None):
                                             "roofline")}
     if p3 is not None:
         line["period3"] = p3
+    if ev is not None:
+        line["offgrid_eval"] = ev
     if ls is not None:
         line["ls_latency"] = ls
     if srv is not None:

@@ -222,6 +222,27 @@ int ls_solve_fs(ws_plan_t plan, const void* contrast_tilde, const ws_fs_desc* fs
                 double tol, int restart, int max_matvecs, int mixed_precision, void* u_out, void* work,
                 ws_ls_info* info, void* stream);
 
+/* Device scratch for conv_eval: the spectrum of one density (nb x nb
+ * complex128) plus the row-pass intermediate (n x nb complex128) and, for
+ * real-kernel plans, the density widened to complex.  WS_EUNSUPPORTED for
+ * WS_FP32 plans. */
+int conv_eval_query(ws_plan_t plan, size_t* work_bytes);
+
+/* (A_n u)(x) at `count` arbitrary points x of the plane (Section 2.1: the
+ * series of eq. An, sum_{k in F_n} ghat(k) uhat_{e,n}(k) e^{2 pi i k.x/b},
+ * read at x; the quadrature form of eqs. quad / quad_wts gives the same sum).
+ *  density: [n][n] samples of one density, as for conv_apply (FP64 plans).
+ *  targets: device [count][2] float64, (x1, x2) of each point (any real
+ *           values; the series is b-periodic).
+ *  out:     device [count] complex128.  F_n = [-nb/2, nb/2)^2 is not
+ *           symmetric, so off the grid the value is complex even for a real
+ *           density and kernel; at grid points it equals conv_apply's.
+ *  work:    conv_eval_query bytes, 256-byte aligned.
+ * Cost: one forward transform of the density, then |F_n| = (nb)^2 complex
+ * multiply-adds per target (direct summation, for modest target counts). */
+int conv_eval(ws_plan_t plan, const void* density, int count, const double* targets, void* out,
+              void* work, void* stream);
+
 /* Read back `count` moments ghat(k) (Section 2.2, eq. ghat) of a built plan,
  * for the integer frequencies (k1[i], k2[i]) in F_n, as computed on the device
  * (FP64, without the (nb)^-2 factor).  out: host array of 2*count doubles

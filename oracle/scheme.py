@@ -13,13 +13,15 @@ those steps in order: zero-extend the samples to the nb x nb periodic grid
 (eq. fc_discrete), take the forward DFT with the (nb)^-2 factor, multiply by
 ghat, take the inverse DFT at the grid points of D and restrict to G_n.
 
+``apply_at`` reads eq. An at arbitrary (also off-grid) targets, and
 ``apply_weights`` is the quadrature form of eqs. quad / quad_wts:
 (A_n u)(x) = sum_j w_j^n(x) u_j with
 w_j^n(x) = (nb)^-2 sum_k ghat(k) exp(2 pi i k.(x - x_j)/b),
 evaluated by brute force for any (also off-grid) target x.
 
 Pins (tests/test_oracle_scheme.py): apply == apply_weights (O(N^2) brute
-force) on small grids; agreement with a numpy.fft evaluation (third-party);
+force) on small grids; apply_at == apply_weights at off-grid targets and ==
+apply at grid points; agreement with a numpy.fft evaluation (third-party);
 the Laplace potential of a radial bump from Newton's formula (a 1D integral);
 Delta(A_n u) = -u for g = -(1/2pi) log via the spectral identity of the
 truncated kernel; linearity, circular shift and transpose equivariance; the
@@ -54,6 +56,27 @@ def apply(u: np.ndarray, ghat_full: np.ndarray, b: int) -> np.ndarray:
     prod = ghat_full * uhat                          # multiply by the moments
     full = _fft.fft2(prod, inverse=True)             # sum_k ... exp(+2 pi i k.j / nb)
     return full[..., :n, :n]                         # restrict to G_n
+
+
+def apply_at(u: np.ndarray, ghat_full: np.ndarray, b: int, targets: np.ndarray) -> np.ndarray:
+    """(A_n u)(x) for arbitrary targets x (shape (m, 2)): eq. An read at x.
+
+    The coefficients ghat(k) uhat_{e,n}(k) on F_n are formed as in ``apply``;
+    the series sum_k c(k) exp(2 pi i k.x / b) is then summed at each target,
+    over k2 first (a matrix product with the k2 exponentials) and then over k1.
+    F_n = [-nb/2, nb/2)^2 is not symmetric, so the result is complex even for
+    real u off the grid.
+    """
+    n = u.shape[-1]
+    nb = n * b
+    coef = ghat_full * (_fft.fft2(extend(u, b)) / float(nb * nb))
+    k = frequencies(nb).astype(np.float64)
+    out = np.empty(len(targets), dtype=np.complex128)
+    for t, (x1, x2) in enumerate(targets):
+        e1 = np.exp(2j * np.pi * k * x1 / b)
+        e2 = np.exp(2j * np.pi * k * x2 / b)
+        out[t] = e1 @ (coef @ e2)
+    return out
 
 
 def apply_weights(u: np.ndarray, ghat_full: np.ndarray, b: int,

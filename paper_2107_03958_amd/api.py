@@ -136,6 +136,27 @@ class ConvPlan:
             L.check(self.lib.conv_apply_pass(self.handle, pass_index, density.shape[0], _dev_ptr(density),
                                              _dev_ptr(out), _dev_ptr(work), _stream_ptr(stream)))
 
+    def eval(self, density: torch.Tensor, targets: torch.Tensor, out: torch.Tensor | None = None,
+             work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """(A_n u)(x) at arbitrary points (conv_eval): targets is a [count, 2] float64 tensor of
+        (x1, x2); returns a complex128 [count] tensor."""
+        if density.dtype != self.dtype or density.device != self.device or not density.is_contiguous() \
+                or density.shape != (self.n, self.n):
+            raise ValueError(f"density must be a contiguous ({self.n}, {self.n}) {self.dtype} tensor on {self.device}")
+        if targets.dtype != torch.float64 or targets.device != self.device or not targets.is_contiguous() \
+                or targets.dim() != 2 or targets.shape[1] != 2:
+            raise ValueError("targets must be a contiguous [count, 2] float64 tensor on the plan's device")
+        count = targets.shape[0]
+        res = out if out is not None else torch.empty(count, dtype=torch.complex128, device=self.device)
+        if work is None:
+            nbytes = ctypes.c_size_t()
+            L.check(self.lib.conv_eval_query(self.handle, ctypes.byref(nbytes)))
+            work = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(self.lib.conv_eval(self.handle, _dev_ptr(density), count, _dev_ptr(targets), _dev_ptr(res),
+                                       _dev_ptr(work), _stream_ptr(stream)))
+        return res
+
     def ls_workspace(self, restart: int, mixed: bool, fs: "FsDesc | None" = None) -> torch.Tensor:
         nbytes = ctypes.c_size_t()
         if fs is None:

@@ -488,6 +488,83 @@ __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, i
 }
 
 // ----------------------------------------------------------------------------
+// Spectrum pass of the evaluation at arbitrary points: one column k2 of the
+// complex-path row transform (n rows) -> its forward length-nb transform times
+// the moments, c(k1, k2) = ghat(k) uhat_{e,n}(k) (the (nb)^-2 of eq. An is in
+// the table), for every bin k1, stored row-major as spec[k1 * nb + k2].
+// RTAB: a real-kernel plan, whose table holds the columns |k2| < nb/2
+// (blocked) and the Nyquist column |k2| = nb/2 apart; else the complex table
+// of the Helmholtz plan, one column per bin.  A tile is one column (CPB = 1
+// geometry of the complex column pass); tiles past the end (valid = false)
+// load and store nothing but join every barrier.
+template <int LOGN, bool RTAB, int B>
+__device__ __forceinline__ void cols_spec_tile(const Seg<double>& sg, int t, bool valid, int tid,
+                                               cx<double>* lds, cx<double>* __restrict__ spec) {
+  using C = Cfg<double, LOGN, B>;
+  using LL = LineLayout<C::LF, C::EF>;
+  constexpr int nb = C::nb, N = C::NCOLS_R, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
+  constexpr int NB = stage_bases<L, E, 1>();
+  const ColGeo<double, LOGN, true, B> g(t, tid);
+  const int p = g.p, l = g.l;
+  const TwD tw = sg.tw;
+  cx<double>* line[1] = {lds + (B * g.cc + l) * S};
+  cx<double> wpre{}, wstep{}, wb[NB > 0 ? NB : 1];
+  if (l) {
+    wpre = tw.template get<-1>(p * l);
+    wstep = tw.template get<-1>(P * l);
+  }
+  load_bases<L, E, -1, 1>(wb, p, tw, B);
+  cx<double> x[E];
+  cols_load_data<double, LOGN, true, true, B>(sg, t, valid, tid, x);
+  cx<double> v[1][E];
+  {
+    cx<double> w[E];                                       // w_nb^{l j}, j = p + P s
+    if (l) run_from<E>(wpre, wstep, w);
+#pragma unroll
+    for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
+  }
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<double>*>(wb));
+  if (!valid) return;
+  const int k2 = g.cb * CB + g.c;                       // column bin
+#pragma unroll
+  for (int reg = 0; reg < E; ++reg) {
+    const int k1 = B * (p + P * slot_elem<E, RL>(reg)) + l;
+    const int k1f = k1 <= N ? k1 : nb - k1;
+    cx<double> gv;
+    if constexpr (RTAB) {
+      const int a2 = k2 <= N ? k2 : nb - k2;           // |k2|
+      const double r = a2 == N ? sg.gnyq[k1f]
+                               : static_cast<const double*>(sg.gtab)[((size_t)(a2 / CB) * (N + 1) + k1f) * CB + a2 % CB];
+      gv = {r, 0.0};
+    } else {
+      gv = static_cast<const cx<double>*>(sg.gtab)[((size_t)g.cb * (N + 1) + k1f) * CB + g.c];
+    }
+    spec[(size_t)k1 * nb + k2] = cmul(v[0][reg], gv);
+  }
+}
+
+template <int LOGN, bool RTAB, int B>
+__global__ __launch_bounds__((Single<double, kColsCplx, LOGN, B>::BLOCK)) void k_spec(
+    cx<double>* __restrict__ work, cx<double>* __restrict__ spec, const void* __restrict__ gtab,
+    const double* __restrict__ gnyq, TwD tw, int ntiles) {
+  using S1 = Single<double, kColsCplx, LOGN, B>;
+  __shared__ cx<double> lds[S1::LDS];
+  Seg<double> sg{};
+  sg.logn = LOGN;
+  sg.ntiles = ntiles;
+  sg.tw = tw;
+  sg.work = work;
+  sg.gtab = gtab;
+  sg.gnyq = gnyq;
+  const int sub = threadIdx.x / S1::NT, tid = threadIdx.x % S1::NT;
+  const int t = blockIdx.x * S1::TPB + sub;
+  const bool valid = t < ntiles;
+  cols_spec_tile<LOGN, RTAB, B>(sg, valid ? t : 0, valid, tid,
+                                lds + sub * KindOf<double, kColsCplx, B>::template lds_tile<LOGN>(), spec);
+}
+
+// ----------------------------------------------------------------------------
 // Real path, inverse row pass: half spectrum rows -> n real outputs.
 // With N = nb/2, Y(k + N) = conj Y(N - k) and
 // Z_k = (Y_k + Y_{k+N}) + i w_nb^{-k} (Y_k - Y_{k+N}), z = IDFT_N(Z) gives
@@ -1018,6 +1095,45 @@ template <typename T>
 hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
                             hipStream_t s) {
   return pass_cplx<T>(p, pass, batch, v, nullptr, (T)1, false, out, work, s, nullptr);
+}
+
+// Coefficients c(k) = ghat(k) uhat_{e,n}(k) on all of F_n for one complex
+// density v (FP64 plan): complex-path forward rows into `inter` (n x nb),
+// then the spectrum column pass into spec (nb x nb, row-major).
+template <int B>
+static hipError_t spectrum_b(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
+                             hipStream_t s) {
+  hipError_t e = launch_one<double, kRowsFwdCplx>(p, 1, v, nullptr, inter, s);
+  if (e != hipSuccess) return e;
+  const double* gnyq = p.cplx ? nullptr : p.gnyq64;
+  switch (p.logn) {
+#define WS_CASE(L)                                                                                  \
+  case L: {                                                                                         \
+    using S1 = Single<double, kColsCplx, L, B>;                                                     \
+    if constexpr (B == 2 || L <= kMaxLognB3) {                                                      \
+      const int ntiles = KindOf<double, kColsCplx, B>::template tiles_per_density<L>();              \
+      const int nblocks = (ntiles + S1::TPB - 1) / S1::TPB;                                         \
+      if (p.cplx)                                                                                   \
+        k_spec<L, false, B><<<nblocks, S1::BLOCK, 0, s>>>(inter, spec, p.g64, gnyq, TwD{p.tw64}, ntiles); \
+      else                                                                                          \
+        k_spec<L, true, B><<<nblocks, S1::BLOCK, 0, s>>>(inter, spec, p.g64, gnyq, TwD{p.tw64}, ntiles);  \
+      return hipGetLastError();                                                                     \
+    }                                                                                               \
+    return hipErrorInvalidValue;                                                                    \
+  }
+    WS_FOR_EACH_LOGN(WS_CASE)
+#undef WS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spectrum(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
+                           hipStream_t s) {
+  if (p.precision != WS_FP64 || p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
+  if (p.b == 2) return spectrum_b<2>(p, v, inter, spec, s);
+  if (p.b == 3) return spectrum_b<3>(p, v, inter, spec, s);
+  return hipErrorInvalidValue;
 }
 
 // Several plans in one set of launches: round r takes the r-th chunk of every

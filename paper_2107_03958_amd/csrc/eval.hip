@@ -1,0 +1,170 @@
+// Evaluation of A_n u at arbitrary points (Section 2.1: eq. An read at any x
+// in the plane; the quadrature form of eqs. quad / quad_wts gives the same
+// sum).  The coefficients c(k) = ghat(k) uhat_{e,n}(k) on F_n come from the
+// spectrum pass (apply.hip); this file sums the series
+//     (A_n u)(x) = sum_{k in F_n} c(k) exp(2 pi i k.x / b)
+// directly at each target: O(|F_n|) per target, for callers with modest
+// numbers of scattered points.  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
+// value is complex even for real u and a real kernel, except on the grid.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "plan.hpp"
+
+namespace ws {
+namespace {
+
+constexpr int kEvalThreads = 256;
+constexpr int kEvalTargets = 8;          // targets per block: every spectrum read serves this many
+constexpr int kReseed = 32;              // exact exponentials every 32 bins, products in between
+
+__global__ void k_real_to_cplx(const double* __restrict__ u, cx<double>* __restrict__ v, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = {u[i], 0.0};
+}
+
+// exp(2 pi i k x / b) for the frequency k of bin q (k = q, or q - nb past nb/2).
+__device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
+  const int k = q < nb / 2 ? q : q - nb;
+  double s, c;
+  sincospi(2.0 * (double)k * x_over_b, &s, &c);
+  return {c, s};
+}
+
+// Block: kEvalTargets targets; thread t sums the columns k2 = t, t + 256, ...:
+// sum over k1 of c(k1, k2) exp(2 pi i k1 x1/b) (exponentials by products,
+// re-seeded exactly every kReseed bins and at the jump to negative k1), times
+// exp(2 pi i k2 x2/b); then a block reduction per target.
+__global__ __launch_bounds__(kEvalThreads) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
+                                                       const double* __restrict__ targets, int count,
+                                                       cx<double>* __restrict__ out) {
+  __shared__ cx<double> red[kEvalTargets][kEvalThreads / 64];
+  const int t0 = blockIdx.x * kEvalTargets;
+  double x1[kEvalTargets], x2[kEvalTargets];
+  cx<double> step[kEvalTargets];
+#pragma unroll
+  for (int g = 0; g < kEvalTargets; ++g) {
+    const int ti = t0 + g < count ? t0 + g : count - 1;
+    x1[g] = targets[2 * (size_t)ti] * inv_b;
+    x2[g] = targets[2 * (size_t)ti + 1] * inv_b;
+    double s, c;
+    sincospi(2.0 * x1[g], &s, &c);
+    step[g] = {c, s};                                 // exp(2 pi i x1 / b): one bin further
+  }
+  cx<double> tot[kEvalTargets];
+#pragma unroll
+  for (int g = 0; g < kEvalTargets; ++g) tot[g] = {0.0, 0.0};
+  for (int k2 = threadIdx.x; k2 < nb; k2 += kEvalThreads) {
+    cx<double> acc[kEvalTargets], e1[kEvalTargets];
+#pragma unroll
+    for (int g = 0; g < kEvalTargets; ++g) acc[g] = {0.0, 0.0};
+    for (int k1 = 0; k1 < nb; ++k1) {
+      if (k1 % kReseed == 0 || k1 == nb / 2) {
+#pragma unroll
+        for (int g = 0; g < kEvalTargets; ++g) e1[g] = expo(k1, nb, x1[g]);
+      }
+      const cx<double> c = spec[(size_t)k1 * nb + k2];
+#pragma unroll
+      for (int g = 0; g < kEvalTargets; ++g) {
+        acc[g] = acc[g] + cmul(c, e1[g]);
+        e1[g] = cmul(e1[g], step[g]);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kEvalTargets; ++g) tot[g] = tot[g] + cmul(acc[g], expo(k2, nb, x2[g]));
+  }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int g = 0; g < kEvalTargets; ++g) {
+    double re = tot[g].x, im = tot[g].y;
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_down(re, off, 64);
+      im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) red[g][wave] = {re, im};
+  }
+  __syncthreads();
+  if (threadIdx.x < kEvalTargets && t0 + (int)threadIdx.x < count) {
+    cx<double> s{0.0, 0.0};
+    for (int w = 0; w < kEvalThreads / 64; ++w) s = s + red[threadIdx.x][w];
+    out[t0 + threadIdx.x] = s;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct EvalWork {
+  size_t widen, inter, spec, total;
+};
+
+EvalWork eval_work(const Plan& p) {
+  EvalWork w{};
+  const size_t n = p.n, nb = (size_t)p.b * p.n;
+  w.widen = p.cplx ? 0 : align256(n * n * sizeof(cx<double>));
+  w.inter = align256(n * nb * sizeof(cx<double>));
+  w.spec = align256(nb * nb * sizeof(cx<double>));
+  w.total = w.widen + w.inter + w.spec;
+  return w;
+}
+
+int eval_checks(ws_plan_t plan) {
+  if (!plan) return set_last_error(WS_EINVAL, "plan is NULL");
+  if (plan->precision != WS_FP64) return set_last_error(WS_EUNSUPPORTED, "conv_eval needs a WS_FP64 plan");
+  return WS_OK;
+}
+
+}  // namespace
+}  // namespace ws
+
+extern "C" {
+
+int conv_eval_query(ws_plan_t plan, size_t* work_bytes) {
+  ws::set_last_error(WS_OK, "");
+  const int rc = ws::eval_checks(plan);
+  if (rc) return rc;
+  if (work_bytes) *work_bytes = ws::eval_work(*plan).total;
+  return WS_OK;
+}
+
+int conv_eval(ws_plan_t plan, const void* density, int count, const double* targets, void* out, void* work,
+              void* stream) {
+  ws::set_last_error(WS_OK, "");
+  int rc = ws::eval_checks(plan);
+  if (rc) return rc;
+  if (count < 0) return ws::set_last_error(WS_EINVAL, "count must be >= 0");
+  if (count == 0) return WS_OK;
+  if (!density || !targets || !out || !work) return ws::set_last_error(WS_EINVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(density) | reinterpret_cast<uintptr_t>(targets) |
+       reinterpret_cast<uintptr_t>(out)) % 16 || reinterpret_cast<uintptr_t>(work) % 256)
+    return ws::set_last_error(WS_EINVAL, "density, targets and out must be 16-byte and work 256-byte aligned");
+  const ws::Plan& p = *plan;
+  const ws::EvalWork w = ws::eval_work(p);
+  char* base = static_cast<char*>(work);
+  ws::cx<double>* widen = reinterpret_cast<ws::cx<double>*>(base);
+  ws::cx<double>* inter = reinterpret_cast<ws::cx<double>*>(base + w.widen);
+  ws::cx<double>* spec = reinterpret_cast<ws::cx<double>*>(base + w.widen + w.inter);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ws::cx<double>* v = static_cast<const ws::cx<double>*>(density);
+  if (!p.cplx) {
+    const size_t nn = (size_t)p.n * p.n;
+    ws::k_real_to_cplx<<<(unsigned)((nn + 255) / 256 < 4096 ? (nn + 255) / 256 : 4096), 256, 0, s>>>(
+        static_cast<const double*>(density), widen, nn);
+    v = widen;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = ws::launch_spectrum(p, v, inter, spec, s);
+  if (e == hipSuccess) {
+    const int blocks = (count + ws::kEvalTargets - 1) / ws::kEvalTargets;
+    ws::k_eval<<<blocks, ws::kEvalThreads, 0, s>>>(spec, p.nb, 1.0 / p.b, targets, count,
+                                                   static_cast<ws::cx<double>*>(out));
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return ws::set_last_error(WS_EDEVICE, std::string("conv_eval: ") + hipGetErrorString(e));
+  return WS_OK;
+}
+
+}  // extern "C"

@@ -142,6 +142,12 @@ struct ApplyItem {
 template <typename T>
 hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipStream_t s);
 
+// Coefficients c(k) = ghat(k) uhat_{e,n}(k), k in F_n, of one complex density
+// v of an FP64 plan: spec is nb x nb complex, row-major over the bins (k1, k2);
+// inter is n x nb complex scratch (apply.hip).
+hipError_t launch_spectrum(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
+                           hipStream_t s);
+
 // Plan construction kernels (moments.hip).
 hipError_t launch_build_tables(Plan& p, hipStream_t s);
 

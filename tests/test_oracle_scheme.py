@@ -33,6 +33,38 @@ def test_apply_equals_quadrature_weights_bruteforce(n, b):
         assert abs(full[i, j] - v) < 1e-13 * np.max(np.abs(full))
 
 
+@pytest.mark.parametrize("n,b,kname", [(8, 2, "power"), (6, 3, "log"), (8, 2, "helmholtz")])
+def test_apply_at_equals_quadrature_weights_off_grid(n, b, kname):
+    # eq. An at off-grid points (series form) equals the quadrature-weight sum
+    # of eqs. quad/quad_wts, term by term; targets also outside D and on it
+    rng = np.random.default_rng(100 + n)
+    u = rng.normal(size=(n, n)) + (1j * rng.normal(size=(n, n)) if kname == "helmholtz" else 0.0)
+    a = (math.sqrt(2) + b - 1) / 2 if b >= 3 else A2
+    kern = {"power": moments.Kernel("power", 1.0, -0.5), "log": moments.Kernel("log", 1.0),
+            "helmholtz": moments.Kernel("helmholtz", 1.0, 0.0, 20.0)}[kname]
+    g = moments.ghat_table(kern, n, b, a)
+    pts = np.concatenate([rng.uniform(0.0, 1.0, size=(5, 2)), [[0.0, 0.0], [1.0, 0.5], [-0.3, 1.7]]])
+    at = scheme.apply_at(u, g, b, pts)
+    brute = scheme.apply_weights(u, g, b, pts)
+    assert np.max(np.abs(at - brute)) < 1e-12 * np.max(np.abs(brute))
+    # off the grid the sum over the asymmetric F_n is complex even for real u
+    if kname != "helmholtz":
+        assert np.max(np.abs(at[:5].imag)) > 1e-6 * np.max(np.abs(at))
+
+
+def test_apply_at_grid_points_equals_apply():
+    n, b = 16, 2
+    u = synth.smooth_density(n, 3)
+    g = moments.ghat_table(moments.Kernel("log", 1.0), n, b, A2)
+    full = scheme.apply(u, g, b)
+    idx = [(0, 0), (3, 11), (15, 15), (8, 0)]
+    pts = np.array([[i / n, j / n] for i, j in idx])
+    at = scheme.apply_at(u, g, b, pts)
+    for (i, j), v in zip(idx, at):
+        assert abs(full[i, j] - v) < 1e-13 * np.max(np.abs(full))
+        assert abs(v.imag) < 1e-13 * np.max(np.abs(full))
+
+
 def test_apply_matches_numpy_fft():
     n = 32
     u = synth.smooth_density(n, 5)
