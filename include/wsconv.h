@@ -49,6 +49,7 @@ extern "C" {
 #define WS_LOG       0   /* g(x) = scale * log|x|                               */
 #define WS_POWER     1   /* g(x) = scale * |x|^gamma,  -2 < gamma < 0           */
 #define WS_HELMHOLTZ 2   /* g(x) = scale * (i/4) H0^(1)(kappa |x|), kappa > 0   */
+#define WS_YUKAWA    3   /* g(x) = scale * K0(kappa |x|), kappa > 0 (Table yukawa: scale = 1/(2 pi)) */
 
 /* Arithmetic of the apply. */
 #define WS_FP64 0
@@ -65,10 +66,16 @@ extern "C" {
 #define WS_LS_BREAKDOWN 2
 
 typedef struct {
-    int    family;   /* WS_LOG, WS_POWER or WS_HELMHOLTZ */
+    int    family;   /* WS_LOG, WS_POWER, WS_HELMHOLTZ or WS_YUKAWA */
     double scale;    /* multiplies g */
     double gamma;    /* WS_POWER: exponent, -2 < gamma < 0 */
-    double kappa;    /* WS_HELMHOLTZ: wavenumber > 0 */
+    double kappa;    /* WS_HELMHOLTZ: wavenumber > 0; WS_YUKAWA: decay rate > 0 */
+    double beta;     /* real kernels: 0 for the global moments (closed forms of Section 2.2; for
+                        WS_YUKAWA the truncated moment int_0^a rho K0(kappa rho) J0(xi rho) d rho
+                        in closed form), or the localisation radius 0 < beta <= a of Section 2.3:
+                        the table is then ghat_eta(k) + Khat(k), the moments of g eta_beta by the
+                        trapezoidal rule after rho = beta tau^4, plus the DFT of the trapezoid
+                        samples of the smooth part g (1 - eta_beta) (see conv_plan) */
 } ws_kernel;
 
 typedef struct {
@@ -111,8 +118,10 @@ typedef struct ws_plan* ws_plan_t;
 
 /* Sizes of the caller-owned buffers for a plan.
  * plan_bytes: device buffer holding the kernel moments ghat(k) (Section 2.2)
- *   and the twiddle tables; work_bytes_per_density: device scratch for one
- *   density in conv_apply (the half-spectrum intermediate).
+ *   and the twiddle tables (with beta > 0 also the localised scheme's
+ *   construction scratch: the quadrature nodes and the n x n smooth-kernel
+ *   samples and their half-transformed copy); work_bytes_per_density: device
+ *   scratch for one density in conv_apply (the half-spectrum intermediate).
  * Returns WS_EINVAL / WS_EUNSUPPORTED for parameters conv_plan would reject. */
 int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
                     size_t* plan_bytes, size_t* work_bytes_per_density);
@@ -121,6 +130,14 @@ int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
  * Computes, on the device and in FP64, the moments ghat(k) for every k in
  * F_n scaled by (nb)^-2, in the layout the apply kernels read, plus the
  * twiddle tables; all of it is written into plan_buf (plan_bytes, device).
+ * With kernel->beta > 0 (real kernels) the table is that of the localised
+ * scheme (Section 2.3, eq. io_split): ghat_eta(k) = 2 pi int_0^beta g eta J0
+ * rho d rho by the trapezoidal rule in tau after rho = beta tau^4 (M + 1 nodes,
+ * M = max(768, ceil(4 beta pi sqrt(2) n))), plus Khat(k), the DFT over
+ * (-n, n)^2 of h^2 g(|m| h)(1 - eta_beta(|m| h)), h = 1/n; eta_beta is 1 on
+ * [0, beta/2] and the smooth step exp(2 e^(-1/t) / (t - 1)) of
+ * t = (rho - beta/2)/(beta/2) beyond.  Localised plans copy their quadrature
+ * nodes from the host and synchronise `stream` before returning.
  * The host-side plan object keeps raw pointers into plan_buf: the caller must
  * keep plan_buf alive until conv_destroy.  Enqueued on `stream`. */
 int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision,

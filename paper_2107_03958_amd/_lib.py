@@ -17,14 +17,15 @@ WS_EINVAL = -1
 WS_EUNSUPPORTED = -2
 WS_EDEVICE = -3
 
-WS_LOG, WS_POWER, WS_HELMHOLTZ = 0, 1, 2
+WS_LOG, WS_POWER, WS_HELMHOLTZ, WS_YUKAWA = 0, 1, 2, 3
 WS_FP64, WS_FP32 = 0, 1
 WS_FS_NONE, WS_FS_DISC, WS_FS_SQUARE = 0, 1, 2
 WS_LS_CONVERGED, WS_LS_MAXIT, WS_LS_BREAKDOWN = 0, 1, 2
 
 
 class WsKernel(ctypes.Structure):
-    _fields_ = [("family", c_int), ("scale", c_double), ("gamma", c_double), ("kappa", c_double)]
+    _fields_ = [("family", c_int), ("scale", c_double), ("gamma", c_double), ("kappa", c_double),
+                ("beta", c_double)]
 
 
 class WsGrid(ctypes.Structure):

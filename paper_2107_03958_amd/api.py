@@ -16,7 +16,7 @@ import torch
 
 from . import _lib as L
 
-_FAMILIES = {"log": L.WS_LOG, "power": L.WS_POWER, "helmholtz": L.WS_HELMHOLTZ}
+_FAMILIES = {"log": L.WS_LOG, "power": L.WS_POWER, "helmholtz": L.WS_HELMHOLTZ, "yukawa": L.WS_YUKAWA}
 _PRECISIONS = {"fp64": L.WS_FP64, "fp32": L.WS_FP32}
 
 
@@ -58,7 +58,7 @@ class ConvPlan:
 
     def __init__(self, family: str, n: int, b: int = 2, a: float = 0.0, scale: float = 1.0,
                  gamma: float = 0.0, kappa: float = 0.0, precision: str = "fp64",
-                 support_radius: float = 0.0, device="cuda", stream=None):
+                 support_radius: float = 0.0, device="cuda", stream=None, beta: float = 0.0):
         self.lib = L.load()
         self.family = family
         self.n = n
@@ -68,7 +68,7 @@ class ConvPlan:
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
-        self.kernel = L.WsKernel(_FAMILIES[family], scale, gamma, kappa)
+        self.kernel = L.WsKernel(_FAMILIES[family], scale, gamma, kappa, beta)
         self.grid = L.WsGrid(n, b, a, support_radius)
         prec = _PRECISIONS[precision]
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()

@@ -38,6 +38,10 @@ int check_kernel(const ws_kernel* k) {
       return WS_OK;
     case WS_HELMHOLTZ:
       if (!(k->kappa > 0.0) || !std::isfinite(k->kappa)) return fail(WS_EINVAL, "Helmholtz kernel needs kappa > 0");
+      if (k->beta != 0.0) return fail(WS_EUNSUPPORTED, "localised moments are implemented for real kernels");
+      return WS_OK;
+    case WS_YUKAWA:
+      if (!(k->kappa > 0.0) || !std::isfinite(k->kappa)) return fail(WS_EINVAL, "Yukawa kernel needs kappa > 0");
       return WS_OK;
     default: return fail(WS_EINVAL, "unknown kernel family");
   }
@@ -64,7 +68,18 @@ struct Sizes {
   size_t tw64, tw32, g64, nyq64, g32, nyq32, total, work;
 };
 
-Sizes sizes_for(int n, int b, bool cplx, int precision) {
+// The localisation radius against the grid: 0 < beta <= a, and at most
+// kMaxLocalNodes quadrature intervals.
+int check_beta(const ws_kernel* k, int n, double a) {
+  if (k->beta == 0.0) return WS_OK;
+  if (!(k->beta > 0.0) || !std::isfinite(k->beta)) return fail(WS_EINVAL, "beta must be 0 or positive");
+  if (k->beta > a) return fail(WS_EINVAL, "localisation radius beta must not exceed the truncation radius a");
+  if (ws::local_nodes(n, k->beta) > ws::kMaxLocalNodes)
+    return fail(WS_EUNSUPPORTED, "beta too large for this n (more than 16384 quadrature intervals)");
+  return WS_OK;
+}
+
+Sizes sizes_for(int n, int b, bool cplx, int precision, double beta = 0.0) {
   Sizes s{};
   const size_t nb = (size_t)b * n;
   const size_t te = ws::table_elems(n, b, cplx);
@@ -75,6 +90,7 @@ Sizes sizes_for(int n, int b, bool cplx, int precision) {
   s.g32 = precision == WS_FP32 ? align_up(te * (cplx ? 8 : 4)) : 0;
   s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((nb / 2 + 1) * 4) : 0;
   s.total = s.tw64 + s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
+  if (beta > 0.0) s.total += ws::local_scratch_bytes(n, b, beta);
   const size_t elem = precision == WS_FP32 ? 8 : 16;
   s.work = (size_t)n * ws::inter_cols(n, b, cplx) * elem;
   return s;
@@ -114,7 +130,8 @@ int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
   if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
-  const Sizes s = sizes_for(grid->n, grid->b, kernel->family == WS_HELMHOLTZ, precision);
+  if ((rc = check_beta(kernel, grid->n, a))) return rc;
+  const Sizes s = sizes_for(grid->n, grid->b, kernel->family == WS_HELMHOLTZ, precision, kernel->beta);
   if (plan_bytes) *plan_bytes = s.total;
   if (work_bytes_per_density) *work_bytes_per_density = s.work;
   return WS_OK;
@@ -132,11 +149,13 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
   if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
+  if ((rc = check_beta(kernel, grid->n, a))) return rc;
   if (!plan_buf) return fail(WS_EINVAL, "plan buffer is NULL");
   if (reinterpret_cast<uintptr_t>(plan_buf) % 256) return fail(WS_EINVAL, "plan buffer must be 256-byte aligned");
   const bool cplx = kernel->family == WS_HELMHOLTZ;
-  const Sizes s = sizes_for(grid->n, grid->b, cplx, precision);
+  const Sizes s = sizes_for(grid->n, grid->b, cplx, precision, kernel->beta);
   auto* p = new ws_plan();
+  p->beta = kernel->beta;
   p->kern = *kernel;
   p->n = grid->n;
   p->b = grid->b;
@@ -167,6 +186,7 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
       off += s.nyq32;
     }
   }
+  if (p->beta > 0.0) p->local = base + off;
   p->plan_bytes = s.total;
   p->work_bytes = s.work;
   int dev = 0, cus = 0;

@@ -23,6 +23,10 @@
 //                 truncated; below 1e-17 relative for z >= 48).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "plan.hpp"
 
 namespace ws {
@@ -32,6 +36,8 @@ struct KernelArgs {
   double scale, gamma, kappa, a, b;
   // Helmholtz constants at kappa a.
   double j0ka, j1ka, y0ka, y1ka;
+  // Yukawa constants K0, K1 at kappa a.
+  double k0ka, k1ka;
   // power kernels
   int p;              // substitution exponent
   double ginf_coef;   // 2^(1+gamma) Gamma(1+gamma/2) / Gamma(-gamma/2)
@@ -144,10 +150,21 @@ __device__ inline double power_moment(double kabs, const KernelArgs& K) {
   return 2.0 * M_PI * (z < 48.0 ? power_moment_quad(xi, mu, K) : power_moment_asym(xi, mu, K));
 }
 
+// 2 pi int_0^a rho K0(kappa rho) J0(xi rho) d rho in closed form: with
+// F(rho) = rho (xi J1(xi rho) K0(kappa rho) - kappa J0(xi rho) K1(kappa rho)),
+// F' = (xi^2 + kappa^2) rho J0 K0 and F(0+) = -1 (rho kappa K1(kappa rho) -> 1).
+__device__ inline double yukawa_moment(double kabs, const KernelArgs& K) {
+  const double a = K.a, kap = K.kappa;
+  const double xi = 2.0 * M_PI * kabs / K.b;
+  const double num = 1.0 + a * xi * j1(xi * a) * K.k0ka - a * kap * j0(xi * a) * K.k1ka;
+  return 2.0 * M_PI * num / (xi * xi + kap * kap);
+}
+
 // Moment of scale * g at |k|, times inv = nb^-2.
 __device__ inline cx<double> moment(double kabs, const KernelArgs& K, double inv) {
   if (K.family == WS_LOG) return {-2.0 * M_PI * K.scale * log_moment(kabs, K) * inv, 0.0};
   if (K.family == WS_POWER) return {K.scale * power_moment(kabs, K) * inv, 0.0};
+  if (K.family == WS_YUKAWA) return {K.scale * yukawa_moment(kabs, K) * inv, 0.0};
   const cx<double> h = helmholtz_moment(kabs, K);
   return {K.scale * h.x * inv, K.scale * h.y * inv};
 }
@@ -187,6 +204,198 @@ __global__ void k_table(int nb, int ncols, KernelArgs K, double inv, int cplx, d
   }
 }
 
+// ----------------------------------------------------------------------------
+// Localised scheme (Section 2.3, eq. io_split): table = ghat_eta(k) + Khat(k).
+
+// K0 for x > 0: the power series about 0 for x <= 2,
+//   K0(x) = -(log(x/2) + euler_gamma) I0(x) + sum_{k>=1} (x^2/4)^k / (k!)^2 H_k,
+// else the trapezoidal rule on K0(x) = e^-x int_0^inf exp(-2 x sinh^2(t/2)) dt
+// with step min(0.2, 0.7/sqrt(x)): the integrand is analytic in |Im t| < pi/2
+// and near t = 0 a Gaussian of width 1/sqrt(x), which the step resolves
+// (about 2e-15 relative against a reference implementation over [1e-8, 700]).
+__device__ inline double k0_dev(double x) {
+  if (x <= 2.0) {
+    const double t = 0.25 * x * x;
+    double term = 1.0, i0 = 1.0, s = 0.0, hk = 0.0;
+    for (int k = 1; k < 40; ++k) {
+      term *= t / ((double)k * k);
+      hk += 1.0 / k;
+      i0 += term;
+      s += term * hk;
+      if (term * hk < 1e-18 * s) break;
+    }
+    return -(log(0.5 * x) + 0.57721566490153286061) * i0 + s;
+  }
+  const double h = fmin(0.2, 0.7 / sqrt(x));
+  double sum = 0.5;
+  for (int j = 1; j < 400; ++j) {
+    const double sh = sinh(0.5 * j * h);
+    const double v = exp(-2.0 * x * sh * sh);
+    sum += v;
+    if (v < 1e-18 * sum) break;
+  }
+  return h * sum * exp(-x);
+}
+
+// The kernel without its scale, g(rho), for the real families.
+__device__ inline double g_dev(double rho, int family, double gamma, double kappa) {
+  if (family == WS_LOG) return log(rho);
+  if (family == WS_POWER) return pow(rho, gamma);
+  return k0_dev(kappa * rho);                       // WS_YUKAWA
+}
+
+// eta_beta: 1 on [0, beta/2], 0 beyond beta, the smooth step exp(2 e^(-1/t)/(t - 1)) between.
+__host__ __device__ inline double eta_window(double rho, double beta) {
+  const double t = (rho - 0.5 * beta) / (0.5 * beta);
+  if (t <= 0.0) return 1.0;
+  if (t >= 1.0) return 0.0;
+  return exp(2.0 * exp(-1.0 / t) / (t - 1.0));
+}
+
+// Trapezoid samples of the smooth part, with the weight 2 of the mirror
+// images m -> -m: ks[m1 n + m2] = w(m1) w(m2) h^2 g(|m| h)(1 - eta_beta(|m| h)).
+__global__ void k_smooth_samples(int n, int family, double gamma, double kappa, double beta, double* ks) {
+  const double h = 1.0 / n;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+    const int m1 = e / n, m2 = e % n;
+    const double r = h * sqrt((double)m1 * m1 + (double)m2 * m2);
+    double v = 0.0;
+    if (r > 0.0) v = h * h * g_dev(r, family, gamma, kappa) * (1.0 - eta_window(r, beta));
+    ks[e] = (m1 ? 2.0 : 1.0) * (m2 ? 2.0 : 1.0) * v;
+  }
+}
+
+// out(i, j) = sum_{l < L} cos(2 pi i l / nb) B[j L + l] for i < I, j < J (the
+// cosines from the twiddle table), handed to epi(i, j, value).  64 x 64 output
+// tiles, 16 x 16 threads with 4 x 4 outputs each, 16-wide slices of l in LDS.
+template <typename EPI>
+__global__ __launch_bounds__(256) void k_cos_gemm(int I, int J, int L, int nb, const cx<double>* __restrict__ tw,
+                                                  const double* __restrict__ B, EPI epi) {
+  __shared__ double as[16][65];
+  __shared__ double bs[16][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  double acc[4][4] = {};
+  for (int l0 = 0; l0 < L; l0 += 16) {
+    for (int idx = threadIdx.x; idx < 16 * 64; idx += 256) {
+      const int li = idx / 64, ii = idx % 64;
+      const int i = i0 + ii, l = l0 + li;
+      as[li][ii] = (i < I && l < L) ? tw[(int)(((long long)i * l) % nb)].x : 0.0;
+      const int jj = idx / 16, lj = idx % 16;
+      const int j = j0 + jj, l2 = l0 + lj;
+      bs[lj][jj] = (j < J && l2 < L) ? B[(size_t)j * L + l2] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int li = 0; li < 16; ++li) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = as[li][ty * 4 + q];
+        bv[q] = bs[li][tx * 4 + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += av[p] * bv[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + ty * 4 + p, j = j0 + tx * 4 + q;
+      if (i < I && j < J) epi(i, j, acc[p][q]);
+    }
+}
+
+struct StoreRows {             // T[i][j], row length J
+  double* t;
+  int J;
+  __device__ void operator()(int i, int j, double v) const { t[(size_t)i * J + j] = v; }
+};
+
+// Table entry (k1f = i, k2 = j) of a real plan, i, j in [0, N]:
+// (ghat_eta(|k|) + Khat(k)) scale / nb^2, with ghat_eta by the node sums.
+template <int CB64, int CB32>
+struct StoreLocalTable {
+  int N;
+  double b, scale, inv;
+  int nodes;
+  const double* rho;
+  const double* c;
+  double *g64, *nyq64;
+  float *g32, *nyq32;
+  __device__ void operator()(int i, int j, double khat) const {
+    const double xi = 2.0 * M_PI * sqrt((double)i * i + (double)j * j) / b;
+    double ge = 0.0;
+    for (int q = 0; q < nodes; ++q) ge += c[q] * j0(xi * rho[q]);
+    const double v = (ge + khat) * scale * inv;
+    if (j == N) {
+      if (nyq64) nyq64[i] = v;
+      if (nyq32) nyq32[i] = (float)v;
+    } else {
+      if (g64) g64[((size_t)(j / CB64) * (N + 1) + i) * CB64 + j % CB64] = v;
+      if (g32) g32[((size_t)(j / CB32) * (N + 1) + i) * CB32 + j % CB32] = (float)v;
+    }
+  }
+};
+
+int local_nodes(int n, double beta) {
+  const double m = std::ceil(4.0 * beta * M_PI * std::sqrt(2.0) * n);
+  return (int)std::max(768.0, m);
+}
+
+size_t local_scratch_bytes(int n, int b, double beta) {
+  const size_t M = (size_t)local_nodes(n, beta) + 1, N = (size_t)b * n / 2;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return 2 * al(M * sizeof(double)) + al((size_t)n * n * sizeof(double)) + al((N + 1) * n * sizeof(double));
+}
+
+// Host: the nodes rho_j = beta tau_j^4 and coefficients c_j = 2 pi w_j g(rho_j)
+// eta(rho_j) rho_j d rho/d tau of the trapezoidal rule in tau (M intervals).
+static double g_host(double rho, const KernelArgs& K) {
+  if (K.family == WS_LOG) return std::log(rho);
+  if (K.family == WS_POWER) return std::pow(rho, K.gamma);
+  return std::cyl_bessel_k(0.0, K.kappa * rho);
+}
+
+static hipError_t build_local(Plan& pl, const KernelArgs& K, hipStream_t s) {
+  const int n = pl.n, nb = pl.nb, N = nb / 2, M = local_nodes(n, pl.beta);
+  const double beta = pl.beta;
+  std::vector<double> rho(M + 1, 0.0), c(M + 1, 0.0);
+  for (int j = 1; j < M; ++j) {
+    const double tau = (double)j / M;
+    const double r = beta * tau * tau * tau * tau;
+    const double jac = 4.0 * beta * tau * tau * tau;
+    rho[j] = r;
+    c[j] = 2.0 * M_PI * (1.0 / M) * g_host(r, K) * eta_window(r, beta) * r * jac;
+  }
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* base = static_cast<char*>(pl.local);
+  double* drho = reinterpret_cast<double*>(base);
+  double* dc = reinterpret_cast<double*>(base + al((M + 1) * sizeof(double)));
+  double* ks = reinterpret_cast<double*>(base + 2 * al((M + 1) * sizeof(double)));
+  double* t = reinterpret_cast<double*>(base + 2 * al((M + 1) * sizeof(double)) + al((size_t)n * n * sizeof(double)));
+  hipError_t e = hipMemcpyAsync(drho, rho.data(), (M + 1) * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dc, c.data(), (M + 1) * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  k_smooth_samples<<<std::min((n * n + 255) / 256, 4096), 256, 0, s>>>(n, K.family, K.gamma, K.kappa, beta, ks);
+  // T[k][m1] = sum_m2 cos(2 pi k m2 / nb) ks[m1][m2],  k in [0, N]
+  dim3 g1((n + 63) / 64, (N + 1 + 63) / 64);
+  k_cos_gemm<<<g1, 256, 0, s>>>(N + 1, n, n, nb, pl.tw64, ks, StoreRows{t, n});
+  // Khat(k1, k2) = sum_m1 cos(2 pi k1 m1 / nb) T[k2][m1]
+  StoreLocalTable<Layout<double>::CB, Layout<float>::CB> st{N, (double)pl.b, K.scale, 1.0 / ((double)nb * nb), M + 1,
+                                                           drho, dc, (double*)pl.g64, pl.gnyq64,
+                                                           (float*)pl.g32, pl.gnyq32};
+  dim3 g2((N + 1 + 63) / 64, (N + 1 + 63) / 64);
+  k_cos_gemm<<<g2, 256, 0, s>>>(N + 1, N + 1, n, nb, pl.tw64, t, st);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);          // the host node arrays are released on return
+}
+
 __global__ void k_twiddles(int nb, cx<double>* t64, TwPair* t32) {
   for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nb; m += gridDim.x * blockDim.x) {
     double s, c;
@@ -216,6 +425,10 @@ hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
   K.kappa = pl.kern.kappa;
   K.a = pl.a;
   K.b = pl.b;
+  if (K.family == WS_YUKAWA) {
+    K.k0ka = std::cyl_bessel_k(0.0, K.kappa * K.a);
+    K.k1ka = std::cyl_bessel_k(1.0, K.kappa * K.a);
+  }
   if (K.family == WS_HELMHOLTZ) {
     const double ka = K.kappa * K.a;
     K.j0ka = ::j0(ka);
@@ -231,6 +444,7 @@ hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
   const double inv = 1.0 / ((double)nb * nb);
   const int threads = 256;
   k_twiddles<<<(nb + threads - 1) / threads, threads, 0, s>>>(nb, pl.tw64, pl.tw32);
+  if (pl.beta > 0.0) return build_local(pl, K, s);
   const int ncols = (int)inter_cols(n, pl.b, pl.cplx);
   const size_t total = (size_t)ncols * (nb / 2 + 1);
   const int blocks = (int)std::min<size_t>((total + threads - 1) / threads, 65536);

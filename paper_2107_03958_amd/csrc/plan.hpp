@@ -76,6 +76,8 @@ struct Plan {
   double a = 0;
   int precision = WS_FP64;
   bool cplx = false;          // Helmholtz: complex densities, c2c path
+  double beta = 0;            // > 0: localised moments (Section 2.3) with window radius beta
+  void* local = nullptr;      // localised plans: construction scratch in the plan buffer
   // Device pointers into the caller's plan buffer.
   void* g64 = nullptr;        // moments / nb^2, FP64 (real or complex), blocked layout
   double* gnyq64 = nullptr;   // real path: column k2 = nb/2 (Nyquist), rows k1' in [0, n]
@@ -147,6 +149,12 @@ hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipS
 // inter is n x nb complex scratch (apply.hip).
 hipError_t launch_spectrum(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
                            hipStream_t s);
+
+// Localised moments: trapezoid intervals in tau of ghat_eta, and the plan-buffer
+// scratch of the construction (nodes, smooth-kernel samples, half transform).
+int local_nodes(int n, double beta);
+size_t local_scratch_bytes(int n, int b, double beta);
+constexpr int kMaxLocalNodes = 16384;
 
 // Plan construction kernels (moments.hip).
 hipError_t launch_build_tables(Plan& p, hipStream_t s);

@@ -89,7 +89,8 @@ int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
   q.key.family = r->kernel.family;
   q.key.scale = r->kernel.scale;
   q.key.gamma = r->kernel.family == WS_POWER ? r->kernel.gamma : 0.0;
-  q.key.kappa = cplx ? r->kernel.kappa : 0.0;
+  q.key.kappa = (cplx || r->kernel.family == WS_YUKAWA) ? r->kernel.kappa : 0.0;
+  q.key.beta = r->kernel.beta;
   q.key.n = r->n;
   q.key.precision = cfg.precision;
   q.plan_bytes = plan_bytes;

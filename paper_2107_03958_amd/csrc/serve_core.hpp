@@ -85,11 +85,11 @@ class Arena {
 // default truncation radius).
 struct PlanKey {
   int family = 0;
-  double scale = 1, gamma = 0, kappa = 0;
+  double scale = 1, gamma = 0, kappa = 0, beta = 0;
   int n = 0, precision = 0;
   bool operator<(const PlanKey& o) const {
-    return std::tie(family, scale, gamma, kappa, n, precision) <
-           std::tie(o.family, o.scale, o.gamma, o.kappa, o.n, o.precision);
+    return std::tie(family, scale, gamma, kappa, beta, n, precision) <
+           std::tie(o.family, o.scale, o.gamma, o.kappa, o.beta, o.n, o.precision);
   }
   bool operator==(const PlanKey& o) const { return !(*this < o) && !(o < *this); }
 };

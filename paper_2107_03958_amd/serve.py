@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": L.WS_FP64, "fp32": L.WS_FP32}
 def _kernel(spec: dict) -> L.WsKernel:
     fam = FAMILIES[spec["family"]]
     return L.WsKernel(fam, float(spec.get("scale", 1.0)), float(spec.get("gamma", 0.0)),
-                      float(spec.get("kappa", 0.0)))
+                      float(spec.get("kappa", 0.0)), float(spec.get("beta", 0.0)))
 
 
 def _host(t: torch.Tensor, dtype: torch.dtype, n: int, what: str) -> torch.Tensor:
