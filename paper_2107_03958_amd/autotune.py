@@ -1,7 +1,8 @@
 """Autotuner for the apply kernels' compile-time tile shapes.
 
 The tile shapes (column-block width CB, rows per row tile RPB, elements per
-thread ER/EC, which fix the radix plan of every line, the column-tile mapping
+thread ER/EC (and ERF, the forward real row pass's own ER), which fix the radix
+plan of every line, the column-tile mapping
 CPB, the smallest block WS_MIN_BLOCK and the chunk of the intermediate kept in
 the last-level cache) are template constants: they size register arrays and
 LDS.  Tuning is therefore offline: variant libraries are compiled with -D
@@ -31,8 +32,9 @@ TUNED = os.path.join(HERE, "csrc", "tuned.hpp")
 
 # Parameters per precision and the values tried around the current one.
 PARAMS = {
-    "fp64": {"WS_CB64": [2, 4], "WS_RPB64": [1, 2, 4], "WS_ER64": [8, 16], "WS_EC64": [8, 16], "WS_CPB64": [0, 1]},
-    "fp32": {"WS_CB32": [2, 4, 8], "WS_RPB32": [1, 2, 4], "WS_ER32": [8, 16], "WS_EC32": [8, 16],
+    "fp64": {"WS_CB64": [2, 4], "WS_RPB64": [1, 2, 4], "WS_ER64": [8, 16], "WS_ERF64": [8, 16], "WS_EC64": [8, 16],
+             "WS_CPB64": [0, 1]},
+    "fp32": {"WS_CB32": [2, 4, 8], "WS_RPB32": [1, 2, 4], "WS_ER32": [8, 16], "WS_ERF32": [8, 16], "WS_EC32": [8, 16],
              "WS_CPB32": [0, 1]},
     "both": {"WS_MIN_BLOCK": [64, 128, 256], "WS_CHUNK_BYTES": ["(64u<<20)", "(128u<<20)", "(192u<<20)"]},
 }

@@ -141,9 +141,9 @@ __device__ __forceinline__ int pos_of(int k) {
 template <typename T, int LOGN, bool GUARD, int B = 2>
 __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds) {
   using C = Cfg<T, LOGN, B>;
-  using LL = LineLayout<C::LH, C::EH>;
-  constexpr int n = C::n, N = C::NCOLS_R, L = C::LH, E = C::EH, P = C::PH, RPB = C::RPB, CB = C::CB;
-  constexpr int NT = C::NT_RH, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
+  using LL = LineLayout<C::LH, C::EHF>;
+  constexpr int n = C::n, N = C::NCOLS_R, L = C::LH, E = C::EHF, P = C::PHF, RPB = C::RPB, CB = C::CB;
+  constexpr int NT = C::NT_RHF, R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
   constexpr int TPD = n / RPB, TWS = C::nb / L;
   const int p = tid % P, l = (tid / P) % B, r = tid / (B * P);
   const auto tw = sg.tw;

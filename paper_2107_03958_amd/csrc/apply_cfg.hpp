@@ -36,6 +36,11 @@ struct Cfg {
   static constexpr int NT_RH = B * RPB * PH;
   static constexpr int SH_ = LineLayout<LH, EH>::STRIDE;     // LDS elements per half-length line
   static constexpr int LDS_RH = B * RPB * SH_;               // LDS elements per real row tile
+  // The forward real row pass may use its own elements per thread (ERF).
+  static constexpr int EHF = cap(Layout<T>::ERF, B * RPB, LH);
+  static constexpr int PHF = LH / EHF;
+  static constexpr int NT_RHF = B * RPB * PHF;
+  static constexpr int LDS_RHF = B * RPB * LineLayout<LH, EHF>::STRIDE;
   // Column passes: B full-length lines per column, CPB columns per tile
   // (CPB = CB, or 1 with XCD-paired tiles).
   static constexpr int CPB = Layout<T>::CPB1 ? 1 : CB;
@@ -74,7 +79,7 @@ struct Blk {
   template <int... L>
   static constexpr int max_nt(int which, std::integer_sequence<int, L...>) {
     int m = 64;
-    ((m = std::max(m, which == 0 ? Cfg<T, L + kMinLogn>::NT_RH
+    ((m = std::max(m, which == 0 ? std::max(Cfg<T, L + kMinLogn>::NT_RH, Cfg<T, L + kMinLogn>::NT_RHF)
                       : which == 1 ? Cfg<T, L + kMinLogn>::NT_C : Cfg<T, L + kMinLogn>::NT_RC)), ...);
     return m;
   }
@@ -85,7 +90,8 @@ struct Blk {
   template <int... L>
   static constexpr int max_lds(int which, std::integer_sequence<int, L...>) {
     int m = 0;
-    ((m = std::max(m, which == 0 ? (RH / Cfg<T, L + kMinLogn>::NT_RH) * Cfg<T, L + kMinLogn>::LDS_RH
+    ((m = std::max(m, which == 0 ? std::max((RH / Cfg<T, L + kMinLogn>::NT_RH) * Cfg<T, L + kMinLogn>::LDS_RH,
+                                            (RH / Cfg<T, L + kMinLogn>::NT_RHF) * Cfg<T, L + kMinLogn>::LDS_RHF)
                       : which == 1 ? (C / Cfg<T, L + kMinLogn>::NT_C) * Cfg<T, L + kMinLogn>::LDS_C
                                    : (RC / Cfg<T, L + kMinLogn>::NT_RC) * Cfg<T, L + kMinLogn>::LDS_RC)), ...);
     return m;
@@ -160,12 +166,12 @@ struct KindOf {
   template <int LOGN>
   static constexpr int nt() {
     using C = Cfg<T, LOGN, B>;
-    return ROWS_R ? C::NT_RH : ROWS_C ? C::NT_RC : C::NT_C;
+    return K == kRowsFwdReal ? C::NT_RHF : ROWS_R ? C::NT_RH : ROWS_C ? C::NT_RC : C::NT_C;
   }
   template <int LOGN>
   static constexpr int lds_tile() {
     using C = Cfg<T, LOGN, B>;
-    return ROWS_R ? C::LDS_RH : ROWS_C ? C::LDS_RC : C::LDS_C;
+    return K == kRowsFwdReal ? C::LDS_RHF : ROWS_R ? C::LDS_RH : ROWS_C ? C::LDS_RC : C::LDS_C;
   }
   // tiles of a density, and consecutive tiles that share 128-byte lines of the intermediate
   template <int LOGN>

@@ -16,7 +16,7 @@ namespace ws {
 //       writes RPB x CB contiguous elements per block.
 //  RPB: rows per block of the row passes.
 //  ER / EC: elements per thread of a row / column line (raised where needed to keep
-//       a block within 1024 threads).
+//       a block within 1024 threads); ERF: the forward real row pass's own ER.
 //  CPB: 1 = a column-pass block transforms one column and the CB blocks of a
 //       block-column run 8 apart (same XCD, shared L2 lines); 0 = one block
 //       transforms all CB columns of a block-column.
@@ -55,6 +55,13 @@ namespace ws {
 #ifndef WS_CPB64
 #define WS_CPB64 1
 #endif
+// Elements per thread of the forward real row pass (default: that of the inverse, ER).
+#ifndef WS_ERF64
+#define WS_ERF64 WS_ER64
+#endif
+#ifndef WS_ERF32
+#define WS_ERF32 WS_ER32
+#endif
 #ifndef WS_CPB32
 #define WS_CPB32 1
 #endif
@@ -64,10 +71,10 @@ namespace ws {
 
 template <typename T> struct Layout;
 template <> struct Layout<double> {
-  static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, EC = WS_EC64, CPB1 = WS_CPB64;
+  static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, ERF = WS_ERF64, EC = WS_EC64, CPB1 = WS_CPB64;
 };
 template <> struct Layout<float> {
-  static constexpr int CB = WS_CB32, RPB = WS_RPB32, ER = WS_ER32, EC = WS_EC32, CPB1 = WS_CPB32;
+  static constexpr int CB = WS_CB32, RPB = WS_RPB32, ER = WS_ER32, ERF = WS_ERF32, EC = WS_EC32, CPB1 = WS_CPB32;
 };
 
 struct Plan {

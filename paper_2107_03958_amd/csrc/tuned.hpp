@@ -1,6 +1,9 @@
 // Tile shapes chosen by paper_2107_03958_amd/autotune.py on MI355X (gfx950),
 // timing the three apply passes at n = 2048; one parameter changed at a time
-// from the previous shapes, kept when more than 1% faster.
+// from the previous shapes, kept when more than 1% faster.  WS_ERF64 (the
+// forward real row pass's own elements per thread) was split from WS_ER64 after
+// a sweep showed ER 16 faster for that pass alone (25.6 / 24.6 against
+// 27.0 / 27.4 us per density at n = 2048, two runs each).
 #pragma once
 #ifndef WS_CB32
 #define WS_CB32 2
@@ -28,6 +31,9 @@
 #endif
 #ifndef WS_ER64
 #define WS_ER64 8
+#endif
+#ifndef WS_ERF64
+#define WS_ERF64 16
 #endif
 #ifndef WS_MIN_BLOCK
 #define WS_MIN_BLOCK 64

@@ -25,7 +25,7 @@
 
 using namespace ws;
 
-enum { kRowsReal = 0, kRowsCplx = 1, kColsRealK = 2, kColsCplxK = 3 };
+enum { kRowsReal = 0, kRowsCplx = 1, kColsRealK = 2, kColsCplxK = 3, kRowsRealF = 4 };
 
 // Launch shapes of the single-size kernel of pass kind K at size 2^LOGN.
 template <typename T, int LOGN, int K>
@@ -54,14 +54,16 @@ template <typename T, int LOGN, int KIND>
 void check(int batch) {
   const char* tname = sizeof(T) == 8 ? "double" : "float";
   using C = Cfg<T, LOGN>;
-  constexpr bool ROWS = KIND == kRowsReal || KIND == kRowsCplx;
-  constexpr int NT = KIND == kRowsReal ? C::NT_RH : KIND == kRowsCplx ? C::NT_RC : C::NT_C;
-  constexpr int BLK = KIND == kRowsReal ? Blk<T>::RH : KIND == kRowsCplx ? Blk<T>::RC : Blk<T>::C;
-  constexpr int LDS_TILE = KIND == kRowsReal ? C::LDS_RH : KIND == kRowsCplx ? C::LDS_RC : C::LDS_C;
-  constexpr int LDS_BLK = KIND == kRowsReal ? Blk<T>::LDS_RH : KIND == kRowsCplx ? Blk<T>::LDS_RC : Blk<T>::LDS_C;
-  constexpr int UNITS = KIND == kRowsReal ? C::RPB : KIND == kRowsCplx ? C::RPBC : C::CPB;
+  // kRowsRealF: the forward real row pass, with its own elements per thread
+  constexpr bool RR = KIND == kRowsReal || KIND == kRowsRealF;
+  constexpr bool ROWS = RR || KIND == kRowsCplx;
+  constexpr int NT = KIND == kRowsRealF ? C::NT_RHF : RR ? C::NT_RH : KIND == kRowsCplx ? C::NT_RC : C::NT_C;
+  constexpr int BLK = RR ? Blk<T>::RH : KIND == kRowsCplx ? Blk<T>::RC : Blk<T>::C;
+  constexpr int LDS_TILE = KIND == kRowsRealF ? C::LDS_RHF : RR ? C::LDS_RH : KIND == kRowsCplx ? C::LDS_RC : C::LDS_C;
+  constexpr int LDS_BLK = RR ? Blk<T>::LDS_RH : KIND == kRowsCplx ? Blk<T>::LDS_RC : Blk<T>::LDS_C;
+  constexpr int UNITS = RR ? C::RPB : KIND == kRowsCplx ? C::RPBC : C::CPB;
   constexpr int PER = KIND == kColsCplxK ? 2 * C::n : C::n;
-  constexpr int G = KIND == kRowsReal ? C::RG : KIND == kRowsCplx ? C::RGC : C::CB / C::CPB;
+  constexpr int G = RR ? C::RG : KIND == kRowsCplx ? C::RGC : C::CB / C::CPB;
   constexpr int TPB = BLK / NT;
   constexpr int GB = G / TPB > 1 ? G / TPB : 1;
   CHECK(BLK % NT == 0 && BLK <= 1024);
@@ -93,9 +95,9 @@ void check(int batch) {
   // threads of one tile
   std::set<std::tuple<int, int, int>> seen;
   if constexpr (ROWS) {
-    constexpr int P = KIND == kRowsReal ? C::PH : C::PFR;
-    constexpr int L = KIND == kRowsReal ? C::LH : C::LF;
-    constexpr int E = KIND == kRowsReal ? C::EH : C::EFR;
+    constexpr int P = KIND == kRowsRealF ? C::PHF : RR ? C::PH : C::PFR;
+    constexpr int L = RR ? C::LH : C::LF;
+    constexpr int E = KIND == kRowsRealF ? C::EHF : RR ? C::EH : C::EFR;
     using LL = LineLayout<L, E>;
     CHECK(P * E == L);
     for (int tid = 0; tid < NT; ++tid) {
@@ -131,6 +133,7 @@ template <typename T, int LOGN>
 void check_all() {
   for (int batch : {1, 2, 3, 5, 17}) {
     check<T, LOGN, kRowsReal>(batch);
+    check<T, LOGN, kRowsRealF>(batch);
     check<T, LOGN, kRowsCplx>(batch);
     check<T, LOGN, kColsRealK>(batch);
     check<T, LOGN, kColsCplxK>(batch);
@@ -173,9 +176,10 @@ void check_single_b3(int batch) {
   }
   for (int v : tseen) CHECK(v == 1);
   constexpr bool ROWS_R = KO::ROWS_R, ROWS_C = KO::ROWS_C;
-  constexpr int P = ROWS_R ? C::PH : ROWS_C ? C::PFR : C::PF;
+  constexpr bool FWD_R = K == ws::kRowsFwdReal;
+  constexpr int P = FWD_R ? C::PHF : ROWS_R ? C::PH : ROWS_C ? C::PFR : C::PF;
   constexpr int L = ROWS_R ? C::LH : C::LF;
-  constexpr int E = ROWS_R ? C::EH : ROWS_C ? C::EFR : C::EF;
+  constexpr int E = FWD_R ? C::EHF : ROWS_R ? C::EH : ROWS_C ? C::EFR : C::EF;
   constexpr int UNITS = ROWS_R ? C::RPB : ROWS_C ? C::RPBC : C::CPB;
   using LL = LineLayout<L, E>;
   CHECK(P * E == L && S::NT == B * UNITS * P);
