@@ -483,8 +483,8 @@ def main(argv=None):
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only; every workload is per-density "
-                                   "independent and would shard by density across GPUs (see DESIGN.md)",
+        print(json.dumps({"error": "this benchmark measures one GPU only; every workload is per-density "
+                                   "independent and would shard by density across GPUs",
                           "n_gpus": args.gpus}))
         return 2
 

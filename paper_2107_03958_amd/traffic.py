@@ -103,13 +103,13 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
     with open(out + ".json", "w") as fh:
         json.dump(res, fh, indent=1)
     lines = ["# HBM traffic per dispatch, FP64 apply at n=2048 (rocprofv3 PMC)", "",
-             "Commands (from the repository root $R on the GPU box):", "", "```",
+             "Commands ($R: the repository root; $OUT: an output folder):", "", "```",
              "cd /tmp && export TMPDIR=/tmp",
-             "rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o p --output-format csv -- "
-             "python3 $R/paper_2107_03958_amd/traffic.py target > $R/gpurun_out/pmc_fetch.log",
-             "rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o p --output-format csv -- "
-             "python3 $R/paper_2107_03958_amd/traffic.py target > $R/gpurun_out/pmc_write.log",
-             "cd $R && python3 paper_2107_03958_amd/traffic.py summarise gpurun_out/pmc_fetch gpurun_out/pmc_write "
+             "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o p --output-format csv -- "
+             "python3 $R/paper_2107_03958_amd/traffic.py target > $OUT/pmc_fetch.log",
+             "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o p --output-format csv -- "
+             "python3 $R/paper_2107_03958_amd/traffic.py target > $OUT/pmc_write.log",
+             "cd $R && python3 paper_2107_03958_amd/traffic.py summarise $OUT/pmc_fetch $OUT/pmc_write "
              "profiles/apply_fp64_2048_traffic", "```", "",
              f"Each apply dispatch covers {res['densities_per_dispatch']} densities.", "",
              f"Calibration: `{ck}` copying {COPY_BYTES >> 20} MiB read FETCH_SIZE {fetch[ck]:.0f} KiB "
