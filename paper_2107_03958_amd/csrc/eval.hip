@@ -8,6 +8,8 @@
 // value is complex even for real u and a real kernel, except on the grid.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -35,13 +37,15 @@ __device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
   return {c, s};
 }
 
-// Block: kEvalTargets targets; thread t sums the columns k2 = t, t + 256, ...:
-// sum over k1 of c(k1, k2) exp(2 pi i k1 x1/b) (exponentials by products,
+// Block (x, y): kEvalTargets targets x, and the slice y of the columns k2
+// (k2 = y * 256 + t + j * 256 * gridDim.y for thread t): per column, the sum
+// over k1 of c(k1, k2) exp(2 pi i k1 x1/b) (exponentials by products,
 // re-seeded exactly every kReseed bins and at the jump to negative k1), times
-// exp(2 pi i k2 x2/b); then a block reduction per target.
+// exp(2 pi i k2 x2/b); then a block reduction per target into
+// part[y * count + target] (with one slice, straight into the result).
 __global__ __launch_bounds__(kEvalThreads) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
                                                        const double* __restrict__ targets, int count,
-                                                       cx<double>* __restrict__ out) {
+                                                       cx<double>* __restrict__ part) {
   __shared__ cx<double> red[kEvalTargets][kEvalThreads / 64];
   const int t0 = blockIdx.x * kEvalTargets;
   double x1[kEvalTargets], x2[kEvalTargets];
@@ -58,7 +62,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const cx<double>* __restr
   cx<double> tot[kEvalTargets];
 #pragma unroll
   for (int g = 0; g < kEvalTargets; ++g) tot[g] = {0.0, 0.0};
-  for (int k2 = threadIdx.x; k2 < nb; k2 += kEvalThreads) {
+  for (int k2 = blockIdx.y * kEvalThreads + threadIdx.x; k2 < nb; k2 += kEvalThreads * gridDim.y) {
     cx<double> acc[kEvalTargets], e1[kEvalTargets];
 #pragma unroll
     for (int g = 0; g < kEvalTargets; ++g) acc[g] = {0.0, 0.0};
@@ -91,8 +95,27 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(const cx<double>* __restr
   if (threadIdx.x < kEvalTargets && t0 + (int)threadIdx.x < count) {
     cx<double> s{0.0, 0.0};
     for (int w = 0; w < kEvalThreads / 64; ++w) s = s + red[threadIdx.x][w];
-    out[t0 + threadIdx.x] = s;
+    part[(size_t)blockIdx.y * count + t0 + threadIdx.x] = s;
   }
+}
+
+// out[t] = sum over the slices of part[s * count + t], in slice order.
+__global__ void k_eval_sum(const cx<double>* __restrict__ part, int slices, int count, cx<double>* __restrict__ out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+    cx<double> s = part[t];
+    for (int y = 1; y < slices; ++y) s = s + part[(size_t)y * count + t];
+    out[t] = s;
+  }
+}
+
+// Column slices per target group: enough blocks for about 1024 in all, at most
+// one slice per 256 columns, and partial sums that fit in `room` elements.
+int eval_slices(int count, int nb, size_t room) {
+  const int groups = (count + kEvalTargets - 1) / kEvalTargets;
+  int s = (1024 + groups - 1) / groups;
+  s = std::min(s, std::max(1, nb / kEvalThreads));
+  while (s > 1 && (size_t)s * count > room) --s;
+  return std::max(1, s);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -158,9 +181,15 @@ int conv_eval(ws_plan_t plan, const void* density, int count, const double* targ
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = ws::launch_spectrum(p, v, inter, spec, s);
   if (e == hipSuccess) {
-    const int blocks = (count + ws::kEvalTargets - 1) / ws::kEvalTargets;
-    ws::k_eval<<<blocks, ws::kEvalThreads, 0, s>>>(spec, p.nb, 1.0 / p.b, targets, count,
-                                                   static_cast<ws::cx<double>*>(out));
+    // the row-pass intermediate is free once the spectrum exists: it holds the partial sums
+    const int slices = ws::eval_slices(count, p.nb, w.inter / sizeof(ws::cx<double>));
+    const dim3 grid((count + ws::kEvalTargets - 1) / ws::kEvalTargets, slices);
+    ws::cx<double>* res = static_cast<ws::cx<double>*>(out);
+    ws::k_eval<<<grid, ws::kEvalThreads, 0, s>>>(spec, p.nb, 1.0 / p.b, targets, count, slices > 1 ? inter : res);
+    if (slices > 1) {
+      const int blocks = std::min((count + 255) / 256, 1024);
+      ws::k_eval_sum<<<blocks, 256, 0, s>>>(inter, slices, count, res);
+    }
     e = hipGetLastError();
   }
   if (e != hipSuccess) return ws::set_last_error(WS_EDEVICE, std::string("conv_eval: ") + hipGetErrorString(e));

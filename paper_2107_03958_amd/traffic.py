@@ -25,9 +25,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 512 * 1024 * 1024
 
 
+# The translation unit of the measured kernels: apply.hip and what it includes.
+KERNEL_SOURCES = ("csrc/apply.hip", "csrc/apply_cfg.hpp", "csrc/fft_core.hpp", "csrc/plan.hpp", "csrc/tuned.hpp",
+                  "../include/wsconv.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for rel in KERNEL_SOURCES:
+        f = os.path.normpath(os.path.join(HERE, rel))
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
