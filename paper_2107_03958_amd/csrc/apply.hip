@@ -366,8 +366,12 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
   const int cc = g.cc, p = g.p, l = g.l, cb = g.cb, csub = g.csub, c = g.c;
   const TW tw = sg.tw;
   cx<T>* col = g.col(sg.work);
-  cx<T>* mine = lds + (B * cc + l) * S;
-  cx<T>* line[1] = {mine};
+  constexpr bool SPLIT = C::SPLIT_C;                   // line buffers of T: one component at a time
+  static_assert(!SPLIT || B == 2, "split column exchange: period 2");
+  using LT = std::conditional_t<SPLIT, T, cx<T>>;
+  LT* const lbase = reinterpret_cast<LT*>(lds);
+  LT* mine = lbase + (B * cc + l) * S;
+  LT* line[1] = {mine};
   cx<T> v[1][E];
   const int k2 = cb * CB + c;                          // FFT bin of this column
 
@@ -393,7 +397,9 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     load_bases<L, E, -1, 1>(wb, p, tw, B);
   }
   if constexpr (!GEN) {
-    load_g();
+    // Split tiles run three blocks per CU in fewer registers: their moments
+    // are loaded after the forward transform instead of held through it.
+    if constexpr (!SPLIT) load_g();
     if constexpr (TW::kPowers) {
       cx<T> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wstep, w);
@@ -407,6 +413,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
       }
     }
     run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
+    if constexpr (SPLIT) load_g();
     // v[0][reg] = Y(k1 = B q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {
@@ -417,27 +424,55 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
         // -k1 = B (n - q) - l lies in line (B - l) mod B at (n - q) mod n
         // (l = 0) or n - q - 1.
         const bool dc = (!GUARD || valid) && cb == 0 && csub == 0;
-        if (dc) {
+        const LT* pl = lbase + (B * cc + (l == 0 ? 0 : B - l)) * S;
+        if constexpr (!SPLIT) {
+          if (dc) {
 #pragma unroll
-          for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-        }
-        __syncthreads();
-        if (dc && c == 0) {
-          const cx<T>* pl = lds + (B * cc + (l == 0 ? 0 : B - l)) * S;
-#pragma unroll
-          for (int reg = 0; reg < E; ++reg) {
-            const int q = p + P * slot_elem<E, RL>(reg);
-            const int k1 = B * q + l;
-            const int k1f = k1 <= N ? k1 : nb - k1;
-            const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
-            const cx<T> ym = cconj(pl[LL::pad(partner)]);
-            const T g0 = (T)gk[reg];                 // column 0 of block-column 0: gtab[k1f * CB]
-            const T gN = sg.gnyq[k1f];
-            v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
+            for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
           }
-          done = true;
+          __syncthreads();
+          if (dc && c == 0) {
+#pragma unroll
+            for (int reg = 0; reg < E; ++reg) {
+              const int q = p + P * slot_elem<E, RL>(reg);
+              const int k1 = B * q + l;
+              const int k1f = k1 <= N ? k1 : nb - k1;
+              const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
+              const cx<T> ym = cconj(pl[LL::pad(partner)]);
+              const T g0 = (T)gk[reg];               // column 0 of block-column 0: gtab[k1f * CB]
+              const T gN = sg.gnyq[k1f];
+              v[0][reg] = cscale(v[0][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
+            }
+            done = true;
+          }
+          __syncthreads();
+        } else {
+          // The same per component: the real part of the new value takes the
+          // real part of Y(-k), the imaginary part minus its imaginary part.
+          split_parts([&](auto part) {
+            constexpr int PART = decltype(part)::value;
+            if (dc) {
+#pragma unroll
+              for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = part_of<PART>(v[0][reg]);
+            }
+            __syncthreads();
+            if (dc && c == 0) {
+#pragma unroll
+              for (int reg = 0; reg < E; ++reg) {
+                const int q = p + P * slot_elem<E, RL>(reg);
+                const int k1 = B * q + l;
+                const int k1f = k1 <= N ? k1 : nb - k1;
+                const int partner = l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q);
+                const T ym = PART == 0 ? pl[LL::pad(partner)] : -pl[LL::pad(partner)];
+                const T g0 = (T)gk[reg];
+                const T gN = sg.gnyq[k1f];
+                part_of<PART>(v[0][reg]) = part_of<PART>(v[0][reg]) * ((T)0.5 * (g0 + gN)) + ym * ((T)0.5 * (g0 - gN));
+              }
+              done = true;
+            }
+            __syncthreads();
+          });
         }
-        __syncthreads();
       }
     }
     if (!done && (!GUARD || valid)) {
@@ -467,12 +502,38 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     for (int q = 0; q < NB; ++q) wbi[q] = cconj(wb[q]);
   }
   run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wbi));
+  if constexpr (!SPLIT) {
 #pragma unroll
-  for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
-  __syncthreads();
-  if (GUARD && !valid) return;
-  combine_lines<B, L, E, 1>(lds + (B * cc) * S, S, p, l, tw, wcomb, B == 2 ? cconj(wstep) : wcstep,
-                            [&](int i, cx<T> y) { col[(size_t)i * CB + c] = y; });
+    for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
+    __syncthreads();
+    if (GUARD && !valid) return;
+    combine_lines<B, L, E, 1>(lds + (B * cc) * S, S, p, l, tw, wcomb, B == 2 ? cconj(wstep) : wcstep,
+                              [&](int i, cx<T> y) { col[(size_t)i * CB + c] = y; });
+  } else {
+    // combine_lines (B = 2) one component at a time: out_i = line_0[i] +
+    // w_i line_1[i], w_i = w_nb^{-i}, accumulated over the two rounds.
+    const T* l0 = lbase + (B * cc) * S;
+    const T* l1 = l0 + S;
+    cx<T> w[E / 2], acc[E / 2];
+    run_from<E / 2>(wcomb, cconj(wstep), w);
+    split_parts([&](auto part) {
+      constexpr int PART = decltype(part)::value;
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = part_of<PART>(v[0][reg]);
+      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < E / 2; ++tt) {
+        const int i = p + P * (l * (E / 2) + tt);
+        const T a = l0[LL::pad(i)], b = l1[LL::pad(i)];
+        if constexpr (PART == 0) acc[tt] = {a + w[tt].x * b, w[tt].y * b};
+        else acc[tt] = {acc[tt].x - w[tt].y * b, acc[tt].y + (a + w[tt].x * b)};
+      }
+      __syncthreads();
+    });
+    if (GUARD && !valid) return;
+#pragma unroll
+    for (int tt = 0; tt < E / 2; ++tt) col[(size_t)(p + P * (l * (E / 2) + tt)) * CB + c] = acc[tt];
+  }
 }
 
 template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, int B = 2>
@@ -508,7 +569,8 @@ __device__ __forceinline__ void cols_spec_tile(const Seg<double>& sg, int t, boo
   const ColGeo<double, LOGN, true, B> g(t, tid);
   const int p = g.p, l = g.l;
   const TwD tw = sg.tw;
-  cx<double>* line[1] = {lds + (B * g.cc + l) * S};
+  using LT = std::conditional_t<C::SPLIT_C, double, cx<double>>;
+  LT* line[1] = {reinterpret_cast<LT*>(lds) + (B * g.cc + l) * S};
   cx<double> wpre{}, wstep{}, wb[NB > 0 ? NB : 1];
   if (l) {
     wpre = tw.template get<-1>(p * l);

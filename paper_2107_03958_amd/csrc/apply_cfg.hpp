@@ -49,7 +49,12 @@ struct Cfg {
   static constexpr int PF = LF / EF;
   static constexpr int NT_C = B * CPB * PF;
   static constexpr int SF = LineLayout<LF, EF>::STRIDE;
-  static constexpr int LDS_C = B * CPB * SF;
+  // FP64 column tiles whose cx<T> line buffers would leave room for only two
+  // blocks per CU exchange one real component at a time, through line buffers
+  // of T (half the LDS), so three blocks fit.
+  static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && B * CPB * SF * 16 * 3 > 163840 &&
+                                  B * CPB * SF * 8 * 3 <= 163840;
+  static constexpr int LDS_C = SPLIT_C ? (B * CPB * SF + 1) / 2 : B * CPB * SF;   // cx<T> elements
   // Complex row passes: B full-length lines per row, rows per tile limited by LDS.
   template <int ROWS>
   static constexpr bool fits() {
@@ -102,13 +107,14 @@ struct Blk {
   static_assert(LDS_RH * sizeof(cx<T>) <= 163840 && LDS_C * sizeof(cx<T>) <= 163840 &&
                 LDS_RC * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
   // Waves per SIMD the column kernel reserves registers for: as many blocks
-  // per CU (up to two) as its LDS allows.
-  static constexpr int waves(int threads, int lds_bytes) {
-    const int blocks = lds_bytes * 2 <= 163840 ? 2 : 1;
+  // per CU as its LDS allows, up to two, or three for split tiles (which
+  // load their moments late to fit the registers of three).
+  static constexpr int waves(int threads, int lds_bytes, bool three) {
+    const int blocks = three && lds_bytes * 3 <= 163840 ? 3 : lds_bytes * 2 <= 163840 ? 2 : 1;
     const int w = (blocks * threads + 255) / 256;
     return w < 1 ? 1 : w;
   }
-  static constexpr int WAVES_C = waves(C, LDS_C * (int)sizeof(cx<T>));
+  static constexpr int WAVES_C = waves(C, LDS_C * (int)sizeof(cx<T>), false);
 };
 
 // Thread -> (column c, line l, p) of a column tile.  When a wave can hold
@@ -208,7 +214,7 @@ struct Single {
   }
   static constexpr int WAVES = (KindOf<T, K>::ROWS_R || KindOf<T, K>::ROWS_C)
                                    ? lds_waves()
-                                   : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>));
+                                   : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>), Cfg<T, LOGN, B>::SPLIT_C);
   static_assert(BLOCK % NT == 0 && BLOCK <= 1024, "bad block size");
   static_assert(LDS * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
 };

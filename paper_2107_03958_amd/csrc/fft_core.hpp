@@ -15,6 +15,7 @@
 // each twiddle as a float pair (hi, lo) rounded from FP64 and multiplies by
 // both, so the twiddle itself carries FP64 accuracy.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -293,6 +294,14 @@ __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW
   }
 }
 
+// f(integral_constant<0>) then f(integral_constant<1>): the two real
+// components of a split exchange.
+template <typename F>
+__device__ __forceinline__ void split_parts(F f) {
+  f(std::integral_constant<int, 0>{});
+  f(std::integral_constant<int, 1>{});
+}
+
 // Exchange through LDS between stage (R, NS) and the next stage of radix R2.
 // With one padding slot per R0 elements (R0 = first radix >= every radix),
 // pad(b + r * NS) = pad(b) + r * (NS + NS / R0) for NS >= R0 and
@@ -328,8 +337,50 @@ __device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], cx<T>* const* lds, i
   __syncthreads();
 }
 
-template <int L, int E, int NL, int SGN, int NS, typename T, typename TW>
-__device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], cx<T>* const* lds, int p, const TW& tw,
+// The same exchange through line buffers of T, one real component at a time
+// (real parts, then imaginary parts): half the LDS of the cx<T> buffers, for
+// two more barriers.  Element indices are those of exchange().
+template <int PART, typename T>
+__device__ __forceinline__ T& part_of(cx<T>& z) {
+  if constexpr (PART == 0) return z.x;
+  else return z.y;
+}
+template <int L, int E, int NL, int R, int NS, int R2, typename T>
+__device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], T* const* lds, int p) {
+  using LL = LineLayout<L, E>;
+  constexpr int P = L / E;
+  constexpr int R0 = FirstLast<L, E>::R0;
+  static_assert(NS == 1 ? R == R0 : NS % R0 == 0, "stage span must be a multiple of the first radix");
+  static_assert((L / R2) % R0 == 0, "exchange stride must be a multiple of the first radix");
+  constexpr int WSTEP = NS == 1 ? 1 : NS + NS / R0;
+  constexpr int RSTEP = L / R2 + (L / R2) / R0;
+  split_parts([&](auto part) {
+    constexpr int PART = decltype(part)::value;
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+      const int j = p + q * P;
+      const int pb = LL::pad((j / NS) * NS * R + (j % NS));
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int l = 0; l < NL; ++l) lds[l][pb + r * WSTEP] = part_of<PART>(v[l][q * R + r]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E / R2; ++q) {
+      const int pb = LL::pad(p + q * P);
+#pragma unroll
+      for (int r = 0; r < R2; ++r)
+#pragma unroll
+        for (int l = 0; l < NL; ++l) part_of<PART>(v[l][q * R2 + r]) = lds[l][pb + r * RSTEP];
+    }
+    __syncthreads();
+  });
+}
+
+// LP: cx<T>* const* (whole elements through LDS) or T* const* (split exchange).
+template <int L, int E, int NL, int SGN, int NS, typename T, typename TW, typename LP>
+__device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], LP lds, int p, const TW& tw,
                                            int twstep, const cx<T>* wb) {
   constexpr int R = Radix<L, E, NS>::R;
   stage_compute<L, E, NL, R, NS, SGN>(v, p, tw, twstep, wb);

@@ -55,6 +55,11 @@ namespace ws {
 #ifndef WS_CPB64
 #define WS_CPB64 1
 #endif
+// 1: FP64 column tiles too large for three blocks per CU exchange one real
+// component at a time (half the LDS); 0: whole complex elements.
+#ifndef WS_SPLIT64
+#define WS_SPLIT64 1
+#endif
 // Elements per thread of the forward real row pass (default: that of the inverse, ER).
 #ifndef WS_ERF64
 #define WS_ERF64 WS_ER64

@@ -117,7 +117,8 @@ void check(int batch) {
       col_thread<C::CPB, P>(tid, c, p, l);
       CHECK(c >= 0 && c < C::CPB && p >= 0 && p < P && (l == 0 || l == 1));
       seen.insert({c, p, l});
-      CHECK((2 * c + l) * LL::STRIDE + LL::LEN <= LDS_TILE);
+      // split column tiles: line buffers of T, twice as many per cx<T> of LDS
+      CHECK((2 * c + l) * LL::STRIDE + LL::LEN <= (C::SPLIT_C ? 2 : 1) * LDS_TILE);
       for (int s = 0; s < C::EF; ++s) CHECK(LL::pad_ps(p, s) < LL::LEN);
     }
     CHECK((int)seen.size() == NT);
@@ -129,8 +130,22 @@ void check(int batch) {
   }
 }
 
+// Split column tiles: FP64 only, period 2, and their LDS lets three blocks share a CU.
+template <typename T, int LOGN>
+void check_split() {
+  const char* tname = sizeof(T) == 8 ? "double" : "float";
+  constexpr int KIND = -300, batch = 0;
+  using C = Cfg<T, LOGN>;
+  if constexpr (C::SPLIT_C) {
+    CHECK(sizeof(T) == 8);
+    CHECK(C::LDS_C * (int)sizeof(cx<T>) * 3 <= 163840);
+    CHECK(2 * C::LDS_C >= 2 * C::CPB * C::SF);
+  }
+}
+
 template <typename T, int LOGN>
 void check_all() {
+  check_split<T, LOGN>();
   for (int batch : {1, 2, 3, 5, 17}) {
     check<T, LOGN, kRowsReal>(batch);
     check<T, LOGN, kRowsRealF>(batch);
@@ -195,7 +210,7 @@ void check_single_b3(int batch) {
     }
     CHECK(p >= 0 && p < P && l >= 0 && l < B && u >= 0 && u < UNITS);
     seen.insert({p, l, u});
-    CHECK((B * u + l) * LL::STRIDE + LL::LEN <= KO::template lds_tile<LOGN>());
+    CHECK((B * u + l) * LL::STRIDE + LL::LEN <= (!ROWS_R && !ROWS_C && C::SPLIT_C ? 2 : 1) * KO::template lds_tile<LOGN>());
     for (int s = 0; s < E; ++s) CHECK(LL::pad_ps(p, s) < LL::LEN && LL::pad_ps(p, s) == LL::pad(p + P * s));
   }
   CHECK((int)seen.size() == S::NT);

@@ -93,6 +93,18 @@ def test_eval_large_grid_sampled(api):
     assert np.max(np.abs(got - ref)) <= TOL * np.max(np.abs(ref))
 
 
+@pytest.mark.slow
+def test_eval_n2048_sampled(api):
+    # the spectrum pass's column tiles at the largest grid (split exchange)
+    n = 2048
+    u = synth.smooth_density(n, 34)
+    pts = _targets(6, 13)
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    got = plan.eval(torch.as_tensor(u).cuda(), torch.as_tensor(pts).cuda()).cpu().numpy()
+    ref = scheme.apply_at(u, oracle_table("log", n), B, pts)
+    assert np.max(np.abs(got - ref)) <= TOL * np.max(np.abs(ref))
+
+
 def test_eval_edge_cases(api):
     from paper_2107_03958_amd import _lib as L
     n = 32

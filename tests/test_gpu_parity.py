@@ -128,6 +128,20 @@ def test_complex_apply_n1024(api, precision):
         assert metrics.rel_l2(got, ref) <= 5e-7
 
 
+@pytest.mark.slow
+def test_complex_apply_n2048_fp64(api):
+    # at the largest grid the FP64 column tiles exchange one real component
+    # at a time (complex path: Helmholtz moments, full-spectrum columns)
+    n = 2048
+    rng = np.random.default_rng(n)
+    v = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) * synth.cutoff(n)
+    plan = api.ConvPlan(n=n, **plan_kwargs("helm40"))
+    got = plan.apply(_gpu(v, torch.complex128)).cpu().numpy()
+    ref = scheme.apply(v, oracle_table("helm40", n), B)
+    oracle_table.cache_clear()
+    assert metrics.rel_linf(got, ref) <= FP64_TOL
+
+
 @pytest.mark.parametrize("kname", ["helm20", "helm40"])
 @pytest.mark.parametrize("n", [16, 64, 128])
 def test_complex_apply(api, kname, n):
@@ -170,6 +184,19 @@ def test_fourier_smoothing_apply(api, shape, n):
         dens = smoothing.smoothed_square_density(n, B, 0.5 - h, 0.5 + h, h * math.sqrt(2), 0.39)
     got = plan.apply(_gpu(ut, torch.float64).unsqueeze(0), fs=[fs]).cpu().numpy()[0]
     ref = np.real(scheme.apply(dens, oracle_table("laplace", n), B))
+    assert metrics.rel_linf(got, ref) <= FP64_TOL
+
+
+@pytest.mark.slow
+def test_fourier_smoothing_apply_n2048(api):
+    # the smoothing pre-pass's column tiles at the largest grid (split exchange)
+    n, R = 2048, 0.25
+    plan = api.ConvPlan(n=n, **plan_kwargs("laplace"))
+    fs = api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)
+    dens = smoothing.smoothed_disc_density(n, B, R, r2=0.39)
+    got = plan.apply(_gpu(np.ones((n, n)), torch.float64).unsqueeze(0), fs=[fs]).cpu().numpy()[0]
+    ref = np.real(scheme.apply(dens, oracle_table("laplace", n), B))
+    oracle_table.cache_clear()
     assert metrics.rel_linf(got, ref) <= FP64_TOL
 
 
