@@ -161,7 +161,8 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   // FP64: every twiddle load of the tile first (pre-twiddle run w_N^{l (p + P s)},
   // stage bases, unpack run w_nb^{k0 + DK it}), so that no later wait is
   // ordered behind the row loads
-  cx<T> wpre{}, wpstep{}, wu{}, wustep{}, wb[NB > 0 ? NB : 1];
+  using W = typename TW::W;
+  cx<W> wpre{}, wpstep{}, wu{}, wustep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     if (l) {
       wpre = tw.template get<-1>(2 * p * l);
@@ -181,7 +182,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
     for (int reg = 0; reg < E; ++reg)
       x[reg] = (!GUARD || valid) ? src[p + P * slot_elem<E, R0>(reg)] : cx<T>{0, 0};
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                           // w_N^{l m}, m = p + P s
+      cx<W> w[E];                                           // w_N^{l m}, m = p + P s
       if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -193,7 +194,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
       }
     }
   }
-  run_stages<L, E, 1, -1, 1>(v, line, p, tw, TWS, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, TWS, static_cast<const cx<W>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -215,7 +216,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
     dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
   };
   if constexpr (RUN) {
-    cx<T> wk[IT];
+    cx<W> wk[IT];
     run_from<IT>(wu, wustep, wk);
 #pragma unroll
     for (int it = 0; it < IT; ++it) unpack(it, [&](cx<T> x, int) { return cmul(x, wk[it]); });
@@ -250,14 +251,15 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
 // caller loaded early: w0 = w_nb^{-u (p + P l E/2)} (B = 2) or
 // w_nb^{-u (p + P l)} (B = 3), and step = w_nb^{-u P} (B = 2) or w_nb^{-3 u P}.
 template <int B, int L, int E, int U, typename T, typename TW, typename EMIT>
-__device__ __forceinline__ void combine_lines(const cx<T>* base, int S, int p, int l, const TW& tw, cx<T> w0,
-                                              cx<T> step, EMIT emit) {
+__device__ __forceinline__ void combine_lines(const cx<T>* base, int S, int p, int l, const TW& tw,
+                                              cx<typename TW::W> w0, cx<typename TW::W> step, EMIT emit) {
+  using W = typename TW::W;
   using LL = LineLayout<L, E>;
   constexpr int P = L / E;
   const cx<T>* l0 = base;
   const cx<T>* l1 = l0 + S;
   if constexpr (B == 2) {
-    cx<T> w[TW::kPowers ? E / 2 : 1];                        // w_nb^{-u i}, i = p + P (l E/2 + t)
+    cx<W> w[TW::kPowers ? E / 2 : 1];                        // w_nb^{-u i}, i = p + P (l E/2 + t)
     if constexpr (TW::kPowers) run_from<E / 2>(w0, step, w);
 #pragma unroll
     for (int tt = 0; tt < E / 2; ++tt) {
@@ -269,14 +271,14 @@ __device__ __forceinline__ void combine_lines(const cx<T>* base, int S, int p, i
     static_assert(B == 3 && TW::kPowers, "period 3: FP64 only");
     const cx<T>* l2 = l1 + S;
     constexpr int TMAX = (E + B - 1) / B;
-    cx<T> w[TMAX];                                           // w_nb^{-u i}, i = p + P (l + 3 t)
+    cx<W> w[TMAX];                                           // w_nb^{-u i}, i = p + P (l + 3 t)
     run_from<TMAX>(w0, step, w);
 #pragma unroll
     for (int tt = 0; tt < TMAX; ++tt) {
       const int s = l + B * tt;
       if (s < E) {
         const int i = p + P * s;
-        const cx<T> w2 = cmul(w[tt], w[tt]);
+        const cx<W> w2 = cmul(w[tt], w[tt]);
         emit(i, l0[LL::pad(i)] + cmul(l1[LL::pad(i)], w[tt]) + cmul(l2[LL::pad(i)], w2));
       }
     }
@@ -379,8 +381,9 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
   // pre-twiddle; the combine's run seeds; the forward stage bases, whose
   // conjugates are the inverse transform's.  B = 2: both runs step by
   // w_nb^{P} (conjugated for the combine).
-  cx<T> wstep{}, wpre{}, wcomb{}, wcstep{};
-  cx<T> wb[NB > 0 ? NB : 1], wbi[NB > 0 ? NB : 1];
+  using W = typename TW::W;
+  cx<W> wstep{}, wpre{}, wcomb{}, wcstep{};
+  cx<W> wb[NB > 0 ? NB : 1], wbi[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     if constexpr (B == 2) {
       wstep = tw.template get<-1>(P);
@@ -401,7 +404,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     // are loaded after the forward transform instead of held through it.
     if constexpr (!SPLIT) load_g();
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                          // w_nb^{l j}, j = p + P s
+      cx<W> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -412,7 +415,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
         v[0][reg] = l ? tw.template mul<-1>(x[reg], j * l) : x[reg];   // line l: x w_nb^{l j}
       }
     }
-    run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
+    run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
     if constexpr (SPLIT) load_g();
     // v[0][reg] = Y(k1 = B q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
@@ -501,7 +504,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
 #pragma unroll
     for (int q = 0; q < NB; ++q) wbi[q] = cconj(wb[q]);
   }
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wbi));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wbi));
   if constexpr (!SPLIT) {
 #pragma unroll
     for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
@@ -514,7 +517,8 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     // w_i line_1[i], w_i = w_nb^{-i}, accumulated over the two rounds.
     const T* l0 = lbase + (B * cc) * S;
     const T* l1 = l0 + S;
-    cx<T> w[E / 2], acc[E / 2];
+    cx<W> w[E / 2];
+    cx<T> acc[E / 2];
     run_from<E / 2>(wcomb, cconj(wstep), w);
     split_parts([&](auto part) {
       constexpr int PART = decltype(part)::value;
@@ -651,7 +655,8 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
   // FP64: every twiddle load of the tile first (run w_nb^{-(B p + l + B P s)},
   // stage bases, combine run seeds)
-  cx<T> wq0{}, wstep{}, wm0{}, wmstep{}, wb[NB > 0 ? NB : 1];
+  using W = typename TW::W;
+  cx<W> wq0{}, wstep{}, wm0{}, wmstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     wq0 = tw.template get<+1>(B * p + l);
     wstep = tw.template get<+1>(B * P);
@@ -674,7 +679,7 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   }
   __syncthreads();
   cx<T> v[1][E];
-  cx<T> wq[TW::kPowers ? E : 1];                             // w_nb^{-k}, k = B p + l + B P s
+  cx<W> wq[TW::kPowers ? E : 1];                             // w_nb^{-k}, k = B p + l + B P s
   if constexpr (TW::kPowers) run_from<E>(wq0, wstep, wq);
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) {
@@ -701,7 +706,7 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
     v[0][reg] = z;
   }
   __syncthreads();
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, TWS, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, TWS, static_cast<const cx<W>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -738,7 +743,8 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
   // FP64: the twiddle loads first (pre-twiddle run w_nb^{l (p + P s)}, stage bases)
-  cx<T> wpre{}, wpstep{}, wb[NB > 0 ? NB : 1];
+  using W = typename TW::W;
+  cx<W> wpre{}, wpstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     if (l) {
       wpre = tw.template get<-1>(p * l);
@@ -761,7 +767,7 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
       }
     }
     if constexpr (TW::kPowers) {
-      cx<T> w[E];                                          // w_nb^{l j}, j = p + P s
+      cx<W> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wpstep, w);
 #pragma unroll
       for (int reg = 0; reg < E; ++reg) v[0][reg] = l ? cmul(x[reg], w[slot_elem<E, R0>(reg)]) : x[reg];
@@ -773,7 +779,7 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
       }
     }
   }
-  run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -800,7 +806,8 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
   using TW = typename TwOf<T>::type;
   constexpr int NB = TW::kPowers ? stage_bases<L, E, 1>() : 0;
   // FP64: the twiddle loads first (stage bases, combine run seeds)
-  cx<T> wc0{}, wcstep{}, wb[NB > 0 ? NB : 1];
+  using W = typename TW::W;
+  cx<W> wc0{}, wcstep{}, wb[NB > 0 ? NB : 1];
   if constexpr (TW::kPowers) {
     load_bases<L, E, +1, 1>(wb, p, tw, B);
     if constexpr (B == 2) {
@@ -826,7 +833,7 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) v[0][reg] = mine[LL::pad_ps(p, slot_elem<E, R0>(reg))];
   __syncthreads();
-  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<T>*>(wb));
+  run_stages<L, E, 1, +1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
 #pragma unroll
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
@@ -964,7 +971,13 @@ __global__ __launch_bounds__((KindOf<T, K>::BLK), (KindOf<T, K>::WAVES)) void k_
 // Host side.
 template <typename T> typename TwOf<T>::type make_tw(const Plan& p);
 template <> TwD make_tw<double>(const Plan& p) { return TwD{p.tw64}; }
-template <> TwF make_tw<float>(const Plan& p) { return TwF{p.tw32}; }
+template <> TwOf<float>::type make_tw<float>(const Plan& p) {
+#if WS_TW32_POWERS
+  return TwDF{p.tw64};
+#else
+  return TwF{p.tw32};
+#endif
+}
 
 template <typename T> const void* gtab_of(const Plan& p);
 template <> const void* gtab_of<double>(const Plan& p) { return p.g64; }

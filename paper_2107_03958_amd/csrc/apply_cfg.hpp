@@ -207,10 +207,13 @@ struct Single {
   // Waves per SIMD the registers are sized for.  Row kernels: as many blocks
   // as the LDS admits (at most 8 waves per SIMD).  Column kernels: at most two
   // blocks per CU (their butterflies need the registers).
+  // FP32 row kernels stop at three waves (168 VGPRs): their FP64 twiddle
+  // runs do not fit the 128 VGPRs of four without spilling.
   static constexpr int lds_waves() {
     const int blocks = 163840 / (LDS * (int)sizeof(cx<T>));
     const int w = blocks * BLOCK / 256;
-    return w < 1 ? 1 : w > 8 ? 8 : w;
+    const int wmax = sizeof(T) == 4 && WS_TW32_POWERS ? 3 : 8;
+    return w < 1 ? 1 : w > wmax ? wmax : w;
   }
   static constexpr int WAVES = (KindOf<T, K>::ROWS_R || KindOf<T, K>::ROWS_C)
                                    ? lds_waves()

@@ -11,9 +11,11 @@
 //   takes an R-point DFT and writes y[(j/NS) NS R + j mod NS + r NS].
 // A thread may drive NL lines at once (all exchanged with one barrier pair).
 //
-// Twiddles come from a table of exp(-2 pi i m / TWN); the FP32 path keeps
-// each twiddle as a float pair (hi, lo) rounded from FP64 and multiplies by
-// both, so the twiddle itself carries FP64 accuracy.
+// Twiddles come from a table of exp(-2 pi i m / TWN) in FP64.  The FP32 path
+// forms them in FP64 as the FP64 path does and takes each product x w in FP64,
+// rounded once to FP32, so the twiddle itself carries FP64 accuracy (a table
+// of (hi, lo) float pairs rounded from FP64, applied as x hi + x lo, remains
+// as the -DWS_TW32_POWERS=0 build).
 #pragma once
 #include <type_traits>
 #include <hip/hip_runtime.h>
@@ -40,13 +42,15 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // ---------------------------------------------------------------------------
 // Twiddle tables.  w(m) = exp(-2 pi i m / TWN); SGN = -1 forward, +1 inverse.
-// FP64: a butterfly loads its base twiddle w^jm once and forms the powers
-// w^(jm r) by repeated multiplication (a few ulps, far below the FP64 error of
-// the transform).  FP32: every twiddle is read as the pair (hi, lo) of floats
-// rounded from FP64 (one 16-byte load) and applied as x*hi + x*lo.
+// FP64 (TwD) and FP32 data (TwDF): a butterfly loads its base twiddle w^jm
+// once and forms the powers w^(jm r) by repeated multiplication in FP64 (a few
+// ulps, far below the FP64 error of the transform).  TwF: every twiddle is read
+// as the pair (hi, lo) of floats rounded from FP64 (one 16-byte load) and
+// applied as x*hi + x*lo.
 struct TwD {
   const cx<double>* t;
   static constexpr bool kPowers = true;
+  using W = double;                       // arithmetic type of the twiddles
   template <int SGN>
   __device__ __forceinline__ cx<double> mul(cx<double> x, int m) const {
     cx<double> w = t[m];
@@ -64,6 +68,7 @@ struct alignas(16) TwPair { float hx, hy, lx, ly; };
 struct TwF {
   const TwPair* t;
   static constexpr bool kPowers = false;
+  using W = float;
   template <int SGN>
   __device__ __forceinline__ cx<float> mul(cx<float> x, int m) const {
     const TwPair w = t[m];
@@ -90,9 +95,38 @@ __device__ __forceinline__ void tw_run(const TwD& tw, int b, int d, cx<double> (
   run_from<K>(tw.template get<SGN>(b), K > 1 ? tw.template get<SGN>(d) : cx<double>{1, 0}, w);
 }
 
+// FP32 data times an FP64 twiddle: the product in FP64, rounded once.
+__device__ __forceinline__ cx<float> cmul(cx<float> a, cx<double> b) {
+  const double ax = a.x, ay = a.y;
+  return {(float)(ax * b.x - ay * b.y), (float)(ax * b.y + ay * b.x)};
+}
+
+// FP32 data with the FP64 table: bases loaded and powers formed in FP64 as
+// for TwD, each product x w taken in FP64 and rounded once to FP32 (at least
+// as accurate as x hi + x lo with the pair rounded from FP64), with no table
+// load inside a transform.
+struct TwDF {
+  const cx<double>* t;
+  static constexpr bool kPowers = true;
+  using W = double;
+  template <int SGN>
+  __device__ __forceinline__ cx<double> get(int m) const {
+    cx<double> w = t[m];
+    return SGN < 0 ? w : cconj(w);
+  }
+  template <int SGN>
+  __device__ __forceinline__ cx<float> mul(cx<float> x, int m) const {
+    return cmul(x, get<SGN>(m));
+  }
+};
+
+// 1 (default): FP32 passes use TwDF; 0: the (hi, lo) pair table, TwF.
+#ifndef WS_TW32_POWERS
+#define WS_TW32_POWERS 1
+#endif
 template <typename T> struct TwOf;
 template <> struct TwOf<double> { using type = TwD; };
-template <> struct TwOf<float> { using type = TwF; };
+template <> struct TwOf<float> { using type = std::conditional_t<WS_TW32_POWERS != 0, TwDF, TwF>; };
 
 // ---------------------------------------------------------------------------
 // Constant twiddles inside the R-point butterflies: w_R^k, R <= 16.
@@ -263,7 +297,7 @@ __device__ __forceinline__ void load_bases(cx<T>* wb, int p, const TW& tw, int t
 // preloaded base twiddles (FP64 tables), else null.
 template <int L, int E, int NL, int R, int NS, int SGN, typename T, typename TW>
 __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW& tw, int twstep,
-                                              const cx<T>* wb) {
+                                              const cx<typename TW::W>* wb) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
@@ -272,8 +306,8 @@ __device__ __forceinline__ void stage_compute(cx<T> (&v)[NL][E], int p, const TW
       const int jm = j % NS;
       const int unit = (L / (NS * R)) * twstep;   // w_{NS R} in table units
       if constexpr (TW::kPowers) {
-        const cx<T> w1 = wb[q];
-        cx<T> wr = w1;
+        const cx<typename TW::W> w1 = wb[q];
+        cx<typename TW::W> wr = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
 #pragma unroll
@@ -381,7 +415,7 @@ __device__ __forceinline__ void exchange(cx<T> (&v)[NL][E], T* const* lds, int p
 // LP: cx<T>* const* (whole elements through LDS) or T* const* (split exchange).
 template <int L, int E, int NL, int SGN, int NS, typename T, typename TW, typename LP>
 __device__ __forceinline__ void run_stages(cx<T> (&v)[NL][E], LP lds, int p, const TW& tw,
-                                           int twstep, const cx<T>* wb) {
+                                           int twstep, const cx<typename TW::W>* wb) {
   constexpr int R = Radix<L, E, NS>::R;
   stage_compute<L, E, NL, R, NS, SGN>(v, p, tw, twstep, wb);
   if constexpr (NS * R < L) {
@@ -400,11 +434,11 @@ __device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][E], cx<T>* const* lds, 
                                           int twstep) {
   if constexpr (TW::kPowers) {
     constexpr int NB = stage_bases<L, E, 1>();
-    cx<T> wb[NB > 0 ? NB : 1];
+    cx<typename TW::W> wb[NB > 0 ? NB : 1];
     load_bases<L, E, SGN, 1>(wb, p, tw, twstep);
-    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, wb);
+    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, static_cast<const cx<typename TW::W>*>(wb));
   } else {
-    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, static_cast<const cx<T>*>(nullptr));
+    run_stages<L, E, NL, SGN, 1>(v, lds, p, tw, twstep, static_cast<const cx<typename TW::W>*>(nullptr));
   }
 }
 
