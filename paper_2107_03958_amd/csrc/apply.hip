@@ -400,9 +400,10 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     load_bases<L, E, -1, 1>(wb, p, tw, B);
   }
   if constexpr (!GEN) {
-    // Split tiles run three blocks per CU in fewer registers: their moments
-    // are loaded after the forward transform instead of held through it.
-    if constexpr (!SPLIT) load_g();
+    // Tiles that run three blocks per CU (Cfg::THREE_C) load their moments
+    // after the forward transform instead of holding them through it.
+    constexpr bool LATE_G = C::THREE_C;
+    if constexpr (!LATE_G) load_g();
     if constexpr (TW::kPowers) {
       cx<W> w[E];                                          // w_nb^{l j}, j = p + P s
       if (l) run_from<E>(wpre, wstep, w);
@@ -416,7 +417,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
       }
     }
     run_stages<L, E, 1, -1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
-    if constexpr (SPLIT) load_g();
+    if constexpr (LATE_G) load_g();
     // v[0][reg] = Y(k1 = B q + l), q = p + P slot_elem<E,RL>(reg)
     bool done = false;
     if constexpr (!CPLX) {

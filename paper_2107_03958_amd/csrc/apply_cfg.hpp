@@ -55,6 +55,10 @@ struct Cfg {
   static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && B * CPB * SF * 16 * 3 > 163840 &&
                                   B * CPB * SF * 8 * 3 <= 163840;
   static constexpr int LDS_C = SPLIT_C ? (B * CPB * SF + 1) / 2 : B * CPB * SF;   // cx<T> elements
+  // Column tiles compiled for three blocks per CU (168 VGPRs), which load
+  // their moments after the forward transform to fit: split tiles, and FP64
+  // period-3 tiles, whose three lines already fit three blocks' LDS.
+  static constexpr bool THREE_C = SPLIT_C || (sizeof(T) == 8 && B == 3 && LDS_C * 16 * 3 <= 163840);
   // Complex row passes: B full-length lines per row, rows per tile limited by LDS.
   template <int ROWS>
   static constexpr bool fits() {
@@ -217,7 +221,7 @@ struct Single {
   }
   static constexpr int WAVES = (KindOf<T, K>::ROWS_R || KindOf<T, K>::ROWS_C)
                                    ? lds_waves()
-                                   : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>), Cfg<T, LOGN, B>::SPLIT_C);
+                                   : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>), Cfg<T, LOGN, B>::THREE_C);
   static_assert(BLOCK % NT == 0 && BLOCK <= 1024, "bad block size");
   static_assert(LDS * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
 };
