@@ -4,7 +4,7 @@ Two modes:
 
 * ``python paper_2107_03958_amd/traffic.py target``: a short workload to run
   under ``rocprofv3 --pmc FETCH_SIZE`` (then ``--pmc WRITE_SIZE``).  It applies
-  the FP64 plan for log|x| at n = 2048 to 4 densities (two chunks) and then
+  the FP64 plan for log|x| at n = 2048 to two whole chunks of densities and then
   copies a 512 MiB device buffer, whose counters calibrate the byte scale.
 * ``python paper_2107_03958_amd/traffic.py summarise FETCH_DIR WRITE_DIR OUT``:
   reads the two ``*_counter_collection.csv`` files, scales each kernel's
@@ -51,7 +51,7 @@ def target() -> None:
         from paper_2107_03958_amd import api
     n = 2048
     plan = api.ConvPlan("log", n=n)
-    u = torch.as_tensor(np.random.default_rng(0).normal(size=(4, n, n))).cuda()
+    u = torch.as_tensor(np.random.default_rng(0).normal(size=(2 * plan.chunk, n, n))).cuda()   # two whole chunks
     out = torch.empty_like(u)
     work = torch.empty(plan.chunk * plan.work_bytes, dtype=torch.uint8, device="cuda")
     plan.apply(u, out=out, work=work)
