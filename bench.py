@@ -140,9 +140,12 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host, b=2,
     dom = int(np.argmax(avg_pass_ms))
     per_launch = pb[dom] * batch / ng                  # algorithmic bytes of one launch (average group)
     achieved = per_launch / (avg_pass_ms[dom] * 1e-3) / 1e9
+    # The PMC summary holds the bytes of a full-chunk dispatch; scaled here to the
+    # average launch of this batch (whose last chunk may hold fewer densities).
+    full = measured_traffic(PASS_NAMES[dom], precision, n, chunk) if b == 2 else None
+    traffic = None if full is None else full * (batch / ng) / chunk
     res["roofline"] = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=achieved, peak=PEAK_HBM_GBPS,
-                           unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
-                           traffic=measured_traffic(PASS_NAMES[dom], precision, n, chunk) if b == 2 else None,
+                           unit="GB/s", frac=achieved / PEAK_HBM_GBPS, traffic=traffic,
                            bytes_per_launch=per_launch, launch_avg_ms=float(avg_pass_ms[dom]))
     # Keep the last outputs of the first kernel for the FP32-vs-FP64 comparison.
     plans[0].apply(u, out=out, work=work)
