@@ -200,6 +200,20 @@ def test_fourier_smoothing_apply_n2048(api):
     assert metrics.rel_linf(got, ref) <= FP64_TOL
 
 
+@pytest.mark.parametrize("n", [128, 1024])
+def test_fourier_smoothing_apply_fp32(api, n):
+    # the FP32 smoothing pre-pass (synthesised spectrum, FP32 column and row
+    # transforms) against the FP64 oracle, to the FP32 bounds
+    R = 0.25
+    plan = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("laplace"))
+    fs = api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)
+    dens = smoothing.smoothed_disc_density(n, B, R, r2=0.39)
+    got = plan.apply(_gpu(np.ones((n, n)), torch.float32).unsqueeze(0), fs=[fs]).cpu().numpy()[0].astype(np.float64)
+    ref = np.real(scheme.apply(dens, oracle_table("laplace", n), B))
+    assert metrics.rel_linf(got, ref) <= 2e-6
+    assert metrics.rel_l2(got, ref) <= 5e-7
+
+
 def test_mixed_fs_and_plain_batch(api):
     n = 64
     plan = api.ConvPlan(n=n, **plan_kwargs("log"))
