@@ -49,10 +49,10 @@ struct Cfg {
   static constexpr int PF = LF / EF;
   static constexpr int NT_C = B * CPB * PF;
   static constexpr int SF = LineLayout<LF, EF>::STRIDE;
-  // FP64 column tiles whose cx<T> line buffers would leave room for only two
-  // blocks per CU exchange one real component at a time, through line buffers
-  // of T (half the LDS), so three blocks fit.
-  static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && B * CPB * SF * 16 * 3 > 163840 &&
+  // FP64 period-2 column tiles whose cx<T> line buffers would leave room for
+  // only two blocks per CU exchange one real component at a time, through
+  // line buffers of T (half the LDS), so three blocks fit.
+  static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && B == 2 && B * CPB * SF * 16 * 3 > 163840 &&
                                   B * CPB * SF * 8 * 3 <= 163840;
   static constexpr int LDS_C = SPLIT_C ? (B * CPB * SF + 1) / 2 : B * CPB * SF;   // cx<T> elements
   // Column tiles compiled for three blocks per CU (168 VGPRs), which load
