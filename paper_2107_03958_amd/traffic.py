@@ -103,8 +103,10 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
                           read_bytes=fetch[k] * 1024.0 * f_scale,
                           write_bytes=write.get(k, 0.0) * 1024.0 * w_scale)
         kernels[k]["traffic_bytes"] = kernels[k]["read_bytes"] + kernels[k]["write_bytes"]
-    res = dict(source_hash=source_hash(), densities_per_dispatch=_chunk(fetch_dir), calibration_kernel=ck, fetch_scale=f_scale, write_scale=w_scale,
-               copy_bytes=COPY_BYTES, workload="FP64 log|x| plan, n=2048, 4 densities (per-dispatch averages)",
+    chunk = _chunk(fetch_dir)
+    res = dict(source_hash=source_hash(), densities_per_dispatch=chunk, calibration_kernel=ck, fetch_scale=f_scale,
+               write_scale=w_scale, copy_bytes=COPY_BYTES,
+               workload=f"FP64 log|x| plan, n=2048, two chunks of {chunk} densities (per-dispatch averages)",
                kernels=kernels)
     with open(out + ".json", "w") as fh:
         json.dump(res, fh, indent=1)
