@@ -1,0 +1,25 @@
+"""Host parts of bench.py (CPU): the pass model and the one-GPU refusal."""
+import json
+
+import bench
+
+
+def test_pass_model_is_eleven_n2_s():
+    # per density at b = 2: rows n^2 s + 2n^2 s, columns 4n^2 s + (n+1)^2 s, rows 2n^2 s + n^2 s
+    for n, s in ((64, 8), (2048, 8), (2048, 4)):
+        pb = bench.pass_bytes(n, s)
+        assert pb == [3 * n * n * s, 4 * n * n * s + (n + 1) ** 2 * s, 3 * n * n * s]
+        assert abs(sum(pb) / (11 * n * n * s) - 1) < 3 / n
+
+
+def test_period3_pass_model():
+    n, s = 1024, 8
+    pb = bench.pass_bytes(n, s, b=3)
+    inter = 3 * n * n * s
+    assert pb == [n * n * s + inter, 2 * inter + (3 * n // 2 + 1) ** 2 * s, inter + n * n * s]
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert "one GPU" in out["error"] and out["n_gpus"] == 2
