@@ -209,10 +209,10 @@ struct Single {
   static constexpr int TPB = BLOCK / NT;
   static constexpr int LDS = TPB * KindOf<T, K, B>::template lds_tile<LOGN>();
   // Waves per SIMD the registers are sized for.  Row kernels: as many blocks
-  // as the LDS admits (at most 8 waves per SIMD).  Column kernels: at most two
-  // blocks per CU (their butterflies need the registers).
-  // FP32 row kernels stop at three waves (168 VGPRs): their FP64 twiddle
-  // runs do not fit the 128 VGPRs of four without spilling.
+  // as the LDS admits (at most 8 waves per SIMD; FP32 row kernels stop at
+  // three, 168 VGPRs, since their FP64 twiddle runs do not fit the 128 VGPRs
+  // of four without spilling).  Column kernels: at most two blocks per CU
+  // (their butterflies need the registers), or three for Cfg::THREE_C tiles.
   static constexpr int lds_waves() {
     const int blocks = 163840 / (LDS * (int)sizeof(cx<T>));
     const int w = blocks * BLOCK / 256;
