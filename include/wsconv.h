@@ -86,10 +86,22 @@ typedef struct {
                                conv_apply_multi, Fourier smoothing or mixed-precision ls_solve
                                (WS_EUNSUPPORTED) */
     double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
-                               the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the window
-                               [rho + sqrt(2)/2, b - 1/2 - rho] for a density supported in a disc of
-                               radius rho about (1/2, 1/2); an explicit a must satisfy 0 < a < b */
-    double support_radius;  /* informational: radius rho of the density's support about the centre */
+                               the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the disc window
+                               below.  The scheme computes the convolution only when a is at least
+                               the largest distance |x - y| between a target x in D and a point y
+                               of the density's support, and smaller than the distance from x to
+                               every periodic image of that support (Section 2.1, eq. io): for a
+                               density supported in the disc |y - (1/2, 1/2)| <= rho
+                               (support_radius = rho > 0) the window is
+                               [rho + sqrt(2)/2, b - 1/2 - rho]; for support anywhere in D
+                               (support_radius <= 0) it is [sqrt(2), b - 1], which is empty at
+                               b = 2.  A radius outside its window is WS_EINVAL unless force_a is
+                               set; any a must satisfy 0 < a < b */
+    double support_radius;  /* rho: the densities (and LS contrasts, and Fourier-smoothed
+                               densities out to their window radius psi_r2) vanish outside
+                               |y - (1/2, 1/2)| <= rho; <= 0: supported anywhere in D */
+    int    force_a;         /* nonzero: skip the window check of a (the operator is then the
+                               truncated kernel's, which differs from A where the window fails) */
 } ws_grid;
 
 /* Fourier smoothing descriptor for one density (Section 2.4, eqs. ls1, tfs).
@@ -98,7 +110,10 @@ typedef struct {
  * truncated b-periodic Fourier series of the shape's indicator on F_n and
  * psi(r) = 1 for r <= psi_r1, step((r - psi_r1)/(psi_r2 - psi_r1)) between,
  * 0 for r >= psi_r2, with r = |x - c| and step(t) = exp(2 e^{-1/t}/(t - 1)).
- * The centre must be a grid point (n*c1 and n*c2 integers) so chi^n is real. */
+ * The centre must be a grid point (n*c1 and n*c2 integers) so chi^n is real.
+ * The smoothed density vanishes beyond psi_r2 from the centre: with a plan
+ * built for support_radius rho > 0 and without force_a, |c - (1/2, 1/2)| +
+ * psi_r2 must not exceed rho (WS_EINVAL), so the a-window of the plan holds. */
 typedef struct {
     int    shape;          /* WS_FS_NONE, WS_FS_DISC or WS_FS_SQUARE */
     double c1, c2;         /* centre */

@@ -56,7 +56,9 @@ typedef struct {
 typedef struct {
     int kind;                 /* WS_REQ_APPLY or WS_REQ_LS */
     ws_kernel kernel;         /* WS_REQ_LS: must be WS_HELMHOLTZ */
-    int n;                    /* grid side, power of two in [16, 2048]; period b = 2, default a */
+    int n;                    /* grid side, power of two in [16, 2048]; period b = 2, default a.  The
+                                 density (LS: the contrast) must vanish beyond 0.39 of (1/2, 1/2),
+                                 the support for which the default a is valid at b = 2 (Section 2.1) */
     const void* input;        /* host.  Apply: density, float64 (WS_LOG, WS_POWER) or complex128
                                  (WS_HELMHOLTZ).  LS: incident field u_inc, complex128 */
     const double* contrast;   /* host, LS only: m = 1 - mu, float64 [n][n] */

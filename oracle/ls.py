@@ -16,9 +16,17 @@ contrast m = 1 - mu and the Helmholtz kernel g = (i/4) H0^(1)(kappa |x|).
                      The paper only says "matrix-free GMRES"; these settings
                      are a reading.
 
-Pins (tests/test_oracle_ls.py): gmres agrees with dense_solve at n = 8, 16;
-the residual of the returned solution, recomputed with ``matvec``, meets tol;
-for m = 0 the solution is u_inc.
+Pins (tests/test_oracle_smoothing_ls.py):
+* ``matvec`` against a manufactured radial solution: for a radial contrast m
+  and a radial field u about the centre, A(m u) for the Helmholtz kernel is
+  two 1D Bessel integrals (Graf's addition theorem keeps only the m = 0
+  harmonic), computed by adaptive quadrature without the scheme; with
+  u_inc := u + kappa^2 A(m u), ``matvec(u)`` -> u_inc and the solutions of
+  ``dense_solve`` / ``gmres`` -> u at the scheme's super-algebraic rate,
+  while the operator with the scattered term's sign flipped stays O(1) away;
+* gmres agrees with dense_solve at n = 8, 16; the residual of the returned
+  solution, recomputed with ``matvec``, meets tol; for m = 0 the solution is
+  u_inc.
 """
 from __future__ import annotations
 

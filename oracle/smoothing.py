@@ -23,10 +23,16 @@ Readings taken here (the paper is silent or garbled on these points):
   the disc centred at (0.5, 0.5) with n divisible by 4 the series is exactly real
   (the k = -nb/2 terms equal their k = +nb/2 mirror images).
 
-Pins (tests/test_oracle_smoothing.py): chihat against 2D quadrature of the
-indicator; chi^n against a brute-force sum of the series at sample points;
-the disc potential closed form for g = -(1/2pi) log with second-order
-convergence (Table conv_FS reports noc -> 2).
+Pins (tests/test_oracle_smoothing_ls.py): chihat (disc and square) against
+2D quadrature of the indicator; chi^n against a brute-force sum of the series
+at sample points; the windows' values (1 on Omega, 0 beyond the ramp or on
+the boundary of D, the smooth step's value at mid-ramp from 30-digit
+arithmetic, monotone, radial or separable); the disc potential closed form
+for g = -(1/2pi) log with second-order convergence; the square [0.3, 0.7]^2
+against its exact log potential (corner sum of an antiderivative of log|x|):
+Table conv_FS at b = 3 with the tensor window (second order, magnitudes
+within a small factor of the printed ones, the plain indicator first order)
+and the radial-window square at b = 2 (second order).
 """
 from __future__ import annotations
 
@@ -109,7 +115,9 @@ def smoothed_square_density(n: int, b: int, lo: float, hi: float, r1: float, r2:
 
 
 def tensor_window(n: int, lo: float, hi: float) -> np.ndarray:
-    """Product of 1D smooth steps: 1 on [lo, hi]^2, 0 on the boundary of D (b >= 3 runs)."""
+    """Product of 1D smooth steps: 1 on [lo, hi]^2, 0 on the boundary of D.
+
+    The window of Table conv_FS's square, whose support is all of D (so b = 3)."""
     t = np.arange(n) / n
     left = step((lo - t) / lo)            # 1 at t >= lo, 0 at t = 0
     right = step((t - hi) / (1.0 - hi))   # 1 at t <= hi, 0 at t = 1

@@ -29,7 +29,7 @@ class WsKernel(ctypes.Structure):
 
 
 class WsGrid(ctypes.Structure):
-    _fields_ = [("n", c_int), ("b", c_int), ("a", c_double), ("support_radius", c_double)]
+    _fields_ = [("n", c_int), ("b", c_int), ("a", c_double), ("support_radius", c_double), ("force_a", c_int)]
 
 
 class WsFsDesc(ctypes.Structure):

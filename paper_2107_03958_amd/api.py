@@ -53,12 +53,29 @@ def _dev_ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def default_support_radius(b: int) -> float:
+    """Support radius a plan declares when the caller names none.
+
+    b = 2: 0.39 about (1/2, 1/2), where every period-2 density here lives (the
+    C-infinity cutoff of radius 0.4 is below 1e-23 beyond r = 0.3964, and the
+    smoothing windows end at 0.39); the default a then lies in its window
+    [0.39 + sqrt(2)/2, 1.5 - 0.39] (Section 2.1).  b = 3: anywhere in D (0).
+    """
+    return 0.39 if b == 2 else 0.0
+
+
 class ConvPlan:
-    """A plan for A_n with one kernel, grid and precision (conv_plan)."""
+    """A plan for A_n with one kernel, grid and precision (conv_plan).
+
+    support_radius: radius about (1/2, 1/2) outside which the densities vanish
+    (None: default_support_radius(b)); a and the support are checked against
+    the validity window of Section 2.1 unless force_a is set.
+    """
 
     def __init__(self, family: str, n: int, b: int = 2, a: float = 0.0, scale: float = 1.0,
                  gamma: float = 0.0, kappa: float = 0.0, precision: str = "fp64",
-                 support_radius: float = 0.0, device="cuda", stream=None, beta: float = 0.0):
+                 support_radius: float | None = None, force_a: bool = False, device="cuda", stream=None,
+                 beta: float = 0.0):
         self.lib = L.load()
         self.family = family
         self.n = n
@@ -69,7 +86,10 @@ class ConvPlan:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self.kernel = L.WsKernel(_FAMILIES[family], scale, gamma, kappa, beta)
-        self.grid = L.WsGrid(n, b, a, support_radius)
+        if support_radius is None:
+            support_radius = default_support_radius(b)
+        self.support_radius = support_radius
+        self.grid = L.WsGrid(n, b, a, support_radius, 1 if force_a else 0)
         prec = _PRECISIONS[precision]
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         L.check(self.lib.conv_plan_query(ctypes.byref(self.kernel), ctypes.byref(self.grid), prec,

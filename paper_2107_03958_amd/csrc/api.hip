@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
@@ -47,6 +48,21 @@ int check_kernel(const ws_kernel* k) {
   }
 }
 
+// Validity window of the truncation radius (Section 2.1, eq. io): a must reach
+// from any target x in D across the density's support, and stay short of
+// every periodic image of that support.  Support in the disc of radius rho
+// about (1/2, 1/2): [rho + sqrt(2)/2, b - 1/2 - rho]; support anywhere in D:
+// [sqrt(2), b - 1].
+void a_window(int b, double rho, double* lo, double* hi) {
+  if (rho > 0.0) {
+    *lo = rho + std::sqrt(2.0) / 2.0;
+    *hi = b - 0.5 - rho;
+  } else {
+    *lo = std::sqrt(2.0);
+    *hi = b - 1.0;
+  }
+}
+
 int check_grid(const ws_grid* g, double* a_out, int* logn) {
   if (!g) return fail(WS_EINVAL, "grid descriptor is NULL");
   if (g->n <= 0 || (g->n & (g->n - 1))) return fail(WS_EUNSUPPORTED, "n must be a power of two");
@@ -54,9 +70,23 @@ int check_grid(const ws_grid* g, double* a_out, int* logn) {
   if (g->b < 1) return fail(WS_EINVAL, "period b must be a positive integer");
   if (g->b != 2 && g->b != 3) return fail(WS_EUNSUPPORTED, "period b must be 2 or 3 (FFT length 2n or 3n)");
   if (g->b == 3 && g->n > 1024) return fail(WS_EUNSUPPORTED, "period b = 3 supports n <= 1024");
+  if (!std::isfinite(g->support_radius) || g->support_radius >= std::sqrt(2.0) / 2.0)
+    return fail(WS_EINVAL, "support_radius must be finite and below sqrt(2)/2 (<= 0: all of D)");
   double a = g->a;
   if (!(a > 0.0)) a = (g->b + std::sqrt(2.0) / 2.0 - 0.5) / 2.0;
   if (!(a < g->b) || !std::isfinite(a)) return fail(WS_EINVAL, "truncation radius must satisfy 0 < a < b");
+  if (!g->force_a) {
+    double lo, hi;
+    a_window(g->b, g->support_radius, &lo, &hi);
+    if (a < lo - 1e-12 || a > hi + 1e-12) {
+      char msg[256];
+      std::snprintf(msg, sizeof msg,
+                    "truncation radius a = %.17g lies outside its validity window [%.17g, %.17g] for period "
+                    "b = %d and support radius %g (Section 2.1; force_a overrides)",
+                    a, lo, hi, g->b, g->support_radius);
+      return fail(WS_EINVAL, msg);
+    }
+  }
   *a_out = a;
   int l = 0;
   while ((1 << l) < g->n) ++l;
@@ -96,7 +126,8 @@ Sizes sizes_for(int n, int b, bool cplx, int precision, double beta = 0.0) {
   return s;
 }
 
-int check_fs(const ws_fs_desc& d, int n) {
+int check_fs(const ws_fs_desc& d, const ws::Plan& p) {
+  const int n = p.n;
   if (d.shape == WS_FS_NONE) return WS_OK;
   if (d.shape != WS_FS_DISC && d.shape != WS_FS_SQUARE) return fail(WS_EINVAL, "unknown smoothing shape");
   if (!(d.size > 0.0)) return fail(WS_EINVAL, "smoothing shape size must be positive");
@@ -104,6 +135,11 @@ int check_fs(const ws_fs_desc& d, int n) {
   const double e1 = d.c1 * n - std::nearbyint(d.c1 * n), e2 = d.c2 * n - std::nearbyint(d.c2 * n);
   if (std::fabs(e1) > 1e-9 || std::fabs(e2) > 1e-9)
     return fail(WS_EUNSUPPORTED, "smoothing centre must be a grid point (n*c integer)");
+  // The smoothed density lives within psi_r2 of c: it must stay inside the
+  // support the plan's a-window was checked for.
+  if (!p.force_a && p.support_radius > 0.0 &&
+      std::hypot(d.c1 - 0.5, d.c2 - 0.5) + d.psi_r2 > p.support_radius + 1e-12)
+    return fail(WS_EINVAL, "smoothing window reaches beyond the plan's support radius (|c - centre| + psi_r2 > rho)");
   return WS_OK;
 }
 
@@ -162,6 +198,8 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   p->nb = grid->n * grid->b;
   p->logn = logn;
   p->a = a;
+  p->support_radius = grid->support_radius;
+  p->force_a = grid->force_a != 0;
   p->precision = precision;
   p->cplx = cplx;
   char* base = static_cast<char*>(plan_buf);
@@ -233,7 +271,7 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
   bool any_fs = false;
   if (fs) {
     for (int i = 0; i < batch; ++i) {
-      int rc = check_fs(fs[i], p.n);
+      int rc = check_fs(fs[i], p);
       if (rc) return rc;
       any_fs = any_fs || fs[i].shape != WS_FS_NONE;
     }
@@ -393,7 +431,7 @@ int ls_solve_fs_query(ws_plan_t plan, const ws_fs_desc* fs, int restart, int mix
   if (!fs) return fail(WS_EINVAL, "smoothing descriptor is NULL");
   if (plan->b != 2) return fail(WS_EUNSUPPORTED, "Fourier smoothing is implemented for period b = 2");
   if (fs->shape == WS_FS_NONE) return fail(WS_EINVAL, "ls_solve_fs needs a disc or square");
-  int rc = check_fs(*fs, plan->n);
+  int rc = check_fs(*fs, *plan);
   if (rc) return rc;
   size_t ls = 0;
   if ((rc = ls_solve_query(plan, restart, mixed_precision, &ls))) return rc;

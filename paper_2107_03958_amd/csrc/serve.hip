@@ -17,6 +17,10 @@
 #include "plan.hpp"
 #include "serve_core.hpp"
 
+// Support radius every request declares (wsserve.h): the window of the
+// default truncation radius at period b = 2 holds for it (Section 2.1).
+constexpr double kServeSupport = 0.39;
+
 namespace {
 
 constexpr int kConvBlocks = 2048, kConvThreads = 256;
@@ -78,7 +82,7 @@ int check_config(const ws_serve_config* c) {
 int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
   if (!r) return ws::set_last_error(WS_EINVAL, "request is NULL");
   if (r->kind != WS_REQ_APPLY && r->kind != WS_REQ_LS) return ws::set_last_error(WS_EINVAL, "unknown request kind");
-  ws_grid grid{r->n, 2, 0.0, 0.0};
+  ws_grid grid{r->n, 2, 0.0, kServeSupport, 0};
   size_t plan_bytes = 0, work = 0;
   int rc = conv_plan_query(&r->kernel, &grid, cfg.precision, &plan_bytes, &work);
   if (rc) return rc;
@@ -268,7 +272,7 @@ void worker(Engine* E, int w) {
     std::string err;
     int rc = WS_OK;
     if (g.build_plan) {
-      ws_grid grid{g.key.n, 2, 0.0, 0.0};
+      ws_grid grid{g.key.n, 2, 0.0, kServeSupport, 0};
       rc = conv_plan(&rq[0].kernel, &grid, g.key.precision, E->base + g.plan_off, s, &plan);
       if (rc == WS_OK) {
         const hipError_t e = hipStreamSynchronize(s);

@@ -11,6 +11,12 @@ from oracle import moments
 B = 2
 A_DEFAULT = (B + math.sqrt(2) / 2 - 0.5) / 2
 
+# Upper bounds of cond_2(I + kappa^2 A_n M) for the LS workload (contrast 0.5 cut(r), b = 2,
+# default a): the oracle's dense SVD gives 8.49 / 8.38 / 8.34 (kappa = 20, n = 16 / 32 / 64),
+# 29.1 / 27.7 / 27.4 (kappa = 40), 91 / 110 / 109 (kappa = 80).  Checked at n = 32 by
+# tests/test_oracle_smoothing_ls.py.
+COND_BOUND = {20.0: 10.0, 40.0: 35.0, 80.0: 150.0}
+
 KERNELS = {
     "laplace": dict(family="log", scale=-1.0 / (2.0 * math.pi)),
     "log": dict(family="log", scale=1.0),

@@ -38,9 +38,9 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(L.EXPORTS), "binding and header disagree"
 
 
-def _query(lib, family=L.WS_LOG, n=64, b=2, a=0.0, gamma=0.0, kappa=0.0, prec=L.WS_FP64):
+def _query(lib, family=L.WS_LOG, n=64, b=2, a=0.0, gamma=0.0, kappa=0.0, prec=L.WS_FP64, rho=None, force=0):
     k = L.WsKernel(family, 1.0, gamma, kappa)
-    g = L.WsGrid(n, b, a, 0.0)
+    g = L.WsGrid(n, b, a, (0.39 if b == 2 else 0.0) if rho is None else rho, force)
     pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
     rc = lib.conv_plan_query(ctypes.byref(k), ctypes.byref(g), prec, ctypes.byref(pb), ctypes.byref(wb))
     return rc, pb.value, wb.value
@@ -98,7 +98,7 @@ def test_null_handles_rejected(lib):
     assert lib.ls_solve(None, None, None, 1e-8, 50, 100, 0, None, None, ctypes.byref(info), None) == L.WS_EINVAL
     h = ctypes.c_void_p()
     k = L.WsKernel(L.WS_LOG, 1.0, 0.0, 0.0)
-    g = L.WsGrid(64, 2, 0.0, 0.0)
+    g = L.WsGrid(64, 2, 0.0, 0.39, 0)
     assert lib.conv_plan(ctypes.byref(k), ctypes.byref(g), L.WS_FP64, None, None, ctypes.byref(h)) == L.WS_EINVAL
     assert lib.conv_plan_radius(None) == 0.0
     lib.conv_destroy(None)
@@ -134,3 +134,28 @@ def test_serve_footprint_covers_ls_workspace(lib, precision):
     krylov = (restart + 3) * N * esz                 # V (restart + 1), r, t
     apply_work = n * 2 * n * esz                     # the matvec's intermediate
     assert fp.value - plan_bytes - own >= krylov + apply_work
+
+
+def test_truncation_radius_window(lib):
+    # Section 2.1: a must cover every target-to-support distance and stay short of the
+    # periodic images.  Disc support rho about the centre: [rho + sqrt(2)/2, b - 1/2 - rho];
+    # support anywhere in D: [sqrt(2), b - 1].
+    import math
+    ok, bad = L.WS_OK, L.WS_EINVAL
+    assert _query(lib, b=2, rho=0.39)[0] == ok                       # default a = 1.1036 in [1.0971, 1.11]
+    assert _query(lib, b=2, rho=0.4)[0] == bad                       # [1.1071, 1.1] is empty
+    assert _query(lib, b=2, rho=0.0)[0] == bad                       # [sqrt 2, 1] is empty at b = 2
+    assert _query(lib, b=2, rho=0.0, force=1)[0] == ok               # forced
+    assert _query(lib, b=2, rho=0.2, a=0.3)[0] == bad                # a below rho + sqrt(2)/2
+    assert _query(lib, b=2, rho=0.2, a=0.3, force=1)[0] == ok
+    assert _query(lib, b=2, rho=0.2, a=0.2 + math.sqrt(2) / 2)[0] == ok   # window ends are valid
+    assert _query(lib, b=2, rho=0.2, a=1.3)[0] == ok
+    assert _query(lib, b=2, rho=0.2, a=1.31)[0] == bad               # beyond b - 1/2 - rho
+    assert _query(lib, b=3, rho=0.0)[0] == ok                        # default 1.6036 in [sqrt 2, 2]
+    assert _query(lib, b=3, rho=0.0, a=1.4)[0] == bad
+    assert _query(lib, b=3, rho=0.0, a=2.05)[0] == bad
+    assert _query(lib, b=3, rho=0.0, a=2.0)[0] == ok
+    assert _query(lib, b=2, rho=0.8)[0] == bad                       # rho >= sqrt(2)/2: not a disc in D
+    assert _query(lib, b=2, a=2.5, force=1)[0] == bad                # 0 < a < b always
+    rc = _query(lib, b=2, rho=0.2, a=0.3)[0]
+    assert "validity window" in lib.conv_last_error().decode()

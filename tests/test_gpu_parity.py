@@ -63,6 +63,29 @@ def test_real_apply_n512_log(api, n):
         assert metrics.rel_linf(got[i], np.real(scheme.apply(us[i], g, B))) <= FP64_TOL
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_power_apply_n512_config1(api, precision):
+    # The batched-apply workload's second kernel |x|^-1/2 at its larger grid (512^2, a
+    # 1024^2 FFT): smooth densities and a Fourier-smoothed disc against the oracle.
+    n = 512
+    us = np.stack([synth.smooth_density(n, synth.SEED_SMOOTH_BATCH + i) for i in range(2)]
+                  + [np.ones((n, n))])
+    R = synth.disc_radius(synth.SEED_DISC_BATCH)
+    fs = [None, None, api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)]
+    plan = api.ConvPlan(n=n, precision=precision, **plan_kwargs("pow-1/2"))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    got = plan.apply(_gpu(us, dt), fs=fs).cpu().numpy().astype(np.float64)
+    g = oracle_table("pow-1/2", n)
+    dens = [us[0], us[1], smoothing.smoothed_disc_density(n, B, R, r2=0.39)]
+    for i in range(3):
+        ref = np.real(scheme.apply(dens[i], g, B))
+        if precision == "fp64":
+            assert metrics.rel_linf(got[i], ref) <= FP64_TOL, i
+        else:
+            assert metrics.rel_linf(got[i], ref) <= 2e-6 and metrics.rel_l2(got[i], ref) <= 5e-7, i
+
+
 @pytest.fixture(scope="module")
 def full_size_case():
     """Four seeded smooth densities at the largest grid (2048^2, a 4096^2 FFT) and their oracle applies."""
