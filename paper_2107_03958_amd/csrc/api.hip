@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -121,8 +122,7 @@ Sizes sizes_for(int n, int b, bool cplx, int precision, double beta = 0.0) {
   s.nyq32 = (precision == WS_FP32 && !cplx) ? align_up((nb / 2 + 1) * 4) : 0;
   s.total = s.tw64 + s.tw32 + s.g64 + s.nyq64 + s.g32 + s.nyq32;
   if (beta > 0.0) s.total += ws::local_scratch_bytes(n, b, beta);
-  const size_t elem = precision == WS_FP32 ? 8 : 16;
-  s.work = (size_t)n * ws::inter_cols(n, b, cplx) * elem;
+  s.work = ws::inter_bytes(n, b, cplx, precision);
   return s;
 }
 
@@ -254,9 +254,13 @@ int conv_apply_chunk(ws_plan_t plan) {
   return ws::apply_chunk(*plan);
 }
 
-int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work, const ws_fs_desc* fs,
-               void* stream) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+// conv_apply with `chunk` densities per pass round (<= 0: the plan's chunk);
+// `work` holds that many intermediates.
+int apply_checked(ws_plan_t plan, int batch, const void* density, void* out, void* work, const ws_fs_desc* fs,
+                  void* stream, int chunk) {
   if (!plan) return fail(WS_EINVAL, "plan is NULL");
   if (batch < 0) return fail(WS_EINVAL, "batch must be >= 0");
   if (batch == 0) return WS_OK;
@@ -300,20 +304,32 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
     }
     if (e == hipSuccess) {
       if (p.precision == WS_FP64)
-        e = ws::launch_apply_real<double>(p, batch, (const double*)src, (double*)out, (ws::cx<double>*)work, s);
+        e = ws::launch_apply_real<double>(p, batch, (const double*)src, (double*)out, (ws::cx<double>*)work, s,
+                                          chunk);
       else
-        e = ws::launch_apply_real<float>(p, batch, (const float*)src, (float*)out, (ws::cx<float>*)work, s);
+        e = ws::launch_apply_real<float>(p, batch, (const float*)src, (float*)out, (ws::cx<float>*)work, s,
+                                         chunk);
     }
   } else {
     if (p.precision == WS_FP64)
       e = ws::launch_apply_cplx<double>(p, batch, (const ws::cx<double>*)density, nullptr, 1.0, false,
-                                        (ws::cx<double>*)out, (ws::cx<double>*)work, s);
+                                        (ws::cx<double>*)out, (ws::cx<double>*)work, s, nullptr, chunk);
     else
       e = ws::launch_apply_cplx<float>(p, batch, (const ws::cx<float>*)density, nullptr, 1.0f, false,
-                                       (ws::cx<float>*)out, (ws::cx<float>*)work, s);
+                                       (ws::cx<float>*)out, (ws::cx<float>*)work, s, nullptr, chunk);
   }
   if (e != hipSuccess) return hip_fail(e, "conv_apply");
   return WS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work, const ws_fs_desc* fs,
+               void* stream) {
+  g_err.clear();
+  return apply_checked(plan, batch, density, out, work, fs, stream, 0);
 }
 
 int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
@@ -421,7 +437,7 @@ int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol
 // smoothing pre-pass intermediate (n x n complex128), then ls_solve's.
 static size_t fs_contrast_bytes(const ws::Plan& p) {
   const size_t nn = (size_t)p.n * p.n;
-  return align_up(nn * sizeof(double)) + align_up(nn * sizeof(ws::cx<double>));
+  return align_up(nn * sizeof(double)) + align_up(ws::inter_bytes(p.n, p.b, false, WS_FP64));
 }
 
 int ls_solve_fs_query(ws_plan_t plan, const ws_fs_desc* fs, int restart, int mixed_precision,

@@ -1,4 +1,4 @@
-// Tile geometry of the apply kernels (apply.hip): threads, LDS and tile
+// Tile geometry of the apply kernels (apply_impl.hpp): threads, LDS and tile
 // shapes per grid size, block sizes per kind of pass, and the block -> tile
 // and thread -> element maps.  Host and device code, so the geometry can be
 // checked on a host without a GPU.

@@ -1,3 +1,7 @@
+// Templates of the apply kernels and their launchers, instantiated for FP64
+// in apply_f64.hip and for FP32 in apply_f32.hip (two translation units
+// compiled in parallel).
+#pragma once
 // The FFT apply of A_n (Section 2.1, eq. An) for b = 2 (nb = 2n), as three
 // passes over HBM per density:
 //
@@ -199,7 +203,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
-  cx<T>* dst = sg.work + batch * (size_t)n * N;
+  cx<T>* dst = sg.work + batch * inter_elems<T>(n, N);
   auto unpack = [&](int it, auto twiddle) {
     const int k = k0 + it * DK, cb = (tid + it * NT) / (CB * RPB);
     const cx<T> zk = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
@@ -213,7 +217,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
       const cx<T> d = cscale(zk - zm, (T)0.5);
       val = a + twiddle(cx<T>{d.y, -d.x}, k);        // + w_nb^k (-i d)
     }
-    dst[((size_t)cb * n + row0 + rr) * CB + c] = val;
+    dst[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] = val;
   };
   if constexpr (RUN) {
     cx<W> wk[IT];
@@ -236,7 +240,7 @@ __device__ __forceinline__ void rows_fwd_real_tile(const Seg<T>& sg, int t, bool
         const cx<T> d = cscale(zk - zm, (T)0.5);
         val = a + tw.template mul<-1>(cx<T>{d.y, -d.x}, k);
       }
-      dst[((size_t)cb * n + row0 + ri) * CB + ci] = val;
+      dst[cb * blk_stride<T>(n) + (size_t)(row0 + ri) * CB + ci] = val;
     }
   }
 }
@@ -314,7 +318,7 @@ struct ColGeo {
     c = csub * CPB + cc;                                 // column within the block-column cb
   }
   __device__ __forceinline__ cx<T>* col(cx<T>* work) const {
-    return work + batch * (size_t)n * NCOLS + (size_t)cb * n * CB;
+    return work + batch * inter_elems<T>(n, NCOLS) + (size_t)cb * blk_stride<T>(n);
   }
 };
 
@@ -670,12 +674,12 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
     }
   }
   {
-    const cx<T>* src = sg.work + batch * n * N;
+    const cx<T>* src = sg.work + batch * inter_elems<T>(n, N);
     for (int idx = tid; idx < RPB * N; idx += NT) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
       lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
-          (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
+          (!GUARD || valid) ? src[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] : cx<T>{0, 0};
     }
   }
   __syncthreads();
@@ -785,11 +789,11 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
   for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[0][reg];
   __syncthreads();
   if (GUARD && !valid) return;
-  cx<T>* dst = sg.work + (size_t)(t / TPD) * n * nb;
+  cx<T>* dst = sg.work + (size_t)(t / TPD) * inter_elems<T>(n, nb);
   for (int idx = tid; idx < RPB * nb; idx += NT) {
     const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
     const int k = cb * CB + c;
-    dst[((size_t)cb * n + row0 + rr) * CB + c] = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
+    dst[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
   }
 }
 
@@ -820,13 +824,13 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
     }
   }
   {
-    const cx<T>* src = sg.work + (size_t)(t / TPD) * n * nb;
+    const cx<T>* src = sg.work + (size_t)(t / TPD) * inter_elems<T>(n, nb);
     const int row0 = (t % TPD) * RPB;
     for (int idx = tid; idx < RPB * nb; idx += NT) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
       lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
-          (!GUARD || valid) ? src[((size_t)cb * n + row0 + rr) * CB + c] : cx<T>{0, 0};
+          (!GUARD || valid) ? src[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] : cx<T>{0, 0};
     }
   }
   __syncthreads();
@@ -971,8 +975,8 @@ __global__ __launch_bounds__((KindOf<T, K>::BLK), (KindOf<T, K>::WAVES)) void k_
 // ----------------------------------------------------------------------------
 // Host side.
 template <typename T> typename TwOf<T>::type make_tw(const Plan& p);
-template <> TwD make_tw<double>(const Plan& p) { return TwD{p.tw64}; }
-template <> TwOf<float>::type make_tw<float>(const Plan& p) {
+template <> inline TwD make_tw<double>(const Plan& p) { return TwD{p.tw64}; }
+template <> inline TwOf<float>::type make_tw<float>(const Plan& p) {
 #if WS_TW32_POWERS
   return TwDF{p.tw64};
 #else
@@ -981,11 +985,11 @@ template <> TwOf<float>::type make_tw<float>(const Plan& p) {
 }
 
 template <typename T> const void* gtab_of(const Plan& p);
-template <> const void* gtab_of<double>(const Plan& p) { return p.g64; }
-template <> const void* gtab_of<float>(const Plan& p) { return p.g32; }
+template <> inline const void* gtab_of<double>(const Plan& p) { return p.g64; }
+template <> inline const void* gtab_of<float>(const Plan& p) { return p.g32; }
 template <typename T> const T* gnyq_of(const Plan& p);
-template <> const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
-template <> const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
+template <> inline const double* gnyq_of<double>(const Plan& p) { return p.gnyq64; }
+template <> inline const float* gnyq_of<float>(const Plan& p) { return p.gnyq32; }
 
 // Tiles per density, threads per tile and the single-size block of a kind of pass at size 2^logn.
 struct Geo {
@@ -1118,9 +1122,9 @@ hipError_t launch_pass_real(const Plan& p, int pass, int batch, const T* u, T* o
 }
 
 template <typename T>
-hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s) {
+hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s, int chunk) {
   const size_t nn = (size_t)p.n * p.n;
-  const int chunk = apply_chunk(p);
+  if (chunk <= 0) chunk = apply_chunk(p);
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = batch - b0 < chunk ? batch - b0 : chunk;
     for (int pass = 0; pass < 3; ++pass) {
@@ -1154,9 +1158,9 @@ static hipError_t pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, 
 
 template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
+                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip, int chunk) {
   const size_t nn = (size_t)p.n * p.n;
-  const int chunk = apply_chunk(p);
+  if (chunk <= 0) chunk = apply_chunk(p);
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = batch - b0 < chunk ? batch - b0 : chunk;
     for (int pass = 0; pass < 3; ++pass) {
@@ -1171,45 +1175,6 @@ template <typename T>
 hipError_t launch_pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, cx<T>* out, cx<T>* work,
                             hipStream_t s) {
   return pass_cplx<T>(p, pass, batch, v, nullptr, (T)1, false, out, work, s, nullptr);
-}
-
-// Coefficients c(k) = ghat(k) uhat_{e,n}(k) on all of F_n for one complex
-// density v (FP64 plan): complex-path forward rows into `inter` (n x nb),
-// then the spectrum column pass into spec (nb x nb, row-major).
-template <int B>
-static hipError_t spectrum_b(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
-                             hipStream_t s) {
-  hipError_t e = launch_one<double, kRowsFwdCplx>(p, 1, v, nullptr, inter, s);
-  if (e != hipSuccess) return e;
-  const double* gnyq = p.cplx ? nullptr : p.gnyq64;
-  switch (p.logn) {
-#define WS_CASE(L)                                                                                  \
-  case L: {                                                                                         \
-    using S1 = Single<double, kColsCplx, L, B>;                                                     \
-    if constexpr (B == 2 || L <= kMaxLognB3) {                                                      \
-      const int ntiles = KindOf<double, kColsCplx, B>::template tiles_per_density<L>();              \
-      const int nblocks = (ntiles + S1::TPB - 1) / S1::TPB;                                         \
-      if (p.cplx)                                                                                   \
-        k_spec<L, false, B><<<nblocks, S1::BLOCK, 0, s>>>(inter, spec, p.g64, gnyq, TwD{p.tw64}, ntiles); \
-      else                                                                                          \
-        k_spec<L, true, B><<<nblocks, S1::BLOCK, 0, s>>>(inter, spec, p.g64, gnyq, TwD{p.tw64}, ntiles);  \
-      return hipGetLastError();                                                                     \
-    }                                                                                               \
-    return hipErrorInvalidValue;                                                                    \
-  }
-    WS_FOR_EACH_LOGN(WS_CASE)
-#undef WS_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_spectrum(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
-                           hipStream_t s) {
-  if (p.precision != WS_FP64 || p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
-  if (p.b == 2) return spectrum_b<2>(p, v, inter, spec, s);
-  if (p.b == 3) return spectrum_b<3>(p, v, inter, spec, s);
-  return hipErrorInvalidValue;
 }
 
 // Several plans in one set of launches: round r takes the r-th chunk of every
@@ -1258,25 +1223,5 @@ hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipS
     }
   }
 }
-
-template hipError_t launch_pass_real<double>(const Plan&, int, int, const double*, double*, cx<double>*,
-                                             hipStream_t);
-template hipError_t launch_pass_real<float>(const Plan&, int, int, const float*, float*, cx<float>*, hipStream_t);
-template hipError_t launch_pass_cplx<double>(const Plan&, int, int, const cx<double>*, cx<double>*, cx<double>*,
-                                             hipStream_t);
-template hipError_t launch_pass_cplx<float>(const Plan&, int, int, const cx<float>*, cx<float>*, cx<float>*,
-                                            hipStream_t);
-template hipError_t launch_apply_real<double>(const Plan&, int, const double*, double*, cx<double>*, hipStream_t);
-template hipError_t launch_apply_real<float>(const Plan&, int, const float*, float*, cx<float>*, hipStream_t);
-template hipError_t launch_fs_real<double>(const Plan&, const double*, double*, cx<double>*, const ws_fs_desc&,
-                                           hipStream_t);
-template hipError_t launch_fs_real<float>(const Plan&, const float*, float*, cx<float>*, const ws_fs_desc&,
-                                          hipStream_t);
-template hipError_t launch_apply_cplx<double>(const Plan&, int, const cx<double>*, const double*, double, bool,
-                                              cx<double>*, cx<double>*, hipStream_t, const int*);
-template hipError_t launch_apply_cplx<float>(const Plan&, int, const cx<float>*, const float*, float, bool,
-                                             cx<float>*, cx<float>*, hipStream_t, const int*);
-template hipError_t launch_apply_multi<double>(const ApplyItem*, int, bool, hipStream_t);
-template hipError_t launch_apply_multi<float>(const ApplyItem*, int, bool, hipStream_t);
 
 }  // namespace ws

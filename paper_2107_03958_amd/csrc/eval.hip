@@ -1,7 +1,7 @@
 // Evaluation of A_n u at arbitrary points (Section 2.1: eq. An read at any x
 // in the plane; the quadrature form of eqs. quad / quad_wts gives the same
 // sum).  The coefficients c(k) = ghat(k) uhat_{e,n}(k) on F_n come from the
-// spectrum pass (apply.hip); this file sums the series
+// spectrum pass (apply_f64.hip); this file sums the series
 //     (A_n u)(x) = sum_{k in F_n} c(k) exp(2 pi i k.x / b)
 // directly at each target: O(|F_n|) per target, for callers with modest
 // numbers of scattered points.  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
@@ -128,7 +128,7 @@ EvalWork eval_work(const Plan& p) {
   EvalWork w{};
   const size_t n = p.n, nb = (size_t)p.b * p.n;
   w.widen = p.cplx ? 0 : align256(n * n * sizeof(cx<double>));
-  w.inter = align256(n * nb * sizeof(cx<double>));
+  w.inter = align256(inter_elems<double>((int)n, (int)nb) * sizeof(cx<double>));
   w.spec = align256(nb * nb * sizeof(cx<double>));
   w.total = w.widen + w.inter + w.spec;
   return w;

@@ -353,7 +353,7 @@ struct Krylov {
   cx<T>* V = nullptr;        // restart + 1 vectors
   cx<T>* r = nullptr;
   cx<T>* t = nullptr;
-  cx<T>* awork = nullptr;    // apply intermediate (n x nb)
+  cx<T>* awork = nullptr;    // apply intermediate (n x nb, blocked)
 
   static size_t bytes(int restart, size_t N, int n, int nb) {
     size_t b = align_up(sizeof(GState));
@@ -361,7 +361,7 @@ struct Krylov {
     b += 3 * align_up(sizeof(cx<double>) * (size_t)(restart + 1)) + 2 * align_up(sizeof(cx<double>) * restart);
     b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks) + align_up(sizeof(double) * kBlocks);
     b += align_up(sizeof(cx<T>) * (size_t)(restart + 1) * N) + 2 * align_up(sizeof(cx<T>) * N);
-    b += align_up(sizeof(cx<T>) * (size_t)n * nb);
+    b += align_up(sizeof(cx<T>) * inter_elems<T>(n, nb));
     return b;
   }
   char* carve(char* base, int rs, size_t n_elems, int n, int nb) {
@@ -384,7 +384,7 @@ struct Krylov {
     V = (cx<T>*)take(sizeof(cx<T>) * (size_t)(rs + 1) * N);
     r = (cx<T>*)take(sizeof(cx<T>) * N);
     t = (cx<T>*)take(sizeof(cx<T>) * N);
-    awork = (cx<T>*)take(sizeof(cx<T>) * (size_t)n * nb);
+    awork = (cx<T>*)take(sizeof(cx<T>) * inter_elems<T>(n, nb));
     return base;
   }
 };

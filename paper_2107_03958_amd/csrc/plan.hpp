@@ -74,6 +74,11 @@ namespace ws {
 #define WS_CHUNK_BYTES (128u << 20)
 #endif
 
+// Padding (elements) between consecutive column blocks of the intermediate.
+#ifndef WS_BLOCK_PAD
+#define WS_BLOCK_PAD 0
+#endif
+
 template <typename T> struct Layout;
 template <> struct Layout<double> {
   static constexpr int CB = WS_CB64, RPB = WS_RPB64, ER = WS_ER64, ERF = WS_ERF64, EC = WS_EC64, CPB1 = WS_CPB64;
@@ -113,6 +118,22 @@ int set_last_error(int code, const std::string& msg);
 // and Nyquist columns packed into one), nb on the complex path.
 inline size_t inter_cols(int n, int b, bool cplx) { return cplx ? (size_t)b * n : (size_t)b * n / 2; }
 
+// Intermediate of one density: ncols / CB column blocks of n rows x CB
+// columns, element (row, k) of block cb = k / CB at cb * blk_stride + row * CB
+// + k % CB, blocks blk_stride = n CB + WS_BLOCK_PAD elements apart.
+template <typename T>
+__host__ __device__ constexpr size_t blk_stride(int n) { return (size_t)n * Layout<T>::CB + WS_BLOCK_PAD; }
+template <typename T>
+__host__ __device__ constexpr size_t inter_elems(int n, int ncols) {
+  return (size_t)(ncols / Layout<T>::CB) * blk_stride<T>(n);
+}
+// Bytes of one density's intermediate for a plan's (n, b, path, precision).
+inline size_t inter_bytes(int n, int b, bool cplx, int precision) {
+  const int nc = (int)inter_cols(n, b, cplx);
+  return precision == WS_FP64 ? inter_elems<double>(n, nc) * sizeof(cx<double>)
+                              : inter_elems<float>(n, nc) * sizeof(cx<float>);
+}
+
 inline int apply_chunk(const Plan& p) {
   const size_t per = (size_t)p.n * inter_cols(p.n, p.b, p.cplx) * (p.precision == WS_FP64 ? 16 : 8);
   const size_t c = (size_t)WS_CHUNK_BYTES / per;
@@ -123,10 +144,13 @@ inline int apply_chunk(const Plan& p) {
 // per intermediate column (the real path's Nyquist column is stored apart).
 inline size_t table_elems(int n, int b, bool cplx) { return ((size_t)b * n / 2 + 1) * inter_cols(n, b, cplx); }
 
-// Launchers (apply.hip).  Each returns the hipError_t of its launches.
+// Launchers (apply_impl.hpp, instantiated in apply_f64.hip / apply_f32.hip).  Each returns the hipError_t of its launches.
 // Real path (WS_LOG / WS_POWER): out = A_n u for `batch` real densities.
+// chunk: densities taken through all three passes at a time (<= 0: apply_chunk(p));
+// work holds that many intermediates.
 template <typename T>
-hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s);
+hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>* work, hipStream_t s,
+                             int chunk = 0);
 // Fourier-smoothing pre-pass (real path): out = u_tilde * Re(chi^n) * psi for one density.
 template <typename T>
 hipError_t launch_fs_real(const Plan& p, const T* u_tilde, T* out, cx<T>* work, const ws_fs_desc& fs,
@@ -135,7 +159,7 @@ hipError_t launch_fs_real(const Plan& p, const T* u_tilde, T* out, cx<T>* work, 
 // skip: optional device flag; when it reads nonzero the kernels return at entry.
 template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add_input,
-                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr);
+                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr, int chunk = 0);
 
 // Single passes of the apply (pass 0: rows forward, 1: columns, 2: rows inverse).
 template <typename T>
@@ -160,7 +184,7 @@ hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipS
 
 // Coefficients c(k) = ghat(k) uhat_{e,n}(k), k in F_n, of one complex density
 // v of an FP64 plan: spec is nb x nb complex, row-major over the bins (k1, k2);
-// inter is n x nb complex scratch (apply.hip).
+// inter is n x nb complex scratch (apply_f64.hip).
 hipError_t launch_spectrum(const Plan& p, const cx<double>* v, cx<double>* inter, cx<double>* spec,
                            hipStream_t s);
 

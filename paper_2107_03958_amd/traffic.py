@@ -2,9 +2,10 @@
 
 Two modes:
 
-* ``python paper_2107_03958_amd/traffic.py target``: a short workload to run
-  under ``rocprofv3 --pmc FETCH_SIZE`` (then ``--pmc WRITE_SIZE``).  It applies
-  the FP64 plan for log|x| at n = 2048 to two whole chunks of densities and then
+* ``python paper_2107_03958_amd/traffic.py target [--precision fp64|fp32]
+  [--n N] [--b B]``: a short workload to run under ``rocprofv3 --pmc
+  FETCH_SIZE`` (then ``--pmc WRITE_SIZE``).  It applies the plan for log|x|
+  (default FP64, n = 2048, b = 2) to two whole chunks of densities and then
   copies a 512 MiB device buffer, whose counters calibrate the byte scale.
 * ``python paper_2107_03958_amd/traffic.py summarise FETCH_DIR WRITE_DIR OUT``:
   reads the two ``*_counter_collection.csv`` files, scales each kernel's
@@ -25,8 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 512 * 1024 * 1024
 
 
-# The translation unit of the measured kernels: apply.hip and what it includes.
-KERNEL_SOURCES = ("csrc/apply.hip", "csrc/apply_cfg.hpp", "csrc/fft_core.hpp", "csrc/plan.hpp", "csrc/tuned.hpp",
+# The translation units of the measured kernels and what they include.
+KERNEL_SOURCES = ("csrc/apply_f64.hip", "csrc/apply_f32.hip", "csrc/apply_impl.hpp", "csrc/apply_cfg.hpp", "csrc/fft_core.hpp", "csrc/plan.hpp", "csrc/tuned.hpp",
                   "../include/wsconv.h")
 
 
@@ -40,7 +41,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def target() -> None:
+def target(precision: str = "fp64", n: int = 2048, b: int = 2) -> None:
     import numpy as np
     import torch
 
@@ -49,9 +50,9 @@ def target() -> None:
     else:
         sys.path.insert(0, os.path.dirname(HERE))
         from paper_2107_03958_amd import api
-    n = 2048
-    plan = api.ConvPlan("log", n=n)
-    u = torch.as_tensor(np.random.default_rng(0).normal(size=(2 * plan.chunk, n, n))).cuda()   # two whole chunks
+    plan = api.ConvPlan("log", n=n, b=b, precision=precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    u = torch.as_tensor(np.random.default_rng(0).normal(size=(2 * plan.chunk, n, n))).to(dt).cuda()  # two whole chunks
     out = torch.empty_like(u)
     work = torch.empty(plan.chunk * plan.work_bytes, dtype=torch.uint8, device="cuda")
     plan.apply(u, out=out, work=work)
@@ -60,7 +61,12 @@ def target() -> None:
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"target": "done", "chunk": plan.chunk}), flush=True)
+    print(json.dumps({"target": "done", "chunk": plan.chunk, "precision": precision, "n": n, "b": b}), flush=True)
+
+
+def summary_name(precision: str, n: int, b: int) -> str:
+    """Base name (under profiles/) of the traffic summary of one workload."""
+    return f"apply_{precision}_{n}{'_period3' if b == 3 else ''}_traffic"
 
 
 def _read(d: str, counter: str) -> dict:
@@ -77,12 +83,15 @@ def _read(d: str, counter: str) -> dict:
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def _chunk(d: str) -> int:
-    """Densities per apply dispatch, as printed by the target run (log next to the counter directory)."""
+def _workload(d: str) -> dict:
+    """The target run's line (log next to the counter directory): densities per apply dispatch and
+    the plan's precision, n and b."""
     with open(d.rstrip("/") + ".log") as fh:
         for line in fh:
             if line.startswith("{") and '"target"' in line:
-                return int(json.loads(line)["chunk"])
+                w = json.loads(line)
+                return dict(chunk=int(w["chunk"]), precision=w.get("precision", "fp64"), n=int(w.get("n", 2048)),
+                            b=int(w.get("b", 2)))
     raise RuntimeError(f"no target line in {d}.log")
 
 
@@ -103,22 +112,26 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
                           read_bytes=fetch[k] * 1024.0 * f_scale,
                           write_bytes=write.get(k, 0.0) * 1024.0 * w_scale)
         kernels[k]["traffic_bytes"] = kernels[k]["read_bytes"] + kernels[k]["write_bytes"]
-    chunk = _chunk(fetch_dir)
+    wl = _workload(fetch_dir)
+    chunk = wl["chunk"]
+    prec, n, b = wl["precision"], wl["n"], wl["b"]
     res = dict(source_hash=source_hash(), densities_per_dispatch=chunk, calibration_kernel=ck, fetch_scale=f_scale,
-               write_scale=w_scale, copy_bytes=COPY_BYTES,
-               workload=f"FP64 log|x| plan, n=2048, two chunks of {chunk} densities (per-dispatch averages)",
+               write_scale=w_scale, copy_bytes=COPY_BYTES, precision=prec, n=n, b=b,
+               workload=f"{prec.upper()} log|x| plan, n={n}, b={b}, two chunks of {chunk} densities "
+                        f"(per-dispatch averages)",
                kernels=kernels)
+    opts = f" --precision {prec} --n {n} --b {b}"
     with open(out + ".json", "w") as fh:
         json.dump(res, fh, indent=1)
-    lines = ["# HBM traffic per dispatch, FP64 apply at n=2048 (rocprofv3 PMC)", "",
+    lines = [f"# HBM traffic per dispatch, {prec.upper()} apply at n={n}, period b={b} (rocprofv3 PMC)", "",
              "Commands ($R: the repository root; $OUT: an output folder):", "", "```",
              "cd /tmp && export TMPDIR=/tmp",
              "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o p --output-format csv -- "
-             "python3 $R/paper_2107_03958_amd/traffic.py target > $OUT/pmc_fetch.log",
+             f"python3 $R/paper_2107_03958_amd/traffic.py target{opts} > $OUT/pmc_fetch.log",
              "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o p --output-format csv -- "
-             "python3 $R/paper_2107_03958_amd/traffic.py target > $OUT/pmc_write.log",
+             f"python3 $R/paper_2107_03958_amd/traffic.py target{opts} > $OUT/pmc_write.log",
              "cd $R && python3 paper_2107_03958_amd/traffic.py summarise $OUT/pmc_fetch $OUT/pmc_write "
-             "profiles/apply_fp64_2048_traffic", "```", "",
+             f"profiles/{summary_name(prec, n, b)}", "```", "",
              f"Each apply dispatch covers {res['densities_per_dispatch']} densities.", "",
              f"Calibration: `{ck}` copying {COPY_BYTES >> 20} MiB read FETCH_SIZE {fetch[ck]:.0f} KiB "
              f"(scale {f_scale:.3f}) and WRITE_SIZE {write[ck]:.0f} KiB (scale {w_scale:.3f}).", "",
@@ -144,7 +157,13 @@ def load_for_current_sources(path: str):
 
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "target":
-        target()
+        import argparse
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+        ap.add_argument("--n", type=int, default=2048)
+        ap.add_argument("--b", type=int, default=2)
+        a = ap.parse_args(sys.argv[2:])
+        target(a.precision, a.n, a.b)
     elif len(sys.argv) == 5 and sys.argv[1] == "summarise":
         print(json.dumps(summarise(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     else:
