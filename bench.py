@@ -293,6 +293,57 @@ def run_ls_bench(api, torch, ns, kappas, repeats):
     return out
 
 
+def run_ls_batch_bench(api, torch, ns, kappa, count, repeats):
+    """The same `count` LS solves (one plan, seeded contrasts 0.2..0.8 cut and plane-wave angles) one at a
+    time (ls_solve) and as one batch (ls_solve_batch): solves/s and per-solve latency of each form."""
+    import synth
+    out = []
+    for n in ns:
+        rng = np.random.default_rng(synth.SEED_LS_ANGLE + 500 + n)
+        ms = torch.as_tensor(np.stack([rng.uniform(0.2, 0.8) * synth.cutoff(n) for _ in range(count)])).cuda()
+        uis = torch.as_tensor(np.stack([synth.plane_wave(n, kappa, rng.uniform(0, 2 * np.pi))
+                                        for _ in range(count)])).cuda()
+        for mode in ("fp64", "fp32+ir"):
+            mixed = mode != "fp64"
+            plan = api.ConvPlan("helmholtz", n=n, kappa=kappa, precision="fp32" if mixed else "fp64")
+            w1 = plan.ls_workspace(50, mixed)
+            wb = plan.ls_batch_workspace(count, 50, mixed)
+            o1 = torch.empty_like(uis[0])
+            ob = torch.empty_like(uis)
+            plan.ls_solve_batch(ms, uis, tol=1e-8, restart=50, mixed=mixed, out=ob, work=wb)      # warm-up
+            for s in range(count):
+                plan.ls_solve(ms[s], uis[s], tol=1e-8, restart=50, mixed=mixed, out=o1, work=w1)
+            alone_lat, batch_lat = [], []
+            mv = 0
+            for _ in range(repeats):
+                for s in range(count):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, info = plan.ls_solve(ms[s], uis[s], tol=1e-8, restart=50, mixed=mixed, out=o1, work=w1)
+                    torch.cuda.synchronize()
+                    alone_lat.append(time.perf_counter() - t0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, infos = plan.ls_solve_batch(ms, uis, tol=1e-8, restart=50, mixed=mixed, out=ob, work=wb)
+                torch.cuda.synchronize()
+                batch_lat.append(time.perf_counter() - t0)
+                mv = max(i.matvecs for i in infos)
+            a = np.array(alone_lat) * 1e3
+            b = np.array(batch_lat) * 1e3
+            case = dict(n=n, kappa=kappa, mode=mode, count=count,
+                        alone_solves_per_s=len(a) / (a.sum() / 1e3), batched_solves_per_s=count * len(b) / (b.sum() / 1e3),
+                        alone_p50_ms=float(np.percentile(a, 50)), alone_p99_ms=float(np.percentile(a, 99)),
+                        batched_p50_ms=float(np.percentile(b, 50)), batched_p99_ms=float(np.percentile(b, 99)),
+                        batched_max_matvecs=mv, max_rel_residual=max(i.rel_residual for i in infos),
+                        all_converged=all(i.status == 0 for i in infos))
+            out.append(case)
+            log(f"ls batch n={n} kappa={kappa} {mode} x{count}: alone {case['alone_solves_per_s']:.0f} solves/s "
+                f"(p99 {case['alone_p99_ms']:.2f} ms), batched {case['batched_solves_per_s']:.0f} solves/s "
+                f"(p99 {case['batched_p99_ms']:.2f} ms per batch)")
+    return dict(workload=f"{count} LS solves per plan (contrast a*cut, a ~ U[0.2, 0.8]; plane waves at seeded "
+                         f"angles), GMRES(50), tol 1e-8, one at a time vs one ls_solve_batch", cases=out)
+
+
 # Serving trace: grid sides, apply kernels and LS wavenumbers of the request stream.
 SERVE_NS = [64, 128, 256, 512, 1024]
 SERVE_APPLY_KERNELS = [("log|x|", dict(family="log")), ("|x|^-1/2", dict(family="power", gamma=-0.5)),
@@ -603,6 +654,7 @@ def main(argv=None):
     ap.add_argument("--ls-n", type=int, nargs="*", default=[256, 512, 1024])
     ap.add_argument("--ls-kappa", type=float, nargs="*", default=[20.0, 40.0, 80.0])
     ap.add_argument("--ls-repeats", type=int, default=3)
+    ap.add_argument("--ls-batch", type=int, default=8, help="solves per batch of the batched-LS leg (0: skip)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-period3", action="store_true")
     ap.add_argument("--no-eval", action="store_true")
@@ -693,6 +745,9 @@ def main(argv=None):
     if not args.no_ls:
         log("LS latency bench ...")
         ls = run_ls_bench(api, torch, args.ls_n, args.ls_kappa, args.ls_repeats)
+        if args.ls_batch > 1:
+            log("batched LS bench ...")
+            ls["batched"] = run_ls_batch_bench(api, torch, [256, 512], 40.0, args.ls_batch, args.ls_repeats)
     srv = None
     if not args.no_serve:
         log("serving bench ...")

@@ -233,6 +233,27 @@ int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol
              int restart, int max_matvecs, int mixed_precision, void* u_out, void* work,
              ws_ls_info* info, void* stream);
 
+/* Device scratch needed by ls_solve_batch for `count` solves (1 <= count <= 64). */
+int ls_solve_batch_query(ws_plan_t plan, int count, int restart, int mixed_precision, size_t* work_bytes);
+
+/* `count` solves of eq. descretls (Section 3.3) with one plan, run together:
+ * u_s + kappa^2 (A_n(m_s u_s))_j = u_inc_s,j for s < count, each with its own
+ * contrast and incident field.
+ *  contrast: device [count][n][n] float64; u_inc, u_out: device [count][n][n]
+ *            complex128 (16-byte aligned); work: ls_solve_batch_query bytes,
+ *            256-byte aligned; info: host array of `count` entries.
+ * The solves run as `count` GMRES instances in lockstep: every Arnoldi step is
+ * one set of launches for all of them (the operator over `count` densities,
+ * the Gram-Schmidt and Givens kernels over `count` instances), and each
+ * instance keeps its own Hessenberg matrix, rotations, stop test and
+ * max_matvecs budget, so solve s returns what ls_solve returns for it alone.
+ * Arguments otherwise as for ls_solve.  Returns WS_OK when every solve
+ * converged, else the largest status among them (1: some solve stopped at
+ * max_matvecs, 2: some solve broke down on a non-finite value; info[s] says
+ * which), or a negative WS_E* code. */
+int ls_solve_batch(ws_plan_t plan, int count, const void* contrast, const void* u_inc, double tol, int restart,
+                   int max_matvecs, int mixed_precision, void* u_out, void* work, ws_ls_info* info, void* stream);
+
 /* Device scratch needed by ls_solve_fs (the smoothed contrast and its
  * pre-pass intermediate, then ls_solve's scratch).  WS_EUNSUPPORTED for
  * plans of period b != 2; fs is checked as in conv_apply and must name a

@@ -80,6 +80,9 @@ EXPORTS = {
     "ls_solve_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
     "ls_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int, c_int, c_void_p, c_void_p,
                          POINTER(WsLsInfo), c_void_p]),
+    "ls_solve_batch_query": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_size_t)]),
+    "ls_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_double, c_int, c_int, c_int, c_void_p,
+                               c_void_p, POINTER(WsLsInfo), c_void_p]),
     "conv_eval_query": (c_int, [c_void_p, POINTER(c_size_t)]),
     "conv_eval": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ls_solve_fs_query": (c_int, [c_void_p, POINTER(WsFsDesc), c_int, c_int, POINTER(c_size_t)]),

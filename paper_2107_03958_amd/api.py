@@ -215,6 +215,31 @@ class ConvPlan:
                                              ctypes.byref(info), _stream_ptr(stream)))
         return u, LsInfo(info.status, info.iterations, info.matvecs, info.refinements, info.rel_residual)
 
+    def ls_batch_workspace(self, count: int, restart: int = 50, mixed: bool = False) -> torch.Tensor:
+        nb = ctypes.c_size_t()
+        L.check(self.lib.ls_solve_batch_query(self.handle, count, restart, int(mixed), ctypes.byref(nb)))
+        return torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+
+    def ls_solve_batch(self, contrast: torch.Tensor, u_inc: torch.Tensor, tol: float = 1e-8, restart: int = 50,
+                       max_matvecs: int = 5000, mixed: bool = False, out: torch.Tensor | None = None,
+                       work: torch.Tensor | None = None, stream=None):
+        """Several solves with this plan at once (ls_solve_batch): contrast [count, n, n] float64,
+        u_inc [count, n, n] complex128; returns (u [count, n, n], [LsInfo] * count)."""
+        if contrast.dtype != torch.float64 or u_inc.dtype != torch.complex128:
+            raise ValueError("contrast must be float64 and u_inc complex128")
+        count = u_inc.shape[0]
+        for t in (contrast, u_inc):
+            if t.device != self.device or not t.is_contiguous() or t.shape != (count, self.n, self.n):
+                raise ValueError(f"inputs must be contiguous ({count}, {self.n}, {self.n}) tensors on {self.device}")
+        u = out if out is not None else torch.empty_like(u_inc)
+        w = work if work is not None else self.ls_batch_workspace(count, restart, mixed)
+        infos = (L.WsLsInfo * count)()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.ls_solve_batch(self.handle, count, _dev_ptr(contrast), _dev_ptr(u_inc), tol, restart,
+                                            max_matvecs, int(mixed), _dev_ptr(u), _dev_ptr(w), infos,
+                                            _stream_ptr(stream)))
+        return u, [LsInfo(i.status, i.iterations, i.matvecs, i.refinements, i.rel_residual) for i in infos]
+
     def moments(self, k1, k2):
         """Moments ghat(k) at integer frequencies (conv_plan_moments); complex numpy array."""
         import numpy as np

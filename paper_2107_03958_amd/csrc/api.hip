@@ -425,10 +425,42 @@ int ls_solve(ws_plan_t plan, const void* contrast, const void* u_inc, double tol
   if (mixed_precision && plan->precision != WS_FP32)
     return fail(WS_EINVAL, "mixed precision needs a WS_FP32 plan");
   std::string err;
-  const int rc = ws::ls_run(*plan, static_cast<const double*>(contrast),
+  const int rc = ws::ls_run(*plan, 1, static_cast<const double*>(contrast),
                             static_cast<const ws::cx<double>*>(u_inc), tol, restart, max_matvecs,
                             mixed_precision != 0, static_cast<ws::cx<double>*>(u_out), work, info,
                             static_cast<hipStream_t>(stream), &err);
+  if (rc < 0) return fail(rc, err);
+  return rc;
+}
+
+int ls_solve_batch_query(ws_plan_t plan, int count, int restart, int mixed_precision, size_t* work_bytes) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (!plan->cplx) return fail(WS_EUNSUPPORTED, "ls_solve_batch needs a Helmholtz plan");
+  if (count < 1 || count > ws::kMaxLsBatch) return fail(WS_EINVAL, "count must lie in [1, 64]");
+  if (restart < 1 || restart > 200) return fail(WS_EINVAL, "restart must lie in [1, 200]");
+  if (mixed_precision && plan->precision != WS_FP32)
+    return fail(WS_EINVAL, "mixed precision needs a WS_FP32 plan");
+  if (work_bytes) *work_bytes = ws::ls_work_bytes(*plan, restart, mixed_precision != 0, count);
+  return WS_OK;
+}
+
+int ls_solve_batch(ws_plan_t plan, int count, const void* contrast, const void* u_inc, double tol, int restart,
+                   int max_matvecs, int mixed_precision, void* u_out, void* work, ws_ls_info* info, void* stream) {
+  g_err.clear();
+  if (info && count > 0 && count <= ws::kMaxLsBatch) std::memset(info, 0, sizeof(*info) * count);
+  int rc = ls_solve_batch_query(plan, count, restart, mixed_precision, nullptr);
+  if (rc) return rc;
+  if (!contrast || !u_inc || !u_out || !work || !info) return fail(WS_EINVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(contrast) | reinterpret_cast<uintptr_t>(u_inc) |
+       reinterpret_cast<uintptr_t>(u_out)) % 16 || reinterpret_cast<uintptr_t>(work) % 256)
+    return fail(WS_EINVAL, "arrays must be 16-byte and work 256-byte aligned");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WS_EINVAL, "tol must be positive");
+  if (max_matvecs < 1) return fail(WS_EINVAL, "max_matvecs must be >= 1");
+  std::string err;
+  rc = ws::ls_run(*plan, count, static_cast<const double*>(contrast), static_cast<const ws::cx<double>*>(u_inc), tol,
+                  restart, max_matvecs, mixed_precision != 0, static_cast<ws::cx<double>*>(u_out), work, info,
+                  static_cast<hipStream_t>(stream), &err);
   if (rc < 0) return fail(rc, err);
   return rc;
 }
@@ -479,7 +511,7 @@ int ls_solve_fs(ws_plan_t plan, const void* contrast_tilde, const ws_fs_desc* fs
   const hipError_t e = ws::launch_fs_real<double>(p, static_cast<const double*>(contrast_tilde), ms, fsw, *fs, s);
   if (e != hipSuccess) return hip_fail(e, "ls_solve_fs: smoothing pre-pass");
   std::string err;
-  rc = ws::ls_run(p, ms, static_cast<const ws::cx<double>*>(u_inc), tol, restart, max_matvecs,
+  rc = ws::ls_run(p, 1, ms, static_cast<const ws::cx<double>*>(u_inc), tol, restart, max_matvecs,
                   mixed_precision != 0, static_cast<ws::cx<double>*>(u_out), w + fs_contrast_bytes(p), info, s,
                   &err);
   if (rc < 0) return fail(rc, err);

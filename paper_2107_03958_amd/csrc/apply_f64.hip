@@ -52,7 +52,7 @@ template hipError_t launch_apply_real<double>(const Plan&, int, const double*, d
 template hipError_t launch_fs_real<double>(const Plan&, const double*, double*, cx<double>*, const ws_fs_desc&,
                                            hipStream_t);
 template hipError_t launch_apply_cplx<double>(const Plan&, int, const cx<double>*, const double*, double, bool,
-                                              cx<double>*, cx<double>*, hipStream_t, const int*, int);
+                                              cx<double>*, cx<double>*, hipStream_t, const int*, int, size_t);
 template hipError_t launch_apply_multi<double>(const ApplyItem*, int, bool, hipStream_t);
 
 }  // namespace ws

@@ -102,6 +102,7 @@ struct Seg {
   T alpha;                           // complex pass 2: out = [v] + alpha * result
   int add;
   FsArgs fs;
+  size_t mstride;                    // complex pass 0: elements between the densities' contrasts (0: shared)
 };
 
 template <typename T>
@@ -768,7 +769,7 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
       const int j = p + P * slot_elem<E, R0>(reg);
       x[reg] = (!GUARD || valid) ? vin[roff + j] : cx<T>{0, 0};
       if constexpr (MUL) {
-        if (!GUARD || valid) x[reg] = cscale(x[reg], sg.mcon[(size_t)row * n + j]);
+        if (!GUARD || valid) x[reg] = cscale(x[reg], sg.mcon[(size_t)(t / TPD) * sg.mstride + (size_t)row * n + j]);
       }
     }
     if constexpr (TW::kPowers) {
@@ -913,8 +914,10 @@ __device__ __forceinline__ void run_group(const Seg<T>& sg, int blk, cx<T>* lds)
 template <typename T, int K, int LOGN, int B>
 __device__ __forceinline__ void pass1_body(const void* src, void* dst, cx<T>* work, const void* gtab,
                                            const T* gnyq, const T* mcon, typename TwOf<T>::type tw, int ntiles,
-                                           int nblocks, T alpha, int add, const FsArgs& fs, cx<T>* lds) {
+                                           int nblocks, T alpha, int add, const FsArgs& fs, cx<T>* lds,
+                                           size_t mstride) {
   Seg<T> sg;
+  sg.mstride = mstride;
   sg.logn = LOGN;
   sg.block0 = 0;
   sg.nblocks = nblocks;
@@ -936,20 +939,20 @@ template <typename T, int K, int LOGN, int B = 2>
 __global__ __launch_bounds__((Single<T, K, LOGN, B>::BLOCK), (Single<T, K, LOGN, B>::WAVES)) void k_pass1(
     const void* __restrict__ src, void* __restrict__ dst, cx<T>* __restrict__ work, const void* __restrict__ gtab,
     const T* __restrict__ gnyq, const T* __restrict__ mcon, typename TwOf<T>::type tw, int ntiles, int nblocks,
-    T alpha, int add, FsArgs fs, const int* skip) {
+    T alpha, int add, FsArgs fs, const int* skip, size_t mstride) {
   if (skip && *skip) return;
   __shared__ cx<T> lds[Single<T, K, LOGN, B>::LDS];
-  pass1_body<T, K, LOGN, B>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+  pass1_body<T, K, LOGN, B>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds, mstride);
 }
 
 template <typename T, int K, int LOGN>
 __global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::WAVES)) void k_pass1_alias(
     const void* src, void* dst, cx<T>* __restrict__ work, const void* __restrict__ gtab,
     const T* __restrict__ gnyq, const T* __restrict__ mcon, typename TwOf<T>::type tw, int ntiles, int nblocks,
-    T alpha, int add, FsArgs fs, const int* skip) {
+    T alpha, int add, FsArgs fs, const int* skip, size_t mstride) {
   if (skip && *skip) return;
   __shared__ cx<T> lds[Single<T, K, LOGN>::LDS];
-  pass1_body<T, K, LOGN, 2>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds);
+  pass1_body<T, K, LOGN, 2>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds, mstride);
 }
 
 // Launches over several segments of any sizes: one block size for all.
@@ -1068,9 +1071,10 @@ hipError_t launch_segs(Segs<T>& tab, hipStream_t st) {
 template <typename T, int K>
 hipError_t launch_one(const Plan& p, int batch, const void* src, void* dst, cx<T>* work, hipStream_t st,
                       const int* skip = nullptr, const T* mcon = nullptr, T alpha = (T)1, bool add = false,
-                      const FsArgs* fs = nullptr) {
+                      const FsArgs* fs = nullptr, size_t mstride = 0) {
   Seg<T> sg = make_seg<T, K>(p, batch, src, dst, work, false);
   sg.mcon = mcon;
+  sg.mstride = mstride;
   sg.alpha = alpha;
   sg.add = add ? 1 : 0;
   if (fs) sg.fs = *fs;
@@ -1082,7 +1086,7 @@ hipError_t launch_one(const Plan& p, int batch, const void* src, void* dst, cx<T
   case L:                                                                                   \
     k_pass1<T, K, L, 3><<<sg.nblocks, Single<T, K, L, 3>::BLOCK, 0, st>>>(                   \
         sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,    \
-        sg.alpha, sg.add, sg.fs, skip);                                                      \
+        sg.alpha, sg.add, sg.fs, skip, sg.mstride);                                         \
     return hipGetLastError();
         WS_FOR_EACH_LOGN_B3(WS_CASE)
 #undef WS_CASE
@@ -1099,11 +1103,11 @@ hipError_t launch_one(const Plan& p, int batch, const void* src, void* dst, cx<T
     if constexpr (K == kRowsInvFs)                                                          \
       k_pass1_alias<T, K, L><<<sg.nblocks, Single<T, K, L>::BLOCK, 0, st>>>(                 \
           sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,  \
-          sg.alpha, sg.add, sg.fs, skip);                                                    \
+          sg.alpha, sg.add, sg.fs, skip, sg.mstride);                                       \
     else                                                                                    \
       k_pass1<T, K, L><<<sg.nblocks, Single<T, K, L>::BLOCK, 0, st>>>(                       \
           sg.src, sg.dst, sg.work, sg.gtab, sg.gnyq, sg.mcon, sg.tw, sg.ntiles, sg.nblocks,  \
-          sg.alpha, sg.add, sg.fs, skip);                                                    \
+          sg.alpha, sg.add, sg.fs, skip, sg.mstride);                                       \
     break;
     WS_FOR_EACH_LOGN(WS_CASE)
 #undef WS_CASE
@@ -1146,10 +1150,10 @@ hipError_t launch_fs_real(const Plan& p, const T* ut, T* out, cx<T>* work, const
 
 template <typename T>
 static hipError_t pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                            cx<T>* out, cx<T>* work, hipStream_t s, const int* skip) {
+                            cx<T>* out, cx<T>* work, hipStream_t s, const int* skip, size_t mstride = 0) {
   if (p.logn < kMinLogn || p.logn > kMaxLogn) return hipErrorInvalidValue;
   if (pass == 0) {
-    if (m) return launch_one<T, kRowsFwdCplxMul>(p, batch, v, nullptr, work, s, skip, m);
+    if (m) return launch_one<T, kRowsFwdCplxMul>(p, batch, v, nullptr, work, s, skip, m, (T)1, false, nullptr, mstride);
     return launch_one<T, kRowsFwdCplx>(p, batch, v, nullptr, work, s, skip);
   }
   if (pass == 1) return launch_one<T, kColsCplx>(p, batch, nullptr, nullptr, work, s, skip);
@@ -1158,13 +1162,14 @@ static hipError_t pass_cplx(const Plan& p, int pass, int batch, const cx<T>* v, 
 
 template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add,
-                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip, int chunk) {
+                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip, int chunk, size_t mstride) {
   const size_t nn = (size_t)p.n * p.n;
   if (chunk <= 0) chunk = apply_chunk(p);
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nb = batch - b0 < chunk ? batch - b0 : chunk;
+    const T* mb = m ? m + b0 * mstride : nullptr;
     for (int pass = 0; pass < 3; ++pass) {
-      hipError_t e = pass_cplx<T>(p, pass, nb, v + b0 * nn, m, alpha, add, out + b0 * nn, work, s, skip);
+      hipError_t e = pass_cplx<T>(p, pass, nb, v + b0 * nn, mb, alpha, add, out + b0 * nn, work, s, skip, mstride);
       if (e != hipSuccess) return e;
     }
   }

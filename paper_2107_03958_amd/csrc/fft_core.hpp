@@ -95,10 +95,31 @@ __device__ __forceinline__ void tw_run(const TwD& tw, int b, int d, cx<double> (
   run_from<K>(tw.template get<SGN>(b), K > 1 ? tw.template get<SGN>(d) : cx<double>{1, 0}, w);
 }
 
-// FP32 data times an FP64 twiddle: the product in FP64, rounded once.
+// 1 (default): FP32 passes use TwDF, each product x w taken in FP64 and
+// rounded once; 2: the FP64 twiddle is split in registers into the FP32 pair
+// (hi, lo) = (fl(w), fl(w - hi)) and applied as x lo + x hi with FP32 FMAs;
+// 0: the (hi, lo) pair table, TwF.
+#ifndef WS_TW32_POWERS
+#define WS_TW32_POWERS 1
+#endif
+
+// FP32 data times an FP64 twiddle (see WS_TW32_POWERS).
 __device__ __forceinline__ cx<float> cmul(cx<float> a, cx<double> b) {
+#if WS_TW32_POWERS == 2
+  const float hx = (float)b.x, hy = (float)b.y;
+  const float lx = (float)(b.x - (double)hx), ly = (float)(b.y - (double)hy);
+  float rx = a.x * lx, ry = a.x * ly;
+  rx = __builtin_fmaf(-a.y, ly, rx);
+  ry = __builtin_fmaf(a.y, lx, ry);
+  rx = __builtin_fmaf(-a.y, hy, rx);
+  ry = __builtin_fmaf(a.y, hx, ry);
+  rx = __builtin_fmaf(a.x, hx, rx);
+  ry = __builtin_fmaf(a.x, hy, ry);
+  return {rx, ry};
+#else
   const double ax = a.x, ay = a.y;
   return {(float)(ax * b.x - ay * b.y), (float)(ax * b.y + ay * b.x)};
+#endif
 }
 
 // FP32 data with the FP64 table: bases loaded and powers formed in FP64 as
@@ -120,10 +141,6 @@ struct TwDF {
   }
 };
 
-// 1 (default): FP32 passes use TwDF; 0: the (hi, lo) pair table, TwF.
-#ifndef WS_TW32_POWERS
-#define WS_TW32_POWERS 1
-#endif
 template <typename T> struct TwOf;
 template <> struct TwOf<double> { using type = TwD; };
 template <> struct TwOf<float> { using type = std::conditional_t<WS_TW32_POWERS != 0, TwDF, TwF>; };

@@ -14,11 +14,19 @@
 // the cycle's state and once to read the true residual ||rhs - K x|| that
 // decides convergence.
 //
+// Several solves with the same plan run as one batch of `count` GMRES
+// instances in lockstep: every kernel of a step covers all instances
+// (grid dimension z, or one launch of the operator over `count` densities,
+// each with its own contrast), and every instance keeps its own Hessenberg
+// matrix, rotations, stop flag and step budget, so each one computes exactly
+// what it computes alone.  A single solve is a batch of one.
+//
 // Mixed precision: iterative refinement with the FP64 residual r = u_inc - K x
 // (FP64 operator) and corrections from GMRES on the FP32 operator applied to
 // r/||r|| (FP32 basis vectors, FP64 orthogonalisation coefficients).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -36,15 +44,24 @@ constexpr int kThreads = 256;
 constexpr int kBlocks = 512;     // reduction partials per pass
 
 struct GState {
-  int done;        // 1: stop this cycle (converged estimate, or breakdown)
+  int done;        // 1: stop this cycle (converged estimate, breakdown, step budget, or not running)
   int kused;       // Arnoldi steps completed in this cycle
   int bad;         // non-finite value met
-  int pad;
+  int maxk;        // Arnoldi steps this cycle may take
   double est;      // Givens residual estimate |g_{k}|
   double beta;     // norm of the cycle's start residual
   double tol_abs;  // stop when est <= tol_abs
   double norm;     // scratch: last computed norm
 };
+
+// Per-cycle parameters of a batch's instances, passed by value.
+struct CycleCtl {
+  unsigned long long active;          // bit s: instance s runs this cycle
+  double tol_abs[kMaxLsBatch];
+  int maxk[kMaxLsBatch];
+};
+
+__device__ __forceinline__ bool in_mask(unsigned long long m, int s) { return (m >> s) & 1ull; }
 
 template <typename T>
 __device__ __forceinline__ cx<double> up(cx<T> a) { return {(double)a.x, (double)a.y}; }
@@ -67,20 +84,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Arnoldi step kernels.  Reductions finish in the next kernel of the step
 // (stream order makes the partials visible), each block repeating the small
 // final sum in a fixed order, so the results do not depend on timing.
+// Instance s = blockIdx.z of a batch of `count`: basis vector i at
+// V + (i count + s) N; its small arrays at the strides of the Krylov layout.
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// partial[i][b] = sum over block b's elements of conj(V_i) w, i < nv (grid nbd x nv).
+// partial[s][i][b] = sum over block b's elements of conj(V_i) w, i <= j (grid nbd x (j + 1) x count).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_dots(const cx<T>* V, size_t N, const cx<T>* w, cx<double>* partial,
-                                                   const GState* st) {
-  if (st->done) return;
+__global__ __launch_bounds__(kThreads) void k_dots(const cx<T>* V, size_t N, int count, int j, cx<double>* partial,
+                                                   size_t pstride, const GState* st) {
+  const int s = blockIdx.z;
+  if (st[s].done) return;
   __shared__ double sh[kThreads];
   const int i = blockIdx.y;
-  const cx<T>* vi = V + (size_t)i * N;
+  const cx<T>* vi = V + ((size_t)i * count + s) * N;
+  const cx<T>* w = V + ((size_t)(j + 1) * count + s) * N;
   double re = 0.0, im = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
     const cx<double> a = up(vi[e]), b = up(w[e]);
@@ -89,25 +110,31 @@ __global__ __launch_bounds__(kThreads) void k_dots(const cx<T>* V, size_t N, con
   }
   re = block_sum(re, sh);
   im = block_sum(im, sh);
-  if (threadIdx.x == 0) partial[(size_t)i * gridDim.x + blockIdx.x] = {re, im};
+  if (threadIdx.x == 0) partial[s * pstride + (size_t)i * gridDim.x + blockIdx.x] = {re, im};
 }
 
-// h_i = sum_b partial[i][b] (every block, one wave per coefficient; block 0
-// adds h into Hessenberg column Hcol), then w -= sum_{i<nv} V_i h_i and, on
-// the second Gram-Schmidt pass, per-block partial sums of |w|^2.
+// h_i = sum_b partial[s][i][b] (every block, one wave per coefficient; block 0
+// adds h into Hessenberg column j), then w -= sum_{i<=j} V_i h_i and, on the
+// second Gram-Schmidt pass, per-block partial sums of |w|^2.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, int nv, cx<T>* w,
-                                                     const cx<double>* partial, int nbd, cx<double>* Hcol,
-                                                     double* npart, const GState* st) {
-  if (st->done) return;
+__global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, int count, int j, cx<T>* Vw,
+                                                     const cx<double>* partial, size_t pstride, int nbd,
+                                                     cx<double>* H, size_t hstride, int ldh, double* npart,
+                                                     const GState* st) {
+  const int s = blockIdx.z;
+  if (st[s].done) return;
   __shared__ cx<double> hs[256];
   __shared__ double sh[kThreads];
+  const int nv = j + 1;
+  const cx<double>* ps = partial + s * pstride;
+  cx<double>* Hcol = H + s * hstride + (size_t)j * ldh;
+  cx<T>* w = Vw + ((size_t)(j + 1) * count + s) * N;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
   for (int i = wave; i < nv; i += nw) {
     double sr = 0.0, si = 0.0;
     for (int b = lane; b < nbd; b += 64) {
-      sr += partial[(size_t)i * nbd + b].x;
-      si += partial[(size_t)i * nbd + b].y;
+      sr += ps[(size_t)i * nbd + b].x;
+      si += ps[(size_t)i * nbd + b].y;
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
@@ -121,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, i
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
     cx<double> x = up(w[e]);
     for (int i = 0; i < nv; ++i) {
-      const cx<double> v = up(V[(size_t)i * N + e]);
+      const cx<double> v = up(V[((size_t)i * count + s) * N + e]);
       x.x -= v.x * hs[i].x - v.y * hs[i].y;
       x.y -= v.x * hs[i].y + v.y * hs[i].x;
     }
@@ -132,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const cx<T>* V, size_t N, i
   }
   if (npart) {
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) npart[blockIdx.x] = acc;
+    if (threadIdx.x == 0) npart[(size_t)s * kBlocks + blockIdx.x] = acc;
   }
 }
 
@@ -174,7 +201,7 @@ __device__ void givens_step(cx<double>* H, int ldh, cx<double>* cs, cx<double>* 
   if (!isfinite(est) || !isfinite(nrm)) {
     st->bad = 1;
     st->done = 1;
-  } else if (est <= st->tol_abs || nrm <= 1e-300) {
+  } else if (est <= st->tol_abs || nrm <= 1e-300 || j + 1 >= st->maxk) {
     st->done = 1;
   }
 }
@@ -183,120 +210,161 @@ __device__ void givens_step(cx<double>* H, int ldh, cx<double>* cs, cx<double>* 
 // Hessenberg column j and applies the stop test; every block scales its part
 // of w to unit norm.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_normalise_givens(cx<T>* w, size_t N, const double* npart, int nbn,
-                                                               cx<double>* H, int ldh, cx<double>* cs,
-                                                               cx<double>* sn, cx<double>* g, int j, GState* st) {
-  if (st->done) return;
+__global__ __launch_bounds__(kThreads) void k_normalise_givens(cx<T>* V, size_t N, int count, int j,
+                                                               const double* npart, int nbn, cx<double>* H,
+                                                               size_t hstride, int ldh, cx<double>* cs,
+                                                               cx<double>* sn, int rs, cx<double>* g, GState* st) {
+  const int s = blockIdx.z;
+  if (st[s].done) return;
   __shared__ double sh[kThreads];
   double tot = 0.0;
-  for (int b = threadIdx.x; b < nbn; b += blockDim.x) tot += npart[b];
+  for (int b = threadIdx.x; b < nbn; b += blockDim.x) tot += npart[(size_t)s * kBlocks + b];
   tot = block_sum(tot, sh);
   const double nrm = sqrt(tot);
-  if (blockIdx.x == 0 && threadIdx.x == 0) givens_step(H, ldh, cs, sn, g, j, nrm, st);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    givens_step(H + s * hstride, ldh, cs + (size_t)s * rs, sn + (size_t)s * rs, g + (size_t)s * (rs + 1), j, nrm,
+                &st[s]);
   const double inv = 1.0 / nrm;
+  cx<T>* w = V + ((size_t)(j + 1) * count + s) * N;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
     const cx<double> x = up(w[e]);
     w[e] = down<T>({x.x * inv, x.y * inv});
   }
 }
 
-// y = R^-1 g over the kused x kused upper triangle.
-__global__ void k_trisolve(const cx<double>* H, int ldh, const cx<double>* g, cx<double>* y, const GState* st) {
+// flag = every instance of the batch has stopped (the operator's skip flag).
+__global__ void k_all_done(const GState* st, int count, int* flag) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int k = st->kused;
+  int all = 1;
+  for (int s = 0; s < count; ++s) all &= st[s].done ? 1 : 0;
+  *flag = all;
+}
+
+// y = R^-1 g over the kused x kused upper triangle (instance s = blockIdx.x, in mask).
+__global__ void k_trisolve(const cx<double>* H, size_t hstride, int ldh, const cx<double>* g, int gstride,
+                           cx<double>* y, const GState* st, unsigned long long mask) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0 || !in_mask(mask, s)) return;
+  const cx<double>* Hs = H + s * hstride;
+  const cx<double>* gs = g + (size_t)s * gstride;
+  cx<double>* ys = y + (size_t)s * gstride;
+  const int k = st[s].kused;
   for (int i = k - 1; i >= 0; --i) {
-    cx<double> acc = g[i];
+    cx<double> acc = gs[i];
     for (int l = i + 1; l < k; ++l) {
-      const cx<double> h = H[(size_t)l * ldh + i];
-      acc.x -= h.x * y[l].x - h.y * y[l].y;
-      acc.y -= h.x * y[l].y + h.y * y[l].x;
+      const cx<double> h = Hs[(size_t)l * ldh + i];
+      acc.x -= h.x * ys[l].x - h.y * ys[l].y;
+      acc.y -= h.x * ys[l].y + h.y * ys[l].x;
     }
-    const cx<double> d = H[(size_t)i * ldh + i];
+    const cx<double> d = Hs[(size_t)i * ldh + i];
     const double dd = d.x * d.x + d.y * d.y;
-    y[i] = {(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+    ys[i] = {(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
   }
 }
 
-// x += scale * sum_{i<kused} V_i y_i   (x of element type TX, V of element type T)
+// x_s += scale * sum_{i<kused} V_i y_i   (x of element type TX, V of element type T; instances in mask)
 template <typename T, typename TX>
-__global__ __launch_bounds__(kThreads) void k_xupdate(cx<TX>* x, const cx<T>* V, size_t N, const cx<double>* y,
-                                                      const GState* st, double scale) {
+__global__ __launch_bounds__(kThreads) void k_xupdate(cx<TX>* x, const cx<T>* V, size_t N, int count,
+                                                      const cx<double>* y, int gstride, const GState* st,
+                                                      double scale, unsigned long long mask) {
+  const int s = blockIdx.z;
+  if (!in_mask(mask, s)) return;
   __shared__ cx<double> ys[256];
-  const int k = st->kused;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
+  const int k = st[s].kused;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[(size_t)s * gstride + i];
   __syncthreads();
+  cx<TX>* xs = x + (size_t)s * N;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    cx<double> acc = up(x[e]);
+    cx<double> acc = up(xs[e]);
     for (int i = 0; i < k; ++i) {
-      const cx<double> v = up(V[(size_t)i * N + e]);
+      const cx<double> v = up(V[((size_t)i * count + s) * N + e]);
       acc.x += scale * (v.x * ys[i].x - v.y * ys[i].y);
       acc.y += scale * (v.x * ys[i].y + v.y * ys[i].x);
     }
-    x[e] = down<TX>(acc);
+    xs[e] = down<TX>(acc);
   }
 }
 
-// r = rhs - t, partial |r|^2
+// r_s = rhs_s - t_s, partial |r_s|^2 (instance s = blockIdx.z)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_residual(const cx<T>* rhs, const cx<T>* t, cx<T>* r, size_t N,
                                                        double* npart) {
+  const int s = blockIdx.z;
   __shared__ double sh[kThreads];
+  const size_t o = (size_t)s * N;
   double acc = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(rhs[e]), b = up(t[e]);
+    const cx<double> a = up(rhs[o + e]), b = up(t[o + e]);
     const cx<T> d = down<T>({a.x - b.x, a.y - b.y});
-    r[e] = d;
+    r[o + e] = d;
     const cx<double> dd = up(d);
     acc += dd.x * dd.x + dd.y * dd.y;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) npart[blockIdx.x] = acc;
+  if (threadIdx.x == 0) npart[(size_t)s * kBlocks + blockIdx.x] = acc;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_sumsq(const cx<T>* v, size_t N, double* npart) {
+  const int s = blockIdx.z;
   __shared__ double sh[kThreads];
   double acc = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(v[e]);
+    const cx<double> a = up(v[(size_t)s * N + e]);
     acc += a.x * a.x + a.y * a.y;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) npart[blockIdx.x] = acc;
+  if (threadIdx.x == 0) npart[(size_t)s * kBlocks + blockIdx.x] = acc;
 }
 
-// st->norm = sqrt(sum npart)
+// st[s].norm = sqrt(sum npart[s]) (instance s = blockIdx.x)
 __global__ void k_norm_finish(const double* npart, int nb, GState* st) {
+  const int s = blockIdx.x;
   __shared__ double sh[kThreads];
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += npart[b];
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += npart[(size_t)s * kBlocks + b];
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) st->norm = sqrt(acc);
+  if (threadIdx.x == 0) st[s].norm = sqrt(acc);
 }
 
-// Start of a cycle: V0 = r / ||r|| (norm in st->norm), clear H and g, g0 = ||r||.
+// Start of a cycle for the instances in ctl.active: V_s(0) = r_s / ||r_s||
+// (norm in st[s].norm), H_s and g_s cleared, g_s(0) = ||r_s||, stop state
+// reset; every other instance is marked stopped.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cycle_start(const cx<T>* r, cx<T>* v0, size_t N, cx<double>* H,
-                                                          int hsize, cx<double>* g, int gsize, GState* st,
-                                                          double tol_abs) {
-  const double nrm = st->norm;
+__global__ __launch_bounds__(kThreads) void k_cycle_start(const cx<T>* r, cx<T>* V, size_t N, int count,
+                                                          cx<double>* H, size_t hstride, cx<double>* g, int gstride,
+                                                          GState* st, CycleCtl ctl) {
+  const int s = blockIdx.z;
+  if (!in_mask(ctl.active, s)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st[s].done = 1;
+      st[s].kused = 0;
+    }
+    return;
+  }
+  const double nrm = st[s].norm;
   const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  const cx<T>* rs = r + (size_t)s * N;
+  cx<T>* v0 = V + (size_t)s * N;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(r[e]);
+    const cx<double> a = up(rs[e]);
     v0[e] = down<T>({a.x * inv, a.y * inv});
   }
   if (blockIdx.x == 0) {
-    for (int i = threadIdx.x; i < hsize; i += blockDim.x) H[i] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < gsize; i += blockDim.x) g[i] = {0.0, 0.0};
+    cx<double>* Hs = H + s * hstride;
+    cx<double>* gs = g + (size_t)s * gstride;
+    for (size_t i = threadIdx.x; i < hstride; i += blockDim.x) Hs[i] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < gstride; i += blockDim.x) gs[i] = {0.0, 0.0};
     __syncthreads();
     if (threadIdx.x == 0) {
-      g[0] = {nrm, 0.0};
-      st->done = 0;
-      st->kused = 0;
-      st->bad = 0;
-      st->est = nrm;
-      st->beta = nrm;
-      st->tol_abs = tol_abs;
+      gs[0] = {nrm, 0.0};
+      st[s].done = 0;
+      st[s].kused = 0;
+      st[s].bad = 0;
+      st[s].maxk = ctl.maxk[s];
+      st[s].est = nrm;
+      st[s].beta = nrm;
+      st[s].tol_abs = ctl.tol_abs[s];
     }
   }
 }
@@ -308,14 +376,15 @@ __global__ __launch_bounds__(kThreads) void k_zero(cx<T>* x, size_t N) {
     x[e] = {(T)0, (T)0};
 }
 
-// dst = src * scale, converting element types.
+// dst_s = src_s / st[s].norm, converting element types (instance s = blockIdx.z).
 template <typename TS, typename TD>
-__global__ __launch_bounds__(kThreads) void k_convert(const cx<TS>* src, cx<TD>* dst, size_t N, const GState* st,
-                                                      int invert_norm) {
-  const double sc = invert_norm ? 1.0 / st->norm : 1.0;
+__global__ __launch_bounds__(kThreads) void k_convert_unit(const cx<TS>* src, cx<TD>* dst, size_t N,
+                                                           const GState* st) {
+  const int s = blockIdx.z;
+  const double sc = 1.0 / st[s].norm;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(src[e]);
-    dst[e] = down<TD>({a.x * sc, a.y * sc});
+    const cx<double> a = up(src[(size_t)s * N + e]);
+    dst[(size_t)s * N + e] = down<TD>({a.x * sc, a.y * sc});
   }
 }
 
@@ -324,69 +393,90 @@ __global__ __launch_bounds__(kThreads) void k_real_to_float(const double* src, f
     dst[e] = (float)src[e];
 }
 
-// dst += alpha * src (FP64 accumulation)
+// dst_s += st[s].norm * src_s for the instances in mask (FP64 accumulation).
 template <typename TS, typename TD>
-__global__ __launch_bounds__(kThreads) void k_axpy(const cx<TS>* src, cx<TD>* dst, size_t N, double alpha) {
+__global__ __launch_bounds__(kThreads) void k_axpy_norm(const cx<TS>* src, cx<TD>* dst, size_t N, const GState* st,
+                                                        unsigned long long mask) {
+  const int s = blockIdx.z;
+  if (!in_mask(mask, s)) return;
+  const double alpha = st[s].norm;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(src[e]), b = up(dst[e]);
-    dst[e] = down<TD>({b.x + alpha * a.x, b.y + alpha * a.y});
+    const cx<double> a = up(src[(size_t)s * N + e]), b = up(dst[(size_t)s * N + e]);
+    dst[(size_t)s * N + e] = down<TD>({b.x + alpha * a.x, b.y + alpha * a.y});
   }
 }
 
 // ---------------------------------------------------------------------------
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Scratch of one GMRES instance with vectors of element type T.
+// Scratch of a batch of `count` GMRES instances with vectors of element type T:
+// the instances' states, Hessenberg matrices (column-major, ldh = restart + 1),
+// rotations and reduction partials one after the other, the basis interleaved
+// (vector i of instance s at V + (i count + s) N, so the operator reads and
+// writes all instances' vector i as one batch of densities), the residual and
+// work vectors of every instance, and the operator's intermediate for
+// min(count, conv_apply chunk) densities.
 template <typename T>
 struct Krylov {
-  int restart = 0;
+  int restart = 0, count = 1;
   size_t N = 0;
-  GState* st = nullptr;
-  cx<double>* H = nullptr;   // column-major, ldh = restart + 1
-  cx<double>* cs = nullptr;
+  GState* st = nullptr;      // [count]
+  int* alldone = nullptr;    // every instance stopped (batches of more than one)
+  cx<double>* H = nullptr;   // [count][(restart + 1) restart]
+  cx<double>* cs = nullptr;  // [count][restart]
   cx<double>* sn = nullptr;
-  cx<double>* g = nullptr;
+  cx<double>* g = nullptr;   // [count][restart + 1]
   cx<double>* y = nullptr;
   cx<double>* h = nullptr;
-  cx<double>* partial = nullptr;
-  double* npart = nullptr;
-  cx<T>* V = nullptr;        // restart + 1 vectors
-  cx<T>* r = nullptr;
+  cx<double>* partial = nullptr;   // [count][(restart + 1) kBlocks]
+  double* npart = nullptr;         // [count][kBlocks]
+  cx<T>* V = nullptr;        // [restart + 1][count][N]
+  cx<T>* r = nullptr;        // [count][N]
   cx<T>* t = nullptr;
-  cx<T>* awork = nullptr;    // apply intermediate (n x nb, blocked)
+  cx<T>* awork = nullptr;    // apply intermediates (n x nb, blocked)
 
-  static size_t bytes(int restart, size_t N, int n, int nb) {
-    size_t b = align_up(sizeof(GState));
-    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * restart);
-    b += 3 * align_up(sizeof(cx<double>) * (size_t)(restart + 1)) + 2 * align_up(sizeof(cx<double>) * restart);
-    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks) + align_up(sizeof(double) * kBlocks);
-    b += align_up(sizeof(cx<T>) * (size_t)(restart + 1) * N) + 2 * align_up(sizeof(cx<T>) * N);
-    b += align_up(sizeof(cx<T>) * inter_elems<T>(n, nb));
+  size_t hstride() const { return (size_t)(restart + 1) * restart; }
+  size_t pstride() const { return (size_t)(restart + 1) * kBlocks; }
+
+  static size_t bytes(int restart, size_t N, int n, int nb, int count, int inters) {
+    const size_t c = (size_t)count;
+    size_t b = align_up(sizeof(GState) * c + sizeof(int));
+    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * restart * c);
+    b += 3 * align_up(sizeof(cx<double>) * (size_t)(restart + 1) * c) + 2 * align_up(sizeof(cx<double>) * restart * c);
+    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks * c) + align_up(sizeof(double) * kBlocks * c);
+    b += align_up(sizeof(cx<T>) * (size_t)(restart + 1) * N * c) + 2 * align_up(sizeof(cx<T>) * N * c);
+    b += align_up(sizeof(cx<T>) * inter_elems<T>(n, nb) * (size_t)inters);
     return b;
   }
-  char* carve(char* base, int rs, size_t n_elems, int n, int nb) {
+  char* carve(char* base, int rs, size_t n_elems, int n, int nb, int cnt, int inters) {
     restart = rs;
     N = n_elems;
+    count = cnt;
+    const size_t c = (size_t)cnt;
     auto take = [&](size_t sz) {
       char* p = base;
       base += align_up(sz);
       return p;
     };
-    st = (GState*)take(sizeof(GState));
-    H = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * rs);
-    g = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1));
-    h = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1));
-    y = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1));
-    cs = (cx<double>*)take(sizeof(cx<double>) * rs);
-    sn = (cx<double>*)take(sizeof(cx<double>) * rs);
-    partial = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * kBlocks);
-    npart = (double*)take(sizeof(double) * kBlocks);
-    V = (cx<T>*)take(sizeof(cx<T>) * (size_t)(rs + 1) * N);
-    r = (cx<T>*)take(sizeof(cx<T>) * N);
-    t = (cx<T>*)take(sizeof(cx<T>) * N);
-    awork = (cx<T>*)take(sizeof(cx<T>) * inter_elems<T>(n, nb));
+    char* stb = take(sizeof(GState) * c + sizeof(int));
+    st = (GState*)stb;
+    alldone = (int*)(stb + sizeof(GState) * c);
+    H = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * rs * c);
+    g = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
+    h = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
+    y = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
+    cs = (cx<double>*)take(sizeof(cx<double>) * rs * c);
+    sn = (cx<double>*)take(sizeof(cx<double>) * rs * c);
+    partial = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * kBlocks * c);
+    npart = (double*)take(sizeof(double) * kBlocks * c);
+    V = (cx<T>*)take(sizeof(cx<T>) * (size_t)(rs + 1) * N * c);
+    r = (cx<T>*)take(sizeof(cx<T>) * N * c);
+    t = (cx<T>*)take(sizeof(cx<T>) * N * c);
+    awork = (cx<T>*)take(sizeof(cx<T>) * inter_elems<T>(n, nb) * (size_t)inters);
     return base;
   }
+  // The operator's skip flag: the instance's own stop flag, or "all stopped".
+  const int* skip() const { return count == 1 ? &st[0].done : alldone; }
 };
 
 struct Counters {
@@ -394,41 +484,43 @@ struct Counters {
   int iterations = 0;
 };
 
-inline hipError_t host_state(const GState* st, GState* out, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(out, st, sizeof(GState), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
-}
-
 inline int grid_for(size_t N) {
   const size_t b = (N + kThreads - 1) / kThreads;
   return (int)(b < (size_t)kBlocks ? b : (size_t)kBlocks);
 }
 
-// Norm of v into st->norm, returned on the host (one synchronisation).
+// States of a batch's instances, read on the host (one synchronisation).
+inline hipError_t host_states(const GState* st, int count, GState* out, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(out, st, sizeof(GState) * count, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// Norms of the count vectors v_s into st[s].norm, returned on the host.
 template <typename T>
-hipError_t norm_sync(Krylov<T>& K, const cx<T>* v, double* out, hipStream_t s) {
-  k_sumsq<T><<<kBlocks, kThreads, 0, s>>>(v, K.N, K.npart);
-  k_norm_finish<<<1, kThreads, 0, s>>>(K.npart, kBlocks, K.st);
-  GState h;
-  hipError_t e = host_state(K.st, &h, s);
-  *out = h.norm;
+hipError_t norms_sync(Krylov<T>& K, const cx<T>* v, std::vector<double>& out, hipStream_t s) {
+  k_sumsq<T><<<dim3(kBlocks, 1, K.count), kThreads, 0, s>>>(v, K.N, K.npart);
+  k_norm_finish<<<K.count, kThreads, 0, s>>>(K.npart, kBlocks, K.st);
+  std::vector<GState> h(K.count);
+  hipError_t e = host_states(K.st, K.count, h.data(), s);
+  out.resize(K.count);
+  for (int i = 0; i < K.count; ++i) out[i] = h[i].norm;
   return e;
 }
 
-// Arnoldi steps are enqueued kChunk at a time.  After each chunk the cycle's
-// state is copied (asynchronously) to page-locked host memory; before the
-// next chunk is enqueued the host reads the state copied kLag chunks earlier
-// and stops enqueuing once the device has met the stop test there, so at most
-// kLag chunks of steps that exit at entry are enqueued after convergence.
+// Arnoldi steps are enqueued kChunk at a time.  After each chunk the batch's
+// stop flag is copied (asynchronously) to page-locked host memory; before the
+// next chunk is enqueued the host reads the flag copied kLag chunks earlier
+// and stops enqueuing once every instance had stopped there, so at most kLag
+// chunks of steps that exit at entry are enqueued after the stop.
 constexpr int kChunk = 4, kLag = 1, kMaxSnap = 64;
 
 struct HostSnapshots {
-  GState* pinned = nullptr;        // kMaxSnap page-locked slots
+  int* pinned = nullptr;           // kMaxSnap page-locked slots
   hipEvent_t ev[kMaxSnap] = {};
   bool ok = false;
   HostSnapshots() {
-    if (hipHostMalloc((void**)&pinned, sizeof(GState) * kMaxSnap, 0) != hipSuccess) return;
+    if (hipHostMalloc((void**)&pinned, sizeof(int) * kMaxSnap, 0) != hipSuccess) return;
     for (auto& e : ev)
       if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
     ok = true;
@@ -440,27 +532,30 @@ HostSnapshots& snapshots() {
   return h;
 }
 
-// Steps [j0, j0 + c) of an Arnoldi cycle: the operator, classical
-// Gram-Schmidt twice (FP64 coefficients), Givens rotation, normalisation.
+// Steps [j0, j0 + c) of an Arnoldi cycle of every instance: the operator,
+// classical Gram-Schmidt twice (FP64 coefficients), Givens rotation,
+// normalisation.
 template <typename T, typename OpF>
 hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
   const size_t N = K.N;
+  const int cnt = K.count;
   const int ldh = K.restart + 1;
   const int nbu = grid_for(N);
   // dot-product blocks per vector: few, so every update block can finish the sums cheaply
   const int nbd = (int)std::min<size_t>(64, std::max<size_t>(8, N / 4096));
   for (int j = j0; j < j0 + c; ++j) {
-    cx<T>* vj = K.V + (size_t)j * N;
-    cx<T>* w = K.V + (size_t)(j + 1) * N;
-    hipError_t e = op(vj, w, &K.st->done);
+    cx<T>* vj = K.V + (size_t)j * cnt * N;
+    cx<T>* w = K.V + (size_t)(j + 1) * cnt * N;
+    hipError_t e = op(vj, w, K.skip());
     if (e != hipSuccess) return e;
-    cx<double>* Hcol = K.H + (size_t)j * ldh;
     for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
-      k_dots<T><<<dim3(nbd, j + 1), kThreads, 0, s>>>(K.V, N, w, K.partial, K.st);
-      k_update<T><<<nbu, kThreads, 0, s>>>(K.V, N, j + 1, w, K.partial, nbd, Hcol, pass == 1 ? K.npart : nullptr,
-                                           K.st);
+      k_dots<T><<<dim3(nbd, j + 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, K.partial, K.pstride(), K.st);
+      k_update<T><<<dim3(nbu, 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, K.V, K.partial, K.pstride(), nbd, K.H,
+                                                          K.hstride(), ldh, pass == 1 ? K.npart : nullptr, K.st);
     }
-    k_normalise_givens<T><<<nbu, kThreads, 0, s>>>(w, N, K.npart, nbu, K.H, ldh, K.cs, K.sn, K.g, j, K.st);
+    k_normalise_givens<T><<<dim3(nbu, 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, K.npart, nbu, K.H, K.hstride(), ldh,
+                                                                  K.cs, K.sn, K.restart, K.g, K.st);
+    if (cnt > 1) k_all_done<<<1, 64, 0, s>>>(K.st, cnt, K.alldone);
   }
   return hipGetLastError();
 }
@@ -470,11 +565,11 @@ hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
 // then replayed.  The captured kernels read every changing value (the cycle
 // state, the stop flag) from device memory.
 struct GraphKey {
-  const void* st;          // Krylov instance (its scratch layout follows from restart and T)
+  const void* st;          // Krylov batch (its scratch layout follows from restart, T and count)
   const void* op;          // operator's contrast
-  int restart, elem, j0, c;
+  int restart, elem, count, j0, c;
   bool operator<(const GraphKey& o) const {
-    return std::tie(st, op, restart, elem, j0, c) < std::tie(o.st, o.op, o.restart, o.elem, o.j0, o.c);
+    return std::tie(st, op, restart, elem, count, j0, c) < std::tie(o.st, o.op, o.restart, o.elem, o.count, o.j0, o.c);
   }
 };
 struct GraphCache {
@@ -492,7 +587,7 @@ hipError_t run_chunk(const Plan& p, Krylov<T>& K, OpF& op, const void* op_id, in
                      bool graphs) {
   if (!graphs) return arnoldi_steps(K, op, j0, c, s);
   auto* cache = static_cast<GraphCache*>(p.graphs);
-  const GraphKey key{K.st, op_id, K.restart, (int)sizeof(T), j0, c};
+  const GraphKey key{K.st, op_id, K.restart, (int)sizeof(T), K.count, j0, c};
   hipGraphExec_t ex = nullptr;
   {
     std::lock_guard<std::mutex> lk(cache->mu);
@@ -525,43 +620,79 @@ hipError_t run_chunk(const Plan& p, Krylov<T>& K, OpF& op, const void* op_id, in
   return hipGraphLaunch(ex, s);
 }
 
-// GMRES(restart) for Op x = rhs from x = 0 (x must be zeroed by the caller).
-// Stops when the true residual ||rhs - Op x|| <= tol_rel ||rhs||, at max_mv
-// operator applications, or on a non-finite value.  Returns the status code.
+inline bool in_mask_host(unsigned long long m, int s) { return (m >> s) & 1ull; }
+
+// Per-instance outcome of gmres.
+struct Outcome {
+  int status = WS_LS_MAXIT;
+  double relres = 0.0;
+};
+
+// GMRES(restart) for Op x_s = rhs_s, s < count, from x_s = 0 (x zeroed by the
+// caller), for the instances in `run` (the others are left alone).  Instance s
+// stops when its true residual ||rhs_s - Op x_s|| <= tol_rel ||rhs_s||, at
+// max_mv[s] operator applications (counted in cnt[s]), or on a non-finite
+// value.  Returns 0, or -1 with *herr set.
 template <typename T, typename OpF>
 int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* rhs, cx<T>* x, double tol_rel,
-          int max_mv, Counters& cnt, double* relres, hipStream_t s, bool graphs, hipError_t* herr) {
+          const std::vector<int>& max_mv, unsigned long long run, std::vector<Counters>& cnt,
+          std::vector<Outcome>& out, hipStream_t s, bool graphs, hipError_t* herr) {
   const size_t N = K.N;
-  const int ldh = K.restart + 1;
+  const int C = K.count;
   HostSnapshots& snap = snapshots();
   if (!snap.ok) {
     *herr = hipErrorOutOfMemory;
     return -1;
   }
-  double rhsn = 0.0;
-  if ((*herr = norm_sync(K, rhs, &rhsn, s)) != hipSuccess) return -1;
-  if (!std::isfinite(rhsn)) return WS_LS_BREAKDOWN;
-  if (rhsn == 0.0) {
-    *relres = 0.0;
-    return WS_LS_CONVERGED;
+  std::vector<double> rhsn, rn;
+  if ((*herr = norms_sync(K, rhs, rhsn, s)) != hipSuccess) return -1;
+  unsigned long long active = 0;
+  std::vector<double> tol_abs(C, 0.0);
+  for (int i = 0; i < C; ++i) {
+    if (!in_mask_host(run, i)) continue;
+    if (!std::isfinite(rhsn[i])) {
+      out[i].status = WS_LS_BREAKDOWN;
+    } else if (rhsn[i] == 0.0) {
+      out[i] = {WS_LS_CONVERGED, 0.0};
+    } else {
+      active |= 1ull << i;
+      tol_abs[i] = tol_rel * rhsn[i];
+    }
   }
-  const double tol_abs = tol_rel * rhsn;
-  const cx<T>* rcur = rhs;       // residual of the current iterate (x = 0 at start)
-  double rn = rhsn;
-  // st->norm already holds ||rhs||.
+  rn = rhsn;
+  const cx<T>* rcur = rhs;       // residuals of the current iterates (x = 0 at start)
+  // st[s].norm holds ||rhs_s||.
+  std::vector<GState> hs(C);
   while (true) {
-    *relres = rn / rhsn;
-    if (!std::isfinite(rn)) return WS_LS_BREAKDOWN;
-    if (rn <= tol_abs) return WS_LS_CONVERGED;
-    if (cnt.matvecs >= max_mv) return WS_LS_MAXIT;
-    k_cycle_start<T><<<grid_for(N), kThreads, 0, s>>>(rcur, K.V, N, K.H, ldh * K.restart, K.g, ldh, K.st, tol_abs);
-    const int steps = std::min(K.restart, max_mv - cnt.matvecs);
+    CycleCtl ctl{};
+    int steps = 0;
+    for (int i = 0; i < C; ++i) {
+      if (!in_mask_host(active, i)) continue;
+      out[i].relres = rn[i] / rhsn[i];
+      int st = -1;
+      if (!std::isfinite(rn[i])) st = WS_LS_BREAKDOWN;
+      else if (rn[i] <= tol_abs[i]) st = WS_LS_CONVERGED;
+      else if (cnt[i].matvecs >= max_mv[i]) st = WS_LS_MAXIT;
+      if (st >= 0) {
+        out[i].status = st;
+        active &= ~(1ull << i);
+        continue;
+      }
+      ctl.tol_abs[i] = tol_abs[i];
+      ctl.maxk[i] = std::min(K.restart, max_mv[i] - cnt[i].matvecs);
+      steps = std::max(steps, ctl.maxk[i]);
+    }
+    if (!active) return 0;
+    ctl.active = active;
+    k_cycle_start<T><<<dim3(grid_for(N), 1, C), kThreads, 0, s>>>(rcur, K.V, N, C, K.H, K.hstride(), K.g,
+                                                                    K.restart + 1, K.st, ctl);
+    if (C > 1) k_all_done<<<1, 64, 0, s>>>(K.st, C, K.alldone);
     int nsnap = 0;
     for (int j0 = 0; j0 < steps; j0 += kChunk) {
       const int c = std::min(kChunk, steps - j0);
       if ((*herr = run_chunk(p, K, op, op_id, j0, c, s, graphs)) != hipSuccess) return -1;
       if (nsnap < kMaxSnap) {
-        if ((*herr = hipMemcpyAsync(&snap.pinned[nsnap], K.st, sizeof(GState), hipMemcpyDeviceToHost, s)) !=
+        if ((*herr = hipMemcpyAsync(&snap.pinned[nsnap], K.skip(), sizeof(int), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess ||
             (*herr = hipEventRecord(snap.ev[nsnap], s)) != hipSuccess)
           return -1;
@@ -570,44 +701,61 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
       if (nsnap > kLag && j0 + c < steps) {
         const int k = nsnap - 1 - kLag;
         if ((*herr = hipEventSynchronize(snap.ev[k])) != hipSuccess) return -1;
-        if (snap.pinned[k].done) break;
+        if (snap.pinned[k]) break;
       }
     }
     if ((*herr = hipGetLastError()) != hipSuccess) return -1;
-    GState hs;
-    if ((*herr = host_state(K.st, &hs, s)) != hipSuccess) return -1;
-    cnt.matvecs += hs.kused;
-    cnt.iterations += hs.kused;
-    if (hs.bad) return WS_LS_BREAKDOWN;
-    if (hs.kused > 0) {
-      k_trisolve<<<1, 1, 0, s>>>(K.H, ldh, K.g, K.y, K.st);
-      k_xupdate<T, T><<<kBlocks, kThreads, 0, s>>>(x, K.V, N, K.y, K.st, 1.0);
+    if ((*herr = host_states(K.st, C, hs.data(), s)) != hipSuccess) return -1;
+    unsigned long long upd = 0;
+    for (int i = 0; i < C; ++i) {
+      if (!in_mask_host(active, i)) continue;
+      cnt[i].matvecs += hs[i].kused;
+      cnt[i].iterations += hs[i].kused;
+      if (hs[i].bad) {
+        out[i].status = WS_LS_BREAKDOWN;
+        active &= ~(1ull << i);
+      } else if (hs[i].kused > 0) {
+        upd |= 1ull << i;
+      }
     }
-    // True residual r = rhs - Op x.
+    if (upd) {
+      k_trisolve<<<C, 1, 0, s>>>(K.H, K.hstride(), K.restart + 1, K.g, K.restart + 1, K.y, K.st, upd);
+      k_xupdate<T, T><<<dim3(kBlocks, 1, C), kThreads, 0, s>>>(x, K.V, N, C, K.y, K.restart + 1, K.st, 1.0, upd);
+    }
+    if (!active) return 0;
+    // True residuals r_s = rhs_s - Op x_s.
     if ((*herr = op(x, K.t, nullptr)) != hipSuccess) return -1;
-    cnt.matvecs += 1;
-    k_residual<T><<<kBlocks, kThreads, 0, s>>>(rhs, K.t, K.r, N, K.npart);
-    k_norm_finish<<<1, kThreads, 0, s>>>(K.npart, kBlocks, K.st);
-    if ((*herr = host_state(K.st, &hs, s)) != hipSuccess) return -1;
-    rn = hs.norm;
+    k_residual<T><<<dim3(kBlocks, 1, C), kThreads, 0, s>>>(rhs, K.t, K.r, N, K.npart);
+    k_norm_finish<<<C, kThreads, 0, s>>>(K.npart, kBlocks, K.st);
+    if ((*herr = host_states(K.st, C, hs.data(), s)) != hipSuccess) return -1;
     rcur = K.r;
-    if (hs.kused == 0 && rn > tol_abs) {
-      *relres = rn / rhsn;
-      return WS_LS_MAXIT;   // no progress possible within the budget
+    for (int i = 0; i < C; ++i) {
+      if (!in_mask_host(active, i)) continue;
+      cnt[i].matvecs += 1;
+      rn[i] = hs[i].norm;
+      if (hs[i].kused == 0 && rn[i] > tol_abs[i]) {
+        out[i] = {WS_LS_MAXIT, rn[i] / rhsn[i]};   // no progress possible within the budget
+        active &= ~(1ull << i);
+      }
     }
   }
 }
 
 }  // namespace
 
-size_t ls_work_bytes(const Plan& p, int restart, bool mixed) {
+// Densities whose operator intermediates a batch of `count` keeps at once.
+static int batch_inters(const Plan& p, int count) { return std::max(1, std::min(count, apply_chunk(p))); }
+
+size_t ls_work_bytes(const Plan& p, int restart, bool mixed, int count) {
   const size_t N = (size_t)p.n * p.n;
   const int nb = p.b * p.n;                                   // the plan's period (also for unbuilt plans)
-  if (!mixed) return Krylov<double>::bytes(restart, N, p.n, nb);
-  size_t b = Krylov<float>::bytes(restart, N, p.n, nb);
-  b += align_up(sizeof(float) * N);                           // FP32 contrast
-  b += 2 * align_up(sizeof(cx<float>) * N);                   // correction, inner right-hand side
-  b += Krylov<double>::bytes(1, N, p.n, nb);                  // FP64 residual machinery
+  const int inters = batch_inters(p, count);
+  const size_t c = (size_t)count;
+  if (!mixed) return Krylov<double>::bytes(restart, N, p.n, nb, count, inters);
+  size_t b = Krylov<float>::bytes(restart, N, p.n, nb, count, inters);
+  b += align_up(sizeof(float) * N * c);                       // FP32 contrasts
+  b += 2 * align_up(sizeof(cx<float>) * N * c);               // corrections, inner right-hand sides
+  b += Krylov<double>::bytes(1, N, p.n, nb, count, inters);   // FP64 residual machinery
   return b;
 }
 
@@ -631,17 +779,133 @@ SideStream& side_stream() {
   static thread_local SideStream ss;
   return ss;
 }
+
+int ls_run_on(const Plan& p, int count, const double* contrast, const cx<double>* u_inc, double tol, int restart,
+              int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
+              bool graphs, std::string* err) {
+  const size_t N = (size_t)p.n * p.n;
+  const size_t NC = N * (size_t)count;
+  const double k2 = p.kern.kappa * p.kern.kappa;
+  const int inters = batch_inters(p, count);
+  const unsigned long long all = count == 64 ? ~0ull : ((1ull << count) - 1);
+  std::vector<Counters> cnt(count);
+  std::vector<Outcome> out(count);
+  std::vector<int> refinements(count, 0);
+  hipError_t he = hipSuccess;
+  char* base = static_cast<char*>(work);
+  if (!mixed) {
+    Krylov<double> K;
+    K.carve(base, restart, N, p.n, p.nb, count, inters);
+    auto op = [&](const cx<double>* in, cx<double>* o, const int* skip) {
+      return launch_apply_cplx<double>(p, count, in, contrast, k2, true, o, K.awork, s, skip, inters, N);
+    };
+    k_zero<double><<<grid_for(NC), kThreads, 0, s>>>(u_out, NC);
+    const std::vector<int> budget(count, max_matvecs);
+    if (gmres<double>(p, K, op, contrast, u_inc, u_out, tol, budget, all, cnt, out, s, graphs, &he) < 0)
+      goto device_error;
+  } else {
+    Krylov<float> K32;
+    char* nxt = K32.carve(base, restart, N, p.n, p.nb, count, inters);
+    float* m32 = (float*)nxt;
+    nxt += align_up(sizeof(float) * NC);
+    cx<float>* delta = (cx<float>*)nxt;
+    nxt += align_up(sizeof(cx<float>) * NC);
+    cx<float>* rhs32 = (cx<float>*)nxt;
+    nxt += align_up(sizeof(cx<float>) * NC);
+    Krylov<double> K64;
+    K64.carve(nxt, 1, N, p.n, p.nb, count, inters);
+    k_real_to_float<<<grid_for(NC), kThreads, 0, s>>>(contrast, m32, NC);
+    auto op32 = [&](const cx<float>* in, cx<float>* o, const int* skip) {
+      return launch_apply_cplx<float>(p, count, in, m32, (float)k2, true, o, K32.awork, s, skip, inters, N);
+    };
+    k_zero<double><<<grid_for(NC), kThreads, 0, s>>>(u_out, NC);
+    std::vector<double> fn, rn;
+    if ((he = norms_sync(K64, u_inc, fn, s)) != hipSuccess) goto device_error;
+    {
+      // Refinement: r_s = u_inc_s - K x_s in FP64; K64.st[s].norm holds ||r_s||.
+      unsigned long long active = 0;
+      for (int i = 0; i < count; ++i) {
+        if (!std::isfinite(fn[i])) out[i].status = WS_LS_BREAKDOWN;
+        else if (fn[i] == 0.0) out[i] = {WS_LS_CONVERGED, 0.0};
+        else active |= 1ull << i;
+      }
+      const cx<double>* r64 = u_inc;
+      rn = fn;
+      std::vector<double> prev(count, HUGE_VAL);
+      const double inner_tol = 1e-5;
+      std::vector<GState> hs(count);
+      while (true) {
+        std::vector<int> budget(count, 0);
+        for (int i = 0; i < count; ++i) {
+          if (!in_mask_host(active, i)) continue;
+          out[i].relres = rn[i] / fn[i];
+          int st = -1;
+          if (!std::isfinite(rn[i])) st = WS_LS_BREAKDOWN;
+          else if (rn[i] <= tol * fn[i]) st = WS_LS_CONVERGED;
+          else if (cnt[i].matvecs >= max_matvecs || rn[i] > 0.5 * prev[i]) st = WS_LS_MAXIT;
+          if (st >= 0) {
+            out[i].status = st;
+            active &= ~(1ull << i);
+            continue;
+          }
+          prev[i] = rn[i];
+          budget[i] = max_matvecs - cnt[i].matvecs;
+        }
+        if (!active) break;
+        k_convert_unit<double, float><<<dim3(grid_for(N), 1, count), kThreads, 0, s>>>(r64, rhs32, N, K64.st);
+        k_zero<float><<<grid_for(NC), kThreads, 0, s>>>(delta, NC);
+        std::vector<Outcome> inner(count);
+        if (gmres<float>(p, K32, op32, m32, rhs32, delta, inner_tol, budget, active, cnt, inner, s, graphs, &he) < 0)
+          goto device_error;
+        for (int i = 0; i < count; ++i) {
+          if (in_mask_host(active, i) && inner[i].status == WS_LS_BREAKDOWN) {
+            out[i].status = WS_LS_BREAKDOWN;
+            active &= ~(1ull << i);
+          }
+        }
+        if (!active) break;
+        k_axpy_norm<float, double><<<dim3(grid_for(N), 1, count), kThreads, 0, s>>>(delta, u_out, N, K64.st, active);
+        if ((he = launch_apply_cplx<double>(p, count, u_out, contrast, k2, true, K64.t, K64.awork, s, nullptr, inters,
+                                            N)) != hipSuccess)
+          goto device_error;
+        k_residual<double><<<dim3(kBlocks, 1, count), kThreads, 0, s>>>(u_inc, K64.t, K64.r, N, K64.npart);
+        k_norm_finish<<<count, kThreads, 0, s>>>(K64.npart, kBlocks, K64.st);
+        if ((he = host_states(K64.st, count, hs.data(), s)) != hipSuccess) goto device_error;
+        r64 = K64.r;
+        for (int i = 0; i < count; ++i) {
+          if (!in_mask_host(active, i)) continue;
+          cnt[i].matvecs += 1;
+          rn[i] = hs[i].norm;
+          refinements[i] += 1;
+        }
+      }
+    }
+  }
+  if ((he = hipGetLastError()) != hipSuccess) goto device_error;
+  {
+    int worst = WS_LS_CONVERGED;
+    for (int i = 0; i < count; ++i) {
+      info[i].status = out[i].status;
+      info[i].matvecs = cnt[i].matvecs;
+      info[i].iterations = cnt[i].iterations;
+      info[i].refinements = refinements[i];
+      info[i].rel_residual = out[i].relres;
+      worst = std::max(worst, out[i].status);
+    }
+    return worst;
+  }
+device_error:
+  *err = std::string("ls_solve: ") + hipGetErrorString(he);
+  return WS_EDEVICE;
+}
 }  // namespace
 
-int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart,
-              int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
-              bool graphs, std::string* err);
-
-int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart, int max_matvecs,
-           bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s, std::string* err) {
+int ls_run(const Plan& p, int count, const double* contrast, const cx<double>* u_inc, double tol, int restart,
+           int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
+           std::string* err) {
   const bool graphs = p.graphs != nullptr;
   if (!graphs || s != nullptr)
-    return ls_run_on(p, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, s, graphs, err);
+    return ls_run_on(p, count, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, s, graphs, err);
   // Null stream: run on this thread's side stream, ordered after and before the caller's work.
   SideStream& ss = side_stream();
   hipError_t e = ss.ok ? hipSuccess : hipErrorOutOfMemory;
@@ -651,7 +915,8 @@ int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, doubl
     *err = std::string("ls_solve: ") + hipGetErrorString(e);
     return WS_EDEVICE;
   }
-  const int rc = ls_run_on(p, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, ss.s, true, err);
+  const int rc =
+      ls_run_on(p, count, contrast, u_inc, tol, restart, max_matvecs, mixed, u_out, work, info, ss.s, true, err);
   e = hipEventRecord(ss.join, ss.s);
   if (e == hipSuccess) e = hipStreamWaitEvent(s, ss.join, 0);
   if (e != hipSuccess && rc >= 0) {
@@ -659,92 +924,6 @@ int ls_run(const Plan& p, const double* contrast, const cx<double>* u_inc, doubl
     return WS_EDEVICE;
   }
   return rc;
-}
-
-int ls_run_on(const Plan& p, const double* contrast, const cx<double>* u_inc, double tol, int restart,
-              int max_matvecs, bool mixed, cx<double>* u_out, void* work, ws_ls_info* info, hipStream_t s,
-              bool graphs, std::string* err) {
-  const size_t N = (size_t)p.n * p.n;
-  const double k2 = p.kern.kappa * p.kern.kappa;
-  Counters cnt;
-  hipError_t he = hipSuccess;
-  double relres = 0.0;
-  int status = WS_LS_MAXIT;
-  char* base = static_cast<char*>(work);
-  if (!mixed) {
-    Krylov<double> K;
-    K.carve(base, restart, N, p.n, p.nb);
-    auto op = [&](const cx<double>* in, cx<double>* out, const int* skip) {
-      return launch_apply_cplx<double>(p, 1, in, contrast, k2, true, out, K.awork, s, skip);
-    };
-    k_zero<double><<<grid_for(N), kThreads, 0, s>>>(u_out, N);
-    status = gmres<double>(p, K, op, contrast, u_inc, u_out, tol, max_matvecs, cnt, &relres, s, graphs, &he);
-    if (status < 0) goto device_error;
-  } else {
-    Krylov<float> K32;
-    char* nxt = K32.carve(base, restart, N, p.n, p.nb);
-    float* m32 = (float*)nxt;
-    nxt += align_up(sizeof(float) * N);
-    cx<float>* delta = (cx<float>*)nxt;
-    nxt += align_up(sizeof(cx<float>) * N);
-    cx<float>* rhs32 = (cx<float>*)nxt;
-    nxt += align_up(sizeof(cx<float>) * N);
-    Krylov<double> K64;
-    K64.carve(nxt, 1, N, p.n, p.nb);
-    k_real_to_float<<<grid_for(N), kThreads, 0, s>>>(contrast, m32, N);
-    auto op32 = [&](const cx<float>* in, cx<float>* out, const int* skip) {
-      return launch_apply_cplx<float>(p, 1, in, m32, (float)k2, true, out, K32.awork, s, skip);
-    };
-    k_zero<double><<<grid_for(N), kThreads, 0, s>>>(u_out, N);
-    double fn = 0.0;
-    if ((he = norm_sync(K64, u_inc, &fn, s)) != hipSuccess) goto device_error;
-    if (!std::isfinite(fn)) {
-      status = WS_LS_BREAKDOWN;
-    } else if (fn == 0.0) {
-      status = WS_LS_CONVERGED;
-      relres = 0.0;
-    } else {
-      // Refinement: r = u_inc - K x in FP64; K64.st->norm holds ||r||.
-      const cx<double>* r64 = u_inc;
-      double rn = fn, prev = HUGE_VAL;
-      const double inner_tol = 1e-5;
-      while (true) {
-        relres = rn / fn;
-        if (!std::isfinite(rn)) { status = WS_LS_BREAKDOWN; break; }
-        if (rn <= tol * fn) { status = WS_LS_CONVERGED; break; }
-        if (cnt.matvecs >= max_matvecs || rn > 0.5 * prev) { status = WS_LS_MAXIT; break; }
-        prev = rn;
-        k_convert<double, float><<<grid_for(N), kThreads, 0, s>>>(r64, rhs32, N, K64.st, 1);
-        k_zero<float><<<grid_for(N), kThreads, 0, s>>>(delta, N);
-        double inner_rel = 0.0;
-        const int ist = gmres<float>(p, K32, op32, m32, rhs32, delta, inner_tol, max_matvecs - cnt.matvecs, cnt,
-                                     &inner_rel, s, graphs, &he);
-        if (ist < 0) goto device_error;
-        if (ist == WS_LS_BREAKDOWN) { status = WS_LS_BREAKDOWN; break; }
-        k_axpy<float, double><<<grid_for(N), kThreads, 0, s>>>(delta, u_out, N, rn);
-        if ((he = launch_apply_cplx<double>(p, 1, u_out, contrast, k2, true, K64.t, K64.awork, s, nullptr)) !=
-            hipSuccess)
-          goto device_error;
-        cnt.matvecs += 1;
-        k_residual<double><<<kBlocks, kThreads, 0, s>>>(u_inc, K64.t, K64.r, N, K64.npart);
-        k_norm_finish<<<1, kThreads, 0, s>>>(K64.npart, kBlocks, K64.st);
-        GState hs;
-        if ((he = host_state(K64.st, &hs, s)) != hipSuccess) goto device_error;
-        rn = hs.norm;
-        r64 = K64.r;
-        info->refinements += 1;
-      }
-    }
-  }
-  if ((he = hipGetLastError()) != hipSuccess) goto device_error;
-  info->status = status;
-  info->matvecs = cnt.matvecs;
-  info->iterations = cnt.iterations;
-  info->rel_residual = relres;
-  return status == WS_LS_CONVERGED ? WS_OK : status;
-device_error:
-  *err = std::string("ls_solve: ") + hipGetErrorString(he);
-  return WS_EDEVICE;
 }
 
 }  // namespace ws

@@ -160,20 +160,26 @@ __device__ inline double yukawa_moment(double kabs, const KernelArgs& K) {
   return 2.0 * M_PI * num / (xi * xi + kap * kap);
 }
 
-// Moment of scale * g at |k|, times inv = nb^-2.
+// Moment of scale * g at |k|, times inv = nb^-2, for the family FAM (a
+// compile-time constant, so each table kernel holds one family's code only).
+template <int FAM>
 __device__ inline cx<double> moment(double kabs, const KernelArgs& K, double inv) {
-  if (K.family == WS_LOG) return {-2.0 * M_PI * K.scale * log_moment(kabs, K) * inv, 0.0};
-  if (K.family == WS_POWER) return {K.scale * power_moment(kabs, K) * inv, 0.0};
-  if (K.family == WS_YUKAWA) return {K.scale * yukawa_moment(kabs, K) * inv, 0.0};
-  const cx<double> h = helmholtz_moment(kabs, K);
-  return {K.scale * h.x * inv, K.scale * h.y * inv};
+  if constexpr (FAM == WS_LOG) return {-2.0 * M_PI * K.scale * log_moment(kabs, K) * inv, 0.0};
+  if constexpr (FAM == WS_POWER) return {K.scale * power_moment(kabs, K) * inv, 0.0};
+  if constexpr (FAM == WS_YUKAWA) return {K.scale * yukawa_moment(kabs, K) * inv, 0.0};
+  if constexpr (FAM == WS_HELMHOLTZ) {
+    const cx<double> h = helmholtz_moment(kabs, K);
+    return {K.scale * h.x * inv, K.scale * h.y * inv};
+  }
+  return {0.0, 0.0};
 }
 
 // Blocked table: entry (cb, k1f, c) <-> column bin k2 = cb*CB + c, folded row
-// k1f in [0, N], N = nb/2.
-template <int CB>
-__global__ void k_table(int nb, int ncols, KernelArgs K, double inv, int cplx, double* g64, float* g32,
-                        double* nyq64, float* nyq32) {
+// k1f in [0, N], N = nb/2.  Each moment is computed once and written to the
+// FP64 table and, for FP32 plans, to the FP32 copy (same blocked layout).
+template <int FAM, int CB>
+__global__ __launch_bounds__(256) void k_table(int nb, int ncols, KernelArgs K, double inv, int cplx,
+                                               double* g64, float* g32, double* nyq64, float* nyq32) {
   const int N = nb / 2;
   const size_t total = (size_t)ncols * (N + 1);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
@@ -184,21 +190,21 @@ __global__ void k_table(int nb, int ncols, KernelArgs K, double inv, int cplx, d
     int k2 = cb * CB + c;
     if (k2 > N) k2 = nb - k2;                        // |k2| of bin k2
     const double kabs = sqrt((double)k1f * k1f + (double)k2 * k2);
-    const cx<double> v = moment(kabs, K, inv);
+    const cx<double> v = moment<FAM>(kabs, K, inv);
     if (cplx) {
-      if (g64) reinterpret_cast<cx<double>*>(g64)[e] = v;
+      reinterpret_cast<cx<double>*>(g64)[e] = v;
       if (g32) reinterpret_cast<cx<float>*>(g32)[e] = {(float)v.x, (float)v.y};
     } else {
-      if (g64) g64[e] = v.x;
+      g64[e] = v.x;
       if (g32) g32[e] = (float)v.x;
     }
   }
   // Nyquist column k2 = N of the real path.
-  if (nyq64 || nyq32) {
+  if (nyq64) {
     for (int k1f = blockIdx.x * blockDim.x + threadIdx.x; k1f <= N; k1f += gridDim.x * blockDim.x) {
       const double kabs = sqrt((double)k1f * k1f + (double)N * N);
-      const double v = moment(kabs, K, inv).x;
-      if (nyq64) nyq64[k1f] = v;
+      const double v = moment<FAM>(kabs, K, inv).x;
+      nyq64[k1f] = v;
       if (nyq32) nyq32[k1f] = (float)v;
     }
   }
@@ -449,12 +455,30 @@ hipError_t launch_build_tables(Plan& pl, hipStream_t s) {
   const size_t total = (size_t)ncols * (nb / 2 + 1);
   const int blocks = (int)std::min<size_t>((total + threads - 1) / threads, 65536);
   const int cp = pl.cplx ? 1 : 0;
-  // FP64 table (every plan: FP64 applies, the refinement residual of mixed solves).
-  k_table<Layout<double>::CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, nullptr,
-                                                         pl.cplx ? nullptr : pl.gnyq64, nullptr);
-  if (pl.precision == WS_FP32)
-    k_table<Layout<float>::CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, nullptr, (float*)pl.g32,
-                                                          nullptr, pl.cplx ? nullptr : pl.gnyq32);
+  // One pass: the FP64 table (every plan: FP64 applies, the refinement residual of
+  // mixed solves) and, for FP32 plans, its FP32 copy in the same layout.
+  static_assert(Layout<double>::CB == Layout<float>::CB, "FP32 table copy assumes the FP64 block width");
+  float* g32 = pl.precision == WS_FP32 ? (float*)pl.g32 : nullptr;
+  float* n32 = pl.precision == WS_FP32 && !pl.cplx ? pl.gnyq32 : nullptr;
+  double* n64 = pl.cplx ? nullptr : pl.gnyq64;
+  constexpr int CB = Layout<double>::CB;
+  switch (K.family) {
+    case WS_LOG:
+      k_table<WS_LOG, CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, g32, n64, n32);
+      break;
+    case WS_POWER:
+      k_table<WS_POWER, CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, g32, n64, n32);
+      break;
+    case WS_YUKAWA:
+      k_table<WS_YUKAWA, CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, g32, n64, n32);
+      break;
+    case WS_HELMHOLTZ:
+      k_table<WS_HELMHOLTZ, CB><<<blocks, threads, 0, s>>>(nb, ncols, K, inv, cp, (double*)pl.g64, g32, n64,
+                                                            n32);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -60,6 +60,9 @@ namespace ws {
 #ifndef WS_SPLIT64
 #define WS_SPLIT64 1
 #endif
+// 1: a column tile walks its column through every density of the launch
+// (moments loaded once per column, the next density's data loaded during the
+// current one's transforms); 0: one tile per (density, column).
 // Elements per thread of the forward real row pass (default: that of the inverse, ER).
 #ifndef WS_ERF64
 #define WS_ERF64 WS_ER64
@@ -155,11 +158,13 @@ hipError_t launch_apply_real(const Plan& p, int batch, const T* u, T* out, cx<T>
 template <typename T>
 hipError_t launch_fs_real(const Plan& p, const T* u_tilde, T* out, cx<T>* work, const ws_fs_desc& fs,
                           hipStream_t s);
-// Complex path (WS_HELMHOLTZ): out = [add_input ? v : 0] + alpha * A_n(m .* v), m optional.
+// Complex path (WS_HELMHOLTZ): out = [add_input ? v : 0] + alpha * A_n(m .* v), m optional
+// (density b multiplies by m + b * mstride: one contrast per density, or mstride = 0 for one shared).
 // skip: optional device flag; when it reads nonzero the kernels return at entry.
 template <typename T>
 hipError_t launch_apply_cplx(const Plan& p, int batch, const cx<T>* v, const T* m, T alpha, bool add_input,
-                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr, int chunk = 0);
+                             cx<T>* out, cx<T>* work, hipStream_t s, const int* skip = nullptr, int chunk = 0,
+                             size_t mstride = 0);
 
 // Single passes of the apply (pass 0: rows forward, 1: columns, 2: rows inverse).
 template <typename T>

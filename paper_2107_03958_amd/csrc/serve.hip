@@ -126,6 +126,12 @@ int describe(const ws_serve_config& cfg, const ws_request* r, ws::Pending* p) {
     stub.cplx = true;
     stub.precision = cfg.precision;
     q.scratch_each = align256(ws::ls_work_bytes(stub, r->restart, cfg.precision == WS_FP32));
+    q.ls_tol = r->tol;
+    q.ls_restart = r->restart;
+    q.ls_maxmv = r->max_matvecs;
+    const int kmax = std::min(cfg.max_batch, ws::kMaxLsBatch);
+    for (int k = 1; k <= kmax && kmax > 1; ++k)
+      q.ls_scratch.push_back(align256(ws::ls_work_bytes(stub, r->restart, cfg.precision == WS_FP32, k)));
   }
   *p = q;
   return WS_OK;
@@ -216,28 +222,37 @@ int run_job(Engine* E, const ws::Grant& g, const std::vector<ws_request>& rq, co
     status->assign(B, WS_OK);
     return WS_OK;
   }
+  // LS solves (one, or a batch with one plan and one setting): contrasts,
+  // incident fields and solutions each stacked [B][n][n], then the scratch.
   const ws_plan_t plan = plans[0];
+  const int B = (int)rq.size();
   const int n = r0.n;
   const size_t nn = (size_t)n * n;
-  const ws_request& r = r0;
   char* m = buf;
-  char* uinc = m + align256(nn * 8);
-  char* uout = uinc + align256(nn * 16);
-  char* scratch = uout + align256(nn * 16);
-  e = hipMemcpyAsync(m, r.contrast, nn * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(uinc, r.input, nn * 16, hipMemcpyHostToDevice, s);
+  char* uinc = m + align256(B * nn * 8);
+  char* uout = uinc + align256(B * nn * 16);
+  char* scratch = uout + align256(B * nn * 16);
+  for (int i = 0; i < B && e == hipSuccess; ++i) {
+    e = hipMemcpyAsync(m + i * nn * 8, rq[i].contrast, nn * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(uinc + i * nn * 16, rq[i].input, nn * 16, hipMemcpyHostToDevice, s);
+  }
   if (e != hipSuccess) return hip_err("serve: copy in");
-  ws_ls_info info{};
-  const int rc = ls_solve(plan, m, uinc, r.tol, r.restart, r.max_matvecs, fp32 ? 1 : 0, uout, scratch, &info, s);
+  std::vector<ws_ls_info> info(B);
+  const int rc = B == 1 ? ls_solve(plan, m, uinc, r0.tol, r0.restart, r0.max_matvecs, fp32 ? 1 : 0, uout, scratch,
+                                   info.data(), s)
+                        : ls_solve_batch(plan, B, m, uinc, r0.tol, r0.restart, r0.max_matvecs, fp32 ? 1 : 0, uout,
+                                         scratch, info.data(), s);
   if (rc < 0) {
     *err = conv_last_error();
     return rc;
   }
-  e = hipMemcpyAsync(r.output, uout, nn * 16, hipMemcpyDeviceToHost, s);
+  for (int i = 0; i < B && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(rq[i].output, uout + i * nn * 16, nn * 16, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err("serve: LS copy out");
-  ls->assign(1, info);
-  status->assign(1, rc);
+  *ls = info;
+  status->resize(B);
+  for (int i = 0; i < B; ++i) (*status)[i] = info[i].status;
   return WS_OK;
 }
 

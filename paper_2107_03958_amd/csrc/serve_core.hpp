@@ -106,6 +106,15 @@ struct Pending {
   int skipped = 0;           // times a younger request was admitted ahead of it
   int batch_class = 0;       // applies of one class may share a launch across plans
   double t_submit = 0;
+  // LS: solves with the same plan and the same (tol, restart, max_matvecs) may run as one
+  // batch; ls_scratch[k - 1] is the solver scratch of a batch of k (empty: no batching).
+  double ls_tol = 0;
+  int ls_restart = 0, ls_maxmv = 0;
+  std::vector<size_t> ls_scratch;
+  bool ls_joins(const Pending& o) const {
+    return kind == 1 && o.kind == 1 && key == o.key && ls_tol == o.ls_tol && ls_restart == o.ls_restart &&
+           ls_maxmv == o.ls_maxmv;
+  }
 };
 
 struct PlanSlot {
@@ -131,7 +140,10 @@ struct Grant {
 // are considered oldest first; an apply takes along up to max_batch - 1 younger
 // pending applies with the same plan (continuous batching: work that arrives
 // while the device is busy joins the next launch) and, with mix_plans, also
-// applies of the same class whose plans are built (one multi-plan launch).  A job is admitted only if
+// applies of the same class whose plans are built (one multi-plan launch); an
+// LS solve takes along younger solves with the same plan and settings, up to
+// max_batch and the batch sizes its ls_scratch describes (one batched
+// solve).  A job is admitted only if
 // its plan (unless cached) and its buffers fit in the arena, after evicting
 // idle cached plans least recently used first; otherwise younger requests may
 // go ahead, but only max_skips times in a row past the oldest one.  A request
@@ -162,6 +174,11 @@ class Admission {
       auto ps = plans_.find(c.key);
       if (ps != plans_.end() && !ps->second.ready) continue;        // being built by another job
       std::vector<size_t> group{i};
+      if (c.kind == 1) {
+        const size_t cap = std::min<size_t>((size_t)max_batch_, c.ls_scratch.size());
+        for (size_t j = i + 1; j < pending_.size() && group.size() < cap; ++j)
+          if (c.ls_joins(pending_[j])) group.push_back(j);
+      }
       if (c.kind == 0) {
         const bool c_ready = ps != plans_.end() && ps->second.ready;
         for (size_t j = i + 1; j < pending_.size() && (int)group.size() < max_batch_; ++j) {
@@ -256,7 +273,7 @@ class Admission {
       for (size_t k = 0; k < keys.size(); ++k)
         scratch += std::min<size_t>(count[k], (size_t)std::max(1, first[k]->chunk)) * first[k]->scratch_each;
     } else {
-      scratch = c.scratch_each;
+      scratch = group.size() > 1 ? c.ls_scratch[group.size() - 1] : c.scratch_each;
     }
     const size_t buf = own + scratch;
     std::vector<void*> evicted;

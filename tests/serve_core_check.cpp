@@ -226,12 +226,46 @@ static void mixed_plans() {
   CHECK(adm.arena().used() == 0);
 }
 
+// LS solves with one plan and one setting join a batch (up to max_batch and
+// the batch sizes their scratch table covers); a different tol or plan does
+// not; the batch's scratch is the table's entry for its size.
+static void ls_batches() {
+  Admission adm((size_t)1 << 32, 4, 8, 4);
+  auto ls = [](uint64_t t, int n, double tol) {
+    Pending p = ls_req(t, n, 1000);
+    p.ls_tol = tol;
+    p.ls_restart = 50;
+    p.ls_maxmv = 100;
+    for (int k = 1; k <= 8; ++k) p.ls_scratch.push_back(1000 + 700 * (size_t)(k - 1));
+    return p;
+  };
+  adm.push(ls(0, 64, 1e-8));
+  adm.push(apply_req(1, 64));
+  adm.push(ls(2, 64, 1e-8));
+  adm.push(ls(3, 64, 1e-6));                 // other tolerance
+  adm.push(ls(4, 128, 1e-8));                // other plan
+  for (int i = 5; i < 9; ++i) adm.push(ls(i, 64, 1e-8));
+  Grant g;
+  CHECK(adm.next(&g));
+  CHECK(g.reqs.size() == 4);                 // max_batch = 4
+  CHECK(g.reqs[0].ticket == 0 && g.reqs[1].ticket == 2 && g.reqs[2].ticket == 5 && g.reqs[3].ticket == 6);
+  CHECK(g.buf_bytes == 4 * g.reqs[0].own_bytes + (1000 + 700 * 3));
+  adm.finish(g);
+  // without a scratch table an LS solve runs alone
+  Admission one((size_t)1 << 32, 4, 8, 4);
+  one.push(ls_req(10, 64, 1000));
+  one.push(ls_req(11, 64, 1000));
+  Grant g1;
+  CHECK(one.next(&g1) && g1.reqs.size() == 1);
+}
+
 int main() {
   for (unsigned s = 1; s <= 5; ++s) arena_random(s);
   batching();
   admission();
   batch_shrinks();
   mixed_plans();
+  ls_batches();
   std::printf("serve_core checks passed\n");
   return 0;
 }

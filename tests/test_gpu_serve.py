@@ -188,3 +188,25 @@ def test_mixed_plan_launches(serve, precision):
     # launches joined several requests (how many depends on how fast the
     # workers drain the queue, so only "more than one" is certain)
     assert max(info["batch"] for _, info in got) > 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ls_requests_batch(serve, precision):
+    # LS solves with one plan and one setting that wait together run as one batched
+    # solve (ls_solve_batch); each result equals the same request served alone.
+    n, kappa, count = 64, 20.0, 7
+    rng = np.random.default_rng(5)
+    reqs = [("ls", "helm20", n, rng.uniform(0.2, 0.8) * synth.cutoff(n),
+             synth.plane_wave(n, kappa, rng.uniform(0, 2 * np.pi)), kappa) for _ in range(count)]
+    print(f"serve LS batch {precision} n={n} count={count}", flush=True)
+    eng = serve.Engine(precision, streams=1, max_batch=8, arena_bytes=1 << 30)
+    got = _run(eng, reqs, together=True)
+    st = eng.stats()
+    eng.close()
+    alone_eng = serve.Engine(precision, streams=1, max_batch=1, arena_bytes=1 << 30)
+    alone = _run(alone_eng, reqs, together=False)
+    alone_eng.close()
+    assert max(info["batch"] for _, info in got) > 1 and st["launches"] < count
+    for (a, ia), (b, ib) in zip(got, alone):
+        assert ia["status"] == 0 and ib["status"] == 0
+        assert np.array_equal(a, b)
