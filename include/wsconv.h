@@ -173,6 +173,24 @@ double conv_plan_radius(ws_plan_t plan);
 int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* work,
                const ws_fs_desc* fs, void* stream);
 
+/* conv_apply for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operation, arguments and results as conv_apply, without the
+ * `work` argument: the intermediate lives in a fixed 64 MiB device array of
+ * the library (one per device, held from the first call on that device until
+ * the process ends), so a plan qualifies when its work_bytes_per_density is
+ * at most 64 MiB (every real-kernel plan up to n = 2048 in FP64; Helmholtz
+ * plans up to n = 1024 in FP64, 2048 in FP32); larger ones return
+ * WS_EUNSUPPORTED.  Densities go through the passes
+ * min(conv_apply_chunk(plan), 64 MiB / work_bytes_per_density) at a time, with
+ * results bitwise equal to conv_apply's.  The call allocates nothing; its
+ * first call on a device resolves the array's device address once.  Every
+ * call on a device shares the one array: calls that overlap in time on one
+ * device (other streams, other host threads) race and must be serialised by
+ * the caller. */
+int conv_apply_noalloc(ws_plan_t plan, int batch, const void* density, void* out, const ws_fs_desc* fs,
+                       void* stream);
+
 /* One of the three passes of conv_apply without Fourier smoothing, for callers
  * that time or interleave them: pass 0 = row transforms of the density into
  * `work`, pass 1 = column transforms with the multiply by ghat (in `work`),

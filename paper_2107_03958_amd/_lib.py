@@ -74,6 +74,7 @@ EXPORTS = {
     "conv_plan_radius": (c_double, [c_void_p]),
     "conv_apply": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, POINTER(WsFsDesc), c_void_p]),
     "conv_apply_chunk": (c_int, [c_void_p]),
+    "conv_apply_noalloc": (c_int, [c_void_p, c_int, c_void_p, c_void_p, POINTER(WsFsDesc), c_void_p]),
     "conv_apply_multi": (c_int, [c_int, POINTER(c_void_p), POINTER(c_int), POINTER(c_void_p), POINTER(c_void_p),
                                  POINTER(c_void_p), c_void_p]),
     "conv_apply_pass": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),

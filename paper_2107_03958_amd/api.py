@@ -149,6 +149,32 @@ class ConvPlan:
                                         fs_arr, _stream_ptr(stream)))
         return out[0] if squeeze else out
 
+    def apply_noalloc(self, density: torch.Tensor, out: torch.Tensor | None = None, fs=None,
+                      stream=None) -> torch.Tensor:
+        """conv_apply_noalloc: as apply, with the intermediate in the library's fixed device array
+        (no workspace; allocates nothing beyond `out` when out is None)."""
+        squeeze = density.dim() == 2
+        u = density.unsqueeze(0) if squeeze else density
+        if u.dtype != self.dtype or u.device != self.device or not u.is_contiguous():
+            raise ValueError(f"density must be a contiguous {self.dtype} tensor on {self.device}")
+        if u.shape[-2:] != (self.n, self.n):
+            raise ValueError(f"density must have trailing shape ({self.n}, {self.n})")
+        batch = u.shape[0]
+        if out is None:
+            out = torch.empty_like(u)
+        elif squeeze:
+            out = out.unsqueeze(0)
+        fs_arr = None
+        if fs is not None:
+            if len(fs) != batch:
+                raise ValueError("one smoothing descriptor per density")
+            fs_arr = (L.WsFsDesc * batch)(*[(f.to_c() if f is not None else L.WsFsDesc(0, 0, 0, 0, 0, 0))
+                                            for f in fs])
+        with torch.cuda.device(self.device):
+            L.check(self.lib.conv_apply_noalloc(self.handle, batch, _dev_ptr(u), _dev_ptr(out), fs_arr,
+                                                _stream_ptr(stream)))
+        return out[0] if squeeze else out
+
     def apply_pass(self, pass_index: int, density: torch.Tensor, out: torch.Tensor, work: torch.Tensor,
                    stream=None) -> None:
         """Enqueue one pass of the apply (conv_apply_pass); no argument copies, no checks beyond the C side."""

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -322,6 +323,37 @@ int apply_checked(ws_plan_t plan, int batch, const void* density, void* out, voi
   return WS_OK;
 }
 
+// Fixed device scratch of conv_apply_noalloc: one array per device, resolved to
+// its device address once per device with hipGetSymbolAddress (the array's
+// name in host code is only a host-side stand-in).  Every call on a device
+// shares it and it keeps the last call's contents; the apply writes the whole
+// intermediate before reading it, so nothing needs clearing.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "conv_apply_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(WS_EUNSUPPORTED, "conv_apply_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "conv_apply_noalloc: hipGetSymbolAddress");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256) return fail(WS_EDEVICE, "conv_apply_noalloc: bad scratch address");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return WS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -330,6 +362,25 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
                void* stream) {
   g_err.clear();
   return apply_checked(plan, batch, density, out, work, fs, stream, 0);
+}
+
+int conv_apply_noalloc(ws_plan_t plan, int batch, const void* density, void* out, const ws_fs_desc* fs,
+                       void* stream) {
+  g_err.clear();
+  if (!plan) return fail(WS_EINVAL, "plan is NULL");
+  if (batch < 0) return fail(WS_EINVAL, "batch must be >= 0");
+  if (batch == 0) return WS_OK;
+  const size_t per = plan->work_bytes;
+  if (per > kNoAllocScratchBytes)
+    return fail(WS_EUNSUPPORTED, "conv_apply_noalloc: this plan needs " + std::to_string(per) +
+                                     " bytes of scratch per density, above the fixed " +
+                                     std::to_string(kNoAllocScratchBytes) + " (use conv_apply)");
+  void* work = nullptr;
+  int rc = scratch_of_current_device(&work);
+  if (rc) return rc;
+  const int fit = (int)std::min<size_t>(kNoAllocScratchBytes / per, 65535);
+  const int chunk = std::min(ws::apply_chunk(*plan), fit);
+  return apply_checked(plan, batch, density, out, work, fs, stream, chunk);
 }
 
 int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, void* out, void* work,
