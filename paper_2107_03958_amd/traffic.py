@@ -145,6 +145,38 @@ def summarise(fetch_dir: str, write_dir: str, out: str) -> dict:
     return res
 
 
+# Pass of each apply-kernel kind (the second template argument of ws::k_pass1).
+PASS_OF_KIND = {"0": "forward row pass (k_rows_fwd_real)", "1": "column pass (k_cols)",
+                "3": "inverse row pass (k_rows_inv_real)"}
+
+
+def stats_summary(stats_csv: str, out_md: str, title: str, command: str, pattern: str = "") -> list:
+    """Markdown table of the ws:: kernels whose name matches the regular expression `pattern`
+    (all of them when empty) in a rocprofv3 kernel_stats.csv, sorted by total time; returns the rows."""
+    import re
+    rows = []
+    for r in csv.DictReader(open(stats_csv)):
+        name = r["Name"].split("(")[0].replace("void ", "")
+        if not name.startswith("ws::") or (pattern and not re.search(pattern, name)):
+            continue
+        kind = ""
+        if name.startswith("ws::k_pass1<"):
+            kind = PASS_OF_KIND.get(name.split(",")[1].strip(), "")
+        rows.append(dict(name=name, kind=kind, calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
+                         min_us=float(r["MinNs"]) / 1e3, max_us=float(r["MaxNs"]) / 1e3,
+                         share=float(r["Percentage"])))
+    rows.sort(key=lambda x: -x["share"])
+    lines = [f"# {title}", "", "Command ($R: the repository root; $OUT: an output folder):", "", "```",
+             "cd /tmp && export TMPDIR=/tmp", command, "```", "",
+             "| kernel | pass | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|---|"]
+    for x in rows:
+        lines.append(f"| `{x['name']}` | {x['kind']} | {x['calls']} | {x['avg_us']:.1f} | {x['min_us']:.1f} | "
+                     f"{x['max_us']:.1f} | {x['share']:.1f}% |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return rows
+
+
 def load_for_current_sources(path: str):
     """The stored traffic summary if it was taken with the current kernel sources, else None."""
     try:
@@ -164,6 +196,8 @@ if __name__ == "__main__":
         ap.add_argument("--b", type=int, default=2)
         a = ap.parse_args(sys.argv[2:])
         target(a.precision, a.n, a.b)
+    elif len(sys.argv) in (6, 7) and sys.argv[1] == "stats":
+        stats_summary(*sys.argv[2:])
     elif len(sys.argv) == 5 and sys.argv[1] == "summarise":
         print(json.dumps(summarise(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     else:

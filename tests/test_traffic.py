@@ -48,3 +48,21 @@ def test_summary_gated_by_source_hash(tmp_path):
         json.dump({"source_hash": "0" * 16, "kernels": {}}, fh)
     assert traffic.load_for_current_sources(path) is None
     assert traffic.load_for_current_sources(str(tmp_path / "missing.json")) is None
+
+
+def test_stats_summary_filters_and_sorts(tmp_path):
+    path = str(tmp_path / "k_kernel_stats.csv")
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"])
+        w.writerow(["void ws::k_pass1<double, 1, 11, 2>(void const*)", 10, 1000, 100.0, 50.0, 90.0, 110.0, 1])
+        w.writerow(["void ws::k_pass1<double, 0, 11, 2>(void const*)", 10, 600, 60.0, 30.0, 50.0, 70.0, 1])
+        w.writerow(["void ws::k_pass1<float, 1, 11, 2>(void const*)", 5, 300, 60.0, 15.0, 60.0, 60.0, 1])
+        w.writerow(["__amd_rocclr_copyBuffer", 4, 100, 25.0, 5.0, 25.0, 25.0, 1])
+    out = str(tmp_path / "s.md")
+    rows = traffic.stats_summary(path, out, "title", "rocprofv3 cmd", r"k_pass1<double")
+    assert [r["name"] for r in rows] == ["ws::k_pass1<double, 1, 11, 2>", "ws::k_pass1<double, 0, 11, 2>"]
+    assert rows[0]["kind"].startswith("column pass") and rows[0]["avg_us"] == 0.1
+    text = open(out).read()
+    assert "rocprofv3 cmd" in text and "float" not in text
+    assert len(traffic.stats_summary(path, out, "t", "c")) == 3          # every ws:: kernel, not the copy
