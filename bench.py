@@ -285,10 +285,33 @@ def run_ls_bench(api, torch, ns, kappas, repeats):
                                rel_residual=info.rel_residual, status=info.status))
             log(f"ls n={n} kappa={kappa} fp64+fs (disc, m=-1): {dt * 1e3:.2f} ms, matvecs={info.matvecs}, "
                 f"rel_res={info.rel_residual:.2e}, status={info.status}")
+    # The smoothed disc at the largest kappa stalls GMRES(50) restarts (a strongly resonant scatterer);
+    # the same solve with a longer restart, for comparison (not part of the p50/p99 above).
+    restart_cmp = []
+    if 80.0 in kappas and 512 in ns:
+        n, kappa = 512, 80.0
+        mt = torch.full((n, n), -1.0, dtype=torch.float64, device="cuda")
+        ui = torch.as_tensor(synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + int(kappa)))).cuda()
+        fs = api.FsDesc("disc", 0.5, 0.5, 0.25, 0.25, 0.39)
+        plan = api.ConvPlan("helmholtz", n=n, kappa=kappa)
+        for rs in (50, 200):
+            work = plan.ls_workspace(rs, False, fs)
+            out = torch.empty_like(ui)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = plan.ls_solve(mt, ui, tol=1e-8, restart=rs, out=out, work=work, fs=fs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            restart_cmp.append(dict(n=n, kappa=kappa, restart=rs, ms=dt * 1e3, matvecs=info.matvecs,
+                                    rel_residual=info.rel_residual, status=info.status))
+            log(f"ls n={n} kappa={kappa} fp64+fs restart {rs}: {dt * 1e3:.2f} ms, matvecs={info.matvecs}")
+            del work
     out = {}
     for mode, v in lat.items():
         v = np.array(v) * 1e3
         out[mode] = dict(p50_ms=float(np.percentile(v, 50)), p99_ms=float(np.percentile(v, 99)), solves=len(v))
+    if restart_cmp:
+        out["fs_restart_comparison"] = restart_cmp
     out["cases"] = detail
     return out
 
@@ -504,6 +527,22 @@ def run_serve_bench(torch, nreq, arena_gb):
         for tk in tks:
             inputs.give_back(eng.wait(tk)[0])
 
+    # Plan misses: the first request of a plan builds it inside its job (moments and twiddles on the
+    # device); latency of that request against the next one of the same plan, on a fresh engine.
+    miss = []
+    eng = serve.Engine("fp64", streams=1, max_batch=1, arena_bytes=arena)
+    for r in ([dict(kind="apply", n=1024, kernel=0, pool=0, kappa=20.0, gap=0.0),
+               dict(kind="apply", n=1024, kernel=1, pool=0, kappa=20.0, gap=0.0),
+               dict(kind="apply", n=1024, kernel=2, pool=0, kappa=20.0, gap=0.0)]):
+        lat = []
+        for _ in range(2):
+            out, info = eng.wait(inputs.submit(eng, r))
+            inputs.give_back(out)
+            lat.append((info["t_done"] - info["t_submit"]) * 1e3)
+        miss.append(dict(kind=r["kind"], n=r["n"], kernel=SERVE_APPLY_KERNELS[r["kernel"]][0], cold_ms=lat[0],
+                         warm_ms=lat[1], plan_build_ms=lat[0] - lat[1]))
+        log(f"serve plan miss {miss[-1]}")
+    eng.close()
     # Calibrate the rate: mean service time of the FP64 one-at-a-time engine, back to back.
     cal = serve.Engine("fp64", streams=1, max_batch=1, arena_bytes=arena)
     warm(cal)
@@ -520,7 +559,7 @@ def run_serve_bench(torch, nreq, arena_gb):
     res = dict(trace=dict(requests=nreq, seed="SEED_TRACE", apply_fraction=0.7, ns=SERVE_NS,
                           apply_kernels=[k for k, _ in SERVE_APPLY_KERNELS], ls_kappas=SERVE_LS_KAPPAS,
                           ls_tol=1e-8, ls_restart=50, input_pool=SERVE_POOL),
-               calibration_service_ms=svc * 1e3, lambda_per_s=lam)
+               calibration_service_ms=svc * 1e3, lambda_per_s=lam, plan_miss=miss)
     outs = {}
     for name, prec, streams, mb in (("fp64_one_at_a_time", "fp64", 1, 1), ("fp32_batched", "fp32", 4, 16)):
         eng = serve.Engine(prec, streams=streams, max_batch=mb, arena_bytes=arena, mix_plans=mb > 1)
@@ -629,7 +668,7 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     dst = torch.empty_like(src)
     acc = torch.empty((), dtype=torch.float64, device="cuda")
     ops = {"copy_": (lambda: dst.copy_(src), 2), "mul_out": (lambda: torch.mul(src, 1.0, out=dst), 2),
-           "sum_read_only": (lambda: torch.sum(src, out=acc), 1)}
+           "sum_read_only": (lambda: torch.sum(src, dim=0, out=acc), 1)}
     res = {}
     for name, (fn, passes) in ops.items():
         for _ in range(3):
