@@ -88,8 +88,9 @@ def cmd_build(args):
         print(f"{r['name']:28s} {'ok' if r['built'] else 'FAILED'}", flush=True)
 
 
-def time_one(lib: str, n: int, precision: str, reps: int) -> dict:
-    """Runs in a fresh process: load `lib`, time the three passes of one chunk (HIP events)."""
+def time_one(lib: str, n: int, precision: str, reps: int, b: int = 2) -> dict:
+    """Runs in a fresh process: load `lib`, time the three passes of one chunk (HIP events) of the
+    log|x| plan at size n and period b."""
     import ctypes
 
     import numpy as np
@@ -102,7 +103,7 @@ def time_one(lib: str, n: int, precision: str, reps: int) -> dict:
             del _lib.EXPORTS[name]
     _lib.load(lib)
     from . import api
-    plan = api.ConvPlan("log", n=n, precision=precision)
+    plan = api.ConvPlan("log", n=n, b=b, precision=precision)
     b = plan.chunk
     g = torch.Generator().manual_seed(0)
     u = torch.randn((b, n, n), dtype=torch.float64, generator=g).to(plan.dtype).cuda()
@@ -207,7 +208,8 @@ def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "_time":
         lib, n, prec, reps = argv[1], int(argv[2]), argv[3], int(argv[4])
-        print(json.dumps(time_one(lib, n, prec, reps)), flush=True)
+        period = int(argv[5]) if len(argv) > 5 else 2
+        print(json.dumps(time_one(lib, n, prec, reps, period)), flush=True)
         return 0
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)

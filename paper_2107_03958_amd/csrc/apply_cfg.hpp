@@ -59,6 +59,13 @@ struct Cfg {
   // their moments after the forward transform to fit: split tiles, and FP64
   // period-3 tiles, whose three lines already fit three blocks' LDS.
   static constexpr bool THREE_C = SPLIT_C || (sizeof(T) == 8 && B == 3 && LDS_C * 16 * 3 <= 163840);
+  // Real-path period-2 column tiles whose threads hold both lines (NT_CD
+  // threads, the same LDS), where the LDS still admits at least two waves per
+  // SIMD of them (n = 2048): the data is loaded once per thread, the stage
+  // twiddles serve both lines, and the lines combine in registers.
+  static constexpr int NT_CD = CPB * PF;
+  static constexpr bool DUAL_C =
+      WS_DUAL_COLS && B == 2 && TwOf<T>::type::kPowers && (163840 / (LDS_C * (int)sizeof(cx<T>))) * NT_CD >= 512;
   // Complex row passes: B full-length lines per row, rows per tile limited by LDS.
   template <int ROWS>
   static constexpr bool fits() {
@@ -102,14 +109,18 @@ struct Blk {
     ((m = std::max(m, which == 0 ? std::max((RH / Cfg<T, L + kMinLogn>::NT_RH) * Cfg<T, L + kMinLogn>::LDS_RH,
                                             (RH / Cfg<T, L + kMinLogn>::NT_RHF) * Cfg<T, L + kMinLogn>::LDS_RHF)
                       : which == 1 ? (C / Cfg<T, L + kMinLogn>::NT_C) * Cfg<T, L + kMinLogn>::LDS_C
+                      : which == 3 ? (C / (Cfg<T, L + kMinLogn>::DUAL_C ? Cfg<T, L + kMinLogn>::NT_CD
+                                                                        : Cfg<T, L + kMinLogn>::NT_C)) *
+                                         Cfg<T, L + kMinLogn>::LDS_C
                                    : (RC / Cfg<T, L + kMinLogn>::NT_RC) * Cfg<T, L + kMinLogn>::LDS_RC)), ...);
     return m;
   }
   static constexpr int LDS_RH = max_lds(0, Seq{});
   static constexpr int LDS_C = max_lds(1, Seq{});
   static constexpr int LDS_RC = max_lds(2, Seq{});
+  static constexpr int LDS_CR = max_lds(3, Seq{});          // real-path columns (dual tiles where chosen)
   static_assert(LDS_RH * sizeof(cx<T>) <= 163840 && LDS_C * sizeof(cx<T>) <= 163840 &&
-                LDS_RC * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
+                LDS_RC * sizeof(cx<T>) <= 163840 && LDS_CR * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
   // Waves per SIMD the column kernel reserves registers for: as many blocks
   // per CU as its LDS allows, up to two, or three for split tiles (which
   // load their moments late to fit the registers of three).
@@ -119,6 +130,7 @@ struct Blk {
     return w < 1 ? 1 : w;
   }
   static constexpr int WAVES_C = waves(C, LDS_C * (int)sizeof(cx<T>), false);
+  static constexpr int WAVES_CR = waves(C, LDS_CR * (int)sizeof(cx<T>), false);
 };
 
 // Thread -> (column c, line l, p) of a column tile.  When a wave can hold
@@ -169,14 +181,20 @@ struct KindOf {
   static constexpr bool ROWS_R = K == kRowsFwdReal || K == kRowsInvReal || K == kRowsInvFs;
   static constexpr bool ROWS_C = K == kRowsFwdCplx || K == kRowsFwdCplxMul || K == kRowsInvCplx;
   static constexpr bool CPLX_COLS = K == kColsCplx;
+  static constexpr bool REAL_COLS = K == kColsReal || K == kColsGen;
   // block size, LDS elements and waves of the several-size kernel
   static constexpr int BLK = ROWS_R ? Blk<T>::RH : ROWS_C ? Blk<T>::RC : Blk<T>::C;
-  static constexpr int LDS = ROWS_R ? Blk<T>::LDS_RH : ROWS_C ? Blk<T>::LDS_RC : Blk<T>::LDS_C;
-  static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : Blk<T>::WAVES_C;
+  static constexpr int LDS = ROWS_R ? Blk<T>::LDS_RH : ROWS_C ? Blk<T>::LDS_RC : REAL_COLS ? Blk<T>::LDS_CR : Blk<T>::LDS_C;
+  static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : REAL_COLS ? Blk<T>::WAVES_CR : Blk<T>::WAVES_C;
+  // tiles of this kind hold both lines in every thread (Cfg::DUAL_C)
+  template <int LOGN>
+  static constexpr bool dual() {
+    return REAL_COLS && Cfg<T, LOGN, B>::DUAL_C;
+  }
   template <int LOGN>
   static constexpr int nt() {
     using C = Cfg<T, LOGN, B>;
-    return K == kRowsFwdReal ? C::NT_RHF : ROWS_R ? C::NT_RH : ROWS_C ? C::NT_RC : C::NT_C;
+    return K == kRowsFwdReal ? C::NT_RHF : ROWS_R ? C::NT_RH : ROWS_C ? C::NT_RC : dual<LOGN>() ? C::NT_CD : C::NT_C;
   }
   template <int LOGN>
   static constexpr int lds_tile() {
@@ -212,15 +230,17 @@ struct Single {
   // as the LDS admits (at most 8 waves per SIMD; FP32 row kernels stop at
   // three, 168 VGPRs, since their FP64 twiddle runs do not fit the 128 VGPRs
   // of four without spilling).  Column kernels: at most two blocks per CU
-  // (their butterflies need the registers), or three for Cfg::THREE_C tiles.
-  static constexpr int lds_waves() {
+  // (their butterflies need the registers), or three for Cfg::THREE_C tiles;
+  // dual tiles (Cfg::DUAL_C): as many as the LDS admits (two waves per SIMD).
+  static constexpr int lds_waves(int wmax) {
     const int blocks = 163840 / (LDS * (int)sizeof(cx<T>));
     const int w = blocks * BLOCK / 256;
-    const int wmax = sizeof(T) == 4 && WS_TW32_POWERS ? 3 : 8;
     return w < 1 ? 1 : w > wmax ? wmax : w;
   }
   static constexpr int WAVES = (KindOf<T, K>::ROWS_R || KindOf<T, K>::ROWS_C)
-                                   ? lds_waves()
+                                   ? lds_waves(sizeof(T) == 4 && WS_TW32_POWERS ? 3 : 8)
+                               : KindOf<T, K, B>::template dual<LOGN>()
+                                   ? lds_waves(8)
                                    : Blk<T>::waves(BLOCK, LDS * (int)sizeof(cx<T>), Cfg<T, LOGN, B>::THREE_C);
   static_assert(BLOCK % NT == 0 && BLOCK <= 1024, "bad block size");
   static_assert(LDS * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");

@@ -62,6 +62,30 @@ __device__ __forceinline__ void prio_loads_end() {
   if constexpr (WS_SETPRIO) __builtin_amdgcn_s_setprio(0);
 }
 
+// Results of the real apply are written once by the inverse row pass and not
+// read again by the library: their stores carry the nontemporal hint
+// (WS_NT_OUT; not those of the smoothing pre-pass, which the apply reads), so
+// they do not displace lines that are (the next chunk's intermediate, the
+// moment table).  At 2048^2 the inverse row pass went from
+// 25.7 to 24.4-24.7 us per density (FP64) and 17.4 to 16.8 (FP32).  The same
+// hint on the forward pass's density loads cost about 1 us per density, and on
+// the inverse pass's intermediate loads 6 (FP64), so those loads keep none.
+#ifndef WS_NT_OUT
+#define WS_NT_OUT 1
+#endif
+template <bool NT, typename T>
+__device__ __forceinline__ void st_hint(cx<T>* p, cx<T> a) {
+  if constexpr (NT) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+  } else {
+    *p = a;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Fourier-smoothing spectrum (Section 2.4): chihat(k) = b^-2 int_Omega e^{-2 pi i k.y/b} dy,
 // with b = 2, for a disc of radius `size` or a square of half-width `size`.
@@ -565,6 +589,182 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
   }
 }
 
+// Register slot that holds position s (element p + P s) in the layout of a
+// stage of radix R: the inverse of slot_elem<E, R>.
+template <int E, int R>
+__device__ __forceinline__ constexpr int slot_of(int s) {
+  return (s % (E / R)) * R + s / (E / R);
+}
+
+// Column tile of the real path at period 2 whose threads hold both lines
+// (Cfg::DUAL_C): thread p loads x_j, j = p + P s, of its column once and
+// transforms line 0 (x) and line 1 (x w_nb^{j}) side by side, so the stage
+// twiddles serve both lines, and after the inverse transforms element i of
+// both lines sits in the same register slot of the same thread: the combine
+// out_i = line_0(i) + w_nb^{-i} line_1(i) needs no exchange.  The steps and
+// their order are those of cols_compute with B = 2 (moments loaded after the
+// forward transform).  GEN: the synthesised spectrum of the smoothing
+// pre-pass instead of the data and moments.
+template <typename T, int LOGN, bool GEN, bool GUARD>
+__device__ __forceinline__ void cols_dual_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
+                                               bool dc_block) {
+  constexpr int B = 2;
+  using C = Cfg<T, LOGN, B>;
+  using LL = LineLayout<C::LF, C::EF>;
+  using TW = typename TwOf<T>::type;
+  static_assert(TW::kPowers, "dual column tiles form their twiddles by products");
+  using W = typename TW::W;
+  constexpr int n = C::n, nb = C::nb, N = C::NCOLS_R, L = C::LF, E = C::EF, P = C::PF, CB = C::CB;
+  constexpr int R0 = FirstLast<L, E>::R0, RL = FirstLast<L, E>::RL, S = LL::STRIDE;
+  constexpr int NB = stage_bases<L, E, 1>();
+  constexpr bool SPLIT = C::SPLIT_C;
+  using LT = std::conditional_t<SPLIT, T, cx<T>>;
+  const ColGeo<T, LOGN, false, B> g(t, tid);     // tid < CPB P: line index 0
+  const int cc = g.cc, p = g.p, cb = g.cb, csub = g.csub, c = g.c;
+  LT* const lbase = reinterpret_cast<LT*>(lds) + (B * cc) * S;
+  LT* line[2] = {lbase, lbase + S};
+  const TW tw = sg.tw;
+  cx<T>* col = g.col(sg.work);
+  const int k2 = cb * CB + c;
+
+  // twiddle loads first: the step w_nb^{P}, the seeds w_nb^{p} of the
+  // pre-twiddle and the combine, the forward stage bases
+  const cx<W> wstep = tw.template get<-1>(P);
+  const cx<W> wpre = tw.template get<-1>(p);
+  const cx<W> wcomb = tw.template get<+1>(p);
+  cx<W> wb[NB > 0 ? NB : 1];
+  load_bases<L, E, -1, 1>(wb, p, tw, B);
+  cx<T> v[2][E];
+  if constexpr (!GEN) {
+#pragma unroll
+    for (int reg = 0; reg < E; ++reg)
+      v[0][reg] = (!GUARD || valid) ? col[(size_t)(p + P * slot_elem<E, R0>(reg)) * CB + c] : cx<T>{0, 0};
+    cx<W> w = wpre;                                  // w_nb^{j}, j = p + P s
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int reg = slot_of<E, R0>(s);
+      v[1][reg] = cmul(v[0][reg], w);
+      if (s + 1 < E) w = cmul(w, wstep);
+    }
+    run_stages<L, E, 2, -1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
+    // v[l][reg] = Y(k1 = 2 q + l), q = p + P slot_elem<E,RL>(reg).  The moments
+    // (folded table) are loaded and applied one line at a time, so at most one
+    // line's moments are held beside both lines' data.
+    const T* gc = static_cast<const T*>(sg.gtab) + (size_t)cb * (N + 1) * CB + c;
+    auto load_g = [&](int l, T (&gl)[E]) {
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) {
+        const int k1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
+        gl[reg] = (!GUARD || valid) ? gc[(size_t)(k1 <= N ? k1 : nb - k1) * CB] : T(0);
+      }
+    };
+    bool done = false;
+    if (dc_block) {
+      // Column 0 packs the real columns k2 = 0 and k2 = N (see cols_compute):
+      // new value (g0+gN)/2 Y(k) + (g0-gN)/2 conj Y(-k), with -k1 = 2 (n - q) - l
+      // in line l at (n - q) mod n (l = 0) or n - 1 - q (l = 1).
+      const bool dc = (!GUARD || valid) && cb == 0 && csub == 0;
+      auto partner = [&](int l, int q) { return l == 0 ? ((n - q) & (n - 1)) : (n - 1 - q); };
+      if constexpr (!SPLIT) {
+        if (dc) {
+#pragma unroll
+          for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int reg = 0; reg < E; ++reg) line[l][LL::pad_ps(p, slot_elem<E, RL>(reg))] = v[l][reg];
+        }
+        __syncthreads();
+        if (dc && c == 0) {
+#pragma unroll
+          for (int l = 0; l < 2; ++l) {
+            T gl[E];
+            load_g(l, gl);
+#pragma unroll
+            for (int reg = 0; reg < E; ++reg) {
+              const int q = p + P * slot_elem<E, RL>(reg);
+              const int k1 = 2 * q + l;
+              const int k1f = k1 <= N ? k1 : nb - k1;
+              const cx<T> ym = cconj(line[l][LL::pad(partner(l, q))]);
+              const T g0 = gl[reg], gN = sg.gnyq[k1f];
+              v[l][reg] = cscale(v[l][reg], (T)0.5 * (g0 + gN)) + cscale(ym, (T)0.5 * (g0 - gN));
+            }
+          }
+          done = true;
+        }
+        __syncthreads();
+      } else {
+        split_parts([&](auto part) {
+          constexpr int PART = decltype(part)::value;
+          if (dc) {
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+#pragma unroll
+              for (int reg = 0; reg < E; ++reg)
+                line[l][LL::pad_ps(p, slot_elem<E, RL>(reg))] = part_of<PART>(v[l][reg]);
+          }
+          __syncthreads();
+          if (dc && c == 0) {
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+              T gl[E];
+              load_g(l, gl);
+#pragma unroll
+              for (int reg = 0; reg < E; ++reg) {
+                const int q = p + P * slot_elem<E, RL>(reg);
+                const int k1 = 2 * q + l;
+                const int k1f = k1 <= N ? k1 : nb - k1;
+                const T yp = line[l][LL::pad(partner(l, q))];
+                const T ym = PART == 0 ? yp : -yp;
+                const T g0 = gl[reg], gN = sg.gnyq[k1f];
+                part_of<PART>(v[l][reg]) = part_of<PART>(v[l][reg]) * ((T)0.5 * (g0 + gN)) + ym * ((T)0.5 * (g0 - gN));
+              }
+            }
+            done = true;
+          }
+          __syncthreads();
+        });
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        T gl[E];
+        load_g(l, gl);
+#pragma unroll
+        for (int reg = 0; reg < E; ++reg) v[l][reg] = cscale(v[l][reg], gl[reg]);
+        asm volatile("" ::: "memory");                // line 1's loads stay after line 0's products
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 2; ++l)
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) {
+        const int b1 = 2 * (p + P * slot_elem<E, RL>(reg)) + l;
+        const int k1 = b1 < n ? b1 : b1 - 2 * n;        // F_n representative
+        cx<double> h = chihat(k1, k2, sg.fs);
+        if (k2 == 0) {
+          const cx<double> hn = chihat(k1, -n, sg.fs);   // column k2 = -nb/2, packed as imaginary part
+          h = {h.x - hn.y, h.y + hn.x};
+        }
+        v[l][reg] = {(T)h.x, (T)h.y};
+      }
+  }
+  relayout<E, RL, R0>(v);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) wb[q] = cconj(wb[q]);
+  run_stages<L, E, 2, +1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
+  if (GUARD && !valid) return;
+  // out_i = line_0(i) + w_nb^{-i} line_1(i), i = p + P s
+  const cx<W> wcstep = cconj(wstep);
+  cx<W> w = wcomb;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int reg = slot_of<E, RL>(s);
+    col[(size_t)(p + P * s) * CB + c] = v[0][reg] + cmul(v[1][reg], w);
+    if (s + 1 < E) w = cmul(w, wcstep);
+  }
+}
+
 template <typename T, typename G, int LOGN, bool CPLX, bool GEN, bool GUARD, int B = 2>
 __device__ __forceinline__ void cols_tile(const Seg<T>& sg, int t, bool valid, int tid, cx<T>* lds,
                                           bool dc_block) {
@@ -749,7 +949,7 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
       const double w1 = fs_window(x1, (double)(2 * m + 1) / n, sg.fs);
       zz = {(T)(zz.x * w0) * ut.x, (T)(zz.y * w1) * ut.y};
     }
-    dst[m] = zz;
+    st_hint<WS_NT_OUT && !FS>(dst + m, zz);
   });
 }
 
@@ -909,9 +1109,13 @@ __device__ __forceinline__ void run_tiles(const Seg<T>& sg, int b, cx<T>* lds) {
     const int first = b * TPB;
     const int last = std::min(first + TPB, sg.ntiles) - 1;
     const bool dc_block = first % NCT == 0 || first / NCT != last / NCT;
-    if constexpr (K == kColsReal)
-      cols_tile<T, T, LOGN, false, false, GUARD, B>(sg, tt, valid, tid, mylds, dc_block);
-    if constexpr (K == kColsGen) cols_tile<T, T, LOGN, false, true, GUARD, B>(sg, tt, valid, tid, mylds, false);
+    if constexpr (KO::template dual<LOGN>()) {
+      cols_dual_tile<T, LOGN, K == kColsGen, GUARD>(sg, tt, valid, tid, mylds, K == kColsReal && dc_block);
+    } else {
+      if constexpr (K == kColsReal)
+        cols_tile<T, T, LOGN, false, false, GUARD, B>(sg, tt, valid, tid, mylds, dc_block);
+      if constexpr (K == kColsGen) cols_tile<T, T, LOGN, false, true, GUARD, B>(sg, tt, valid, tid, mylds, false);
+    }
     if constexpr (K == kColsCplx)
       cols_tile<T, cx<T>, LOGN, true, false, GUARD, B>(sg, tt, valid, tid, mylds, false);
   }

@@ -60,9 +60,12 @@ namespace ws {
 #ifndef WS_SPLIT64
 #define WS_SPLIT64 1
 #endif
-// 1: a column tile walks its column through every density of the launch
-// (moments loaded once per column, the next density's data loaded during the
-// current one's transforms); 0: one tile per (density, column).
+// 1: period-2 real-path column tiles at sizes whose LDS leaves room for two
+// waves per SIMD hold both lines in every thread (Cfg::DUAL_C); 0: one line
+// per thread group.
+#ifndef WS_DUAL_COLS
+#define WS_DUAL_COLS 1
+#endif
 // Elements per thread of the forward real row pass (default: that of the inverse, ER).
 #ifndef WS_ERF64
 #define WS_ERF64 WS_ER64

@@ -57,10 +57,12 @@ void check(int batch) {
   // kRowsRealF: the forward real row pass, with its own elements per thread
   constexpr bool RR = KIND == kRowsReal || KIND == kRowsRealF;
   constexpr bool ROWS = RR || KIND == kRowsCplx;
-  constexpr int NT = KIND == kRowsRealF ? C::NT_RHF : RR ? C::NT_RH : KIND == kRowsCplx ? C::NT_RC : C::NT_C;
+  // real-path column tiles may hold both lines in every thread (Cfg::DUAL_C)
+  constexpr bool DUAL = KIND == kColsRealK && C::DUAL_C;
+  constexpr int NT = KIND == kRowsRealF ? C::NT_RHF : RR ? C::NT_RH : KIND == kRowsCplx ? C::NT_RC : DUAL ? C::NT_CD : C::NT_C;
   constexpr int BLK = RR ? Blk<T>::RH : KIND == kRowsCplx ? Blk<T>::RC : Blk<T>::C;
   constexpr int LDS_TILE = KIND == kRowsRealF ? C::LDS_RHF : RR ? C::LDS_RH : KIND == kRowsCplx ? C::LDS_RC : C::LDS_C;
-  constexpr int LDS_BLK = RR ? Blk<T>::LDS_RH : KIND == kRowsCplx ? Blk<T>::LDS_RC : Blk<T>::LDS_C;
+  constexpr int LDS_BLK = RR ? Blk<T>::LDS_RH : KIND == kRowsCplx ? Blk<T>::LDS_RC : KIND == kColsRealK ? Blk<T>::LDS_CR : Blk<T>::LDS_C;
   constexpr int UNITS = RR ? C::RPB : KIND == kRowsCplx ? C::RPBC : C::CPB;
   constexpr int PER = KIND == kColsCplxK ? 2 * C::n : C::n;
   constexpr int G = RR ? C::RG : KIND == kRowsCplx ? C::RGC : C::CB / C::CPB;
@@ -115,10 +117,10 @@ void check(int batch) {
     for (int tid = 0; tid < NT; ++tid) {
       int c, p, l;
       col_thread<C::CPB, P>(tid, c, p, l);
-      CHECK(c >= 0 && c < C::CPB && p >= 0 && p < P && (l == 0 || l == 1));
+      CHECK(c >= 0 && c < C::CPB && p >= 0 && p < P && (l == 0 || l == 1) && (!DUAL || l == 0));
       seen.insert({c, p, l});
-      // split column tiles: line buffers of T, twice as many per cx<T> of LDS
-      CHECK((2 * c + l) * LL::STRIDE + LL::LEN <= (C::SPLIT_C ? 2 : 1) * LDS_TILE);
+      // split column tiles: line buffers of T, twice as many per cx<T> of LDS; dual tiles use both lines
+      CHECK((2 * c + (DUAL ? 1 : l)) * LL::STRIDE + LL::LEN <= (C::SPLIT_C ? 2 : 1) * LDS_TILE);
       for (int s = 0; s < C::EF; ++s) CHECK(LL::pad_ps(p, s) < LL::LEN);
     }
     CHECK((int)seen.size() == NT);
