@@ -86,6 +86,21 @@ __device__ __forceinline__ void st_hint(cx<T>* p, cx<T> a) {
   }
 }
 
+// for (idx = tid; idx < COUNT; idx += NT) f(idx), fully unrolled: every
+// thread runs COUNT / NT iterations (and a guarded last one when NT does not
+// divide COUNT), so a tile's loads are all issued before the first is waited
+// on.  (Left to the compiler, the period-3 row loops, whose bin -> line map
+// divides by 3, stayed a loop that waited on each load in turn.)
+template <int COUNT, int NT, typename F>
+__device__ __forceinline__ void tile_loop(int tid, F f) {
+  constexpr int IT = (COUNT + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = tid + it * NT;
+    if (COUNT % NT == 0 || idx < COUNT) f(idx);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Fourier-smoothing spectrum (Section 2.4): chihat(k) = b^-2 int_Omega e^{-2 pi i k.y/b} dy,
 // with b = 2, for a disc of radius `size` or a square of half-width `size`.
@@ -896,12 +911,12 @@ __device__ __forceinline__ void rows_inv_real_tile(const Seg<T>& sg, int t, bool
   {
     const cx<T>* src = sg.work + batch * inter_elems<T>(n, N);
     prio_loads_begin();
-    for (int idx = tid; idx < RPB * N; idx += NT) {
+    tile_loop<RPB * N, NT>(tid, [&](int idx) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
       lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
           (!GUARD || valid) ? src[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] : cx<T>{0, 0};
-    }
+    });
     prio_loads_end();
   }
   __syncthreads();
@@ -1014,11 +1029,11 @@ __device__ __forceinline__ void rows_fwd_cplx_tile(const Seg<T>& sg, int t, bool
   __syncthreads();
   if (GUARD && !valid) return;
   cx<T>* dst = sg.work + (size_t)(t / TPD) * inter_elems<T>(n, nb);
-  for (int idx = tid; idx < RPB * nb; idx += NT) {
+  tile_loop<RPB * nb, NT>(tid, [&](int idx) {
     const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
     const int k = cb * CB + c;
     dst[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] = lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))];
-  }
+  });
 }
 
 // Complex path, inverse row pass keeping i2 < n, fused out = [v] + alpha * result.
@@ -1051,12 +1066,12 @@ __device__ __forceinline__ void rows_inv_cplx_tile(const Seg<T>& sg, int t, bool
     const cx<T>* src = sg.work + (size_t)(t / TPD) * inter_elems<T>(n, nb);
     const int row0 = (t % TPD) * RPB;
     prio_loads_begin();
-    for (int idx = tid; idx < RPB * nb; idx += NT) {
+    tile_loop<RPB * nb, NT>(tid, [&](int idx) {
       const int c = idx % CB, rr = (idx / CB) % RPB, cb = idx / (CB * RPB);
       const int k = cb * CB + c;
       lds[(B * rr + line_of<B>(k)) * S + LL::pad(pos_of<B>(k))] =
           (!GUARD || valid) ? src[cb * blk_stride<T>(n) + (size_t)(row0 + rr) * CB + c] : cx<T>{0, 0};
-    }
+    });
     prio_loads_end();
   }
   __syncthreads();
