@@ -1199,7 +1199,10 @@ __global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::W
   pass1_body<T, K, LOGN, 2>(src, dst, work, gtab, gnyq, mcon, tw, ntiles, nblocks, alpha, add, fs, lds, mstride);
 }
 
-// Launches over several segments of any sizes: one block size for all.
+// Launches over several segments of any sizes: one block size for all.  (A
+// persistent form, each block looping over logical blocks, made the compiler
+// keep values across iterations: 700-1100 spilled registers in the column and
+// complex-row kernels.)
 template <typename T, int K>
 __global__ __launch_bounds__((KindOf<T, K>::BLK), (KindOf<T, K>::WAVES)) void k_pass(Segs<T> tab) {
   if (tab.skip && *tab.skip) return;

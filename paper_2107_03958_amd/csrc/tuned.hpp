@@ -3,7 +3,10 @@
 // from the previous shapes, kept when more than 1% faster.  WS_ERF64 (the
 // forward real row pass's own elements per thread) was split from WS_ER64 after
 // a sweep showed ER 16 faster for that pass alone (25.6 / 24.6 against
-// 27.0 / 27.4 us per density at n = 2048, two runs each).
+// 27.0 / 27.4 us per density at n = 2048, two runs each).  WS_ER64 went from
+// 8 to 16 once the row passes issued all of a tile's loads before the first
+// wait: FP64 inverse rows 24.7-24.8 -> 23.8-24.0 us per density at n = 2048
+// (three runs), period-3 inverse rows at n = 1024 12.9 -> 10.0-10.1.
 #pragma once
 #ifndef WS_CB32
 #define WS_CB32 2
@@ -32,7 +35,7 @@
 #define WS_ER32 16
 #endif
 #ifndef WS_ER64
-#define WS_ER64 8
+#define WS_ER64 16
 #endif
 #ifndef WS_ERF64
 #define WS_ERF64 16

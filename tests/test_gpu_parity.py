@@ -212,15 +212,21 @@ def test_fourier_smoothing_apply(api, shape, n):
 
 @pytest.mark.slow
 def test_fourier_smoothing_apply_n2048(api):
-    # the smoothing pre-pass's column tiles at the largest grid (split exchange)
+    # the smoothing pre-pass's column tiles at the largest grid (both lines per
+    # thread; split exchange in FP64), FP64 and FP32, against one oracle result
     n, R = 2048, 0.25
-    plan = api.ConvPlan(n=n, **plan_kwargs("laplace"))
     fs = api.FsDesc("disc", 0.5, 0.5, R, R, 0.39)
     dens = smoothing.smoothed_disc_density(n, B, R, r2=0.39)
-    got = plan.apply(_gpu(np.ones((n, n)), torch.float64).unsqueeze(0), fs=[fs]).cpu().numpy()[0]
     ref = np.real(scheme.apply(dens, oracle_table("laplace", n), B))
     oracle_table.cache_clear()
+    plan = api.ConvPlan(n=n, **plan_kwargs("laplace"))
+    got = plan.apply(_gpu(np.ones((n, n)), torch.float64).unsqueeze(0), fs=[fs]).cpu().numpy()[0]
     assert metrics.rel_linf(got, ref) <= FP64_TOL
+    del plan
+    p32 = api.ConvPlan(n=n, precision="fp32", **plan_kwargs("laplace"))
+    got32 = p32.apply(_gpu(np.ones((n, n)), torch.float32).unsqueeze(0), fs=[fs]).cpu().numpy()[0].astype(np.float64)
+    assert metrics.rel_linf(got32, ref) <= 2e-6
+    assert metrics.rel_l2(got32, ref) <= 5e-7
 
 
 @pytest.mark.parametrize("n", [128, 1024])
