@@ -22,11 +22,12 @@
  * always in FP64 / complex128 whatever the engine precision; page-locked
  * memory lets the copies run asynchronously.  The caller keeps a request's
  * arrays alive and unmodified until serve_wait reports it done.
- * With precision WS_FP32 an apply runs in FP32 (twiddles as hi/lo pairs) and an
- * LS solve runs as FP32 GMRES with FP64 iterative refinement; with WS_FP64
- * both run in FP64.  Each result is the same whether its request ran alone or
- * batched with others: bitwise within one plan's launches, and to rounding
- * (the same arithmetic in another kernel) when mix_plans joins plans.
+ * With precision WS_FP32 an apply runs in FP32 (each twiddle product taken
+ * in FP64 and rounded once) and an LS solve runs as FP32 GMRES with FP64
+ * iterative refinement; with WS_FP64 both run in FP64.  Each result is the
+ * same whether its request ran alone or batched with others: bitwise within
+ * one plan's launches, and to rounding (the same arithmetic in another
+ * kernel) when mix_plans joins plans.
  *
  * Calls that overlap on one engine are safe from several host threads.
  * Return codes are those of wsconv.h; conv_last_error() holds the message.
