@@ -663,8 +663,8 @@ __device__ __forceinline__ void cols_dual_tile(const Seg<T>& sg, int t, bool val
     }
     run_stages<L, E, 2, -1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
     // v[l][reg] = Y(k1 = 2 q + l), q = p + P slot_elem<E,RL>(reg).  The moments
-    // (folded table) are loaded and applied one line at a time, so at most one
-    // line's moments are held beside both lines' data.
+    // (folded table) are loaded and applied one line at a time (holding both
+    // lines' moments beside both lines' data spilled 40 registers).
     const T* gc = static_cast<const T*>(sg.gtab) + (size_t)cb * (N + 1) * CB + c;
     auto load_g = [&](int l, T (&gl)[E]) {
 #pragma unroll
@@ -746,7 +746,6 @@ __device__ __forceinline__ void cols_dual_tile(const Seg<T>& sg, int t, bool val
         load_g(l, gl);
 #pragma unroll
         for (int reg = 0; reg < E; ++reg) v[l][reg] = cscale(v[l][reg], gl[reg]);
-        asm volatile("" ::: "memory");                // line 1's loads stay after line 0's products
       }
     }
   } else {

@@ -177,6 +177,15 @@ template <> struct CMul<double> {
     }
   }
 };
+// FP32 butterfly constants (the powers of w_16 inside the radix-16, -8 and -4
+// butterflies): 0 (default) as single floats, x fl(w); 1 as (hi, lo) pairs
+// rounded from FP64, x w = x hi + x lo.  The table twiddles keep their FP64
+// products (TwDF) either way.  At 2048^2 the single floats took the FP32
+// column pass from 36.5-36.8 to 34.4-35.0 us per density and moved the
+// results by at most 1.5e-7 of their maximum.
+#ifndef WS_CONST32_PAIRS
+#define WS_CONST32_PAIRS 0
+#endif
 template <> struct CMul<float> {
   template <int R, int K, int SGN>
   __device__ __forceinline__ static cx<float> mul(cx<float> x) {
@@ -188,10 +197,14 @@ template <> struct CMul<float> {
     else {
       constexpr double cd = W::c, sd = SGN < 0 ? -W::s : W::s;
       constexpr float ch = (float)cd, sh = (float)sd;
-      constexpr float cl = (float)(cd - (double)ch), sl = (float)(sd - (double)sh);
       cx<float> a = {x.x * ch - x.y * sh, x.x * sh + x.y * ch};
-      cx<float> b = {x.x * cl - x.y * sl, x.x * sl + x.y * cl};
-      return a + b;
+      if constexpr (!WS_CONST32_PAIRS) {
+        return a;
+      } else {
+        constexpr float cl = (float)(cd - (double)ch), sl = (float)(sd - (double)sh);
+        cx<float> b = {x.x * cl - x.y * sl, x.x * sl + x.y * cl};
+        return a + b;
+      }
     }
   }
 };
