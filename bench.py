@@ -6,7 +6,7 @@ times the C-infinity cutoff) on a 2048 x 2048 grid of D, periodic extension
 b = 2 (4096 x 4096 FFT), applied with each of the kernels log|x|, |x|^-1/2 and
 |x|^-1/3: 96 applies per step, inputs resident in HBM, moments precomputed
 in the plans.  The headline value is FP64 applies/s; the same step in FP32
-(FP32 data and butterflies, FP64-accurate twiddles) and the LS solve latencies (GMRES(50), tol 1e-8, FP64 and
+(FP32 data and butterflies, twiddles formed in FP64) and the LS solve latencies (GMRES(50), tol 1e-8, FP64 and
 FP32 + FP64 refinement) are reported beside it, with the roofline of the
 dominant kernel (timed live with HIP events) and the CPU oracle timed on a
 bounded sample on the host.

@@ -53,7 +53,7 @@ extern "C" {
 
 /* Arithmetic of the apply. */
 #define WS_FP64 0
-#define WS_FP32 1        /* FFT passes and spectral multiply in float32; twiddles formed in float64, each product rounded once */
+#define WS_FP32 1        /* FFT passes and spectral multiply in float32; twiddles formed in float64 and rounded once to float32 */
 
 /* Fourier-smoothing shapes (Section 2.4). */
 #define WS_FS_NONE   0

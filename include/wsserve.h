@@ -22,8 +22,8 @@
  * always in FP64 / complex128 whatever the engine precision; page-locked
  * memory lets the copies run asynchronously.  The caller keeps a request's
  * arrays alive and unmodified until serve_wait reports it done.
- * With precision WS_FP32 an apply runs in FP32 (each twiddle product taken
- * in FP64 and rounded once) and an LS solve runs as FP32 GMRES with FP64
+ * With precision WS_FP32 an apply runs in FP32 (twiddles formed in FP64 and
+ * rounded once to FP32) and an LS solve runs as FP32 GMRES with FP64
  * iterative refinement; with WS_FP64 both run in FP64.  Each result is the
  * same whether its request ran alone or batched with others: bitwise within
  * one plan's launches, and to rounding (the same arithmetic in another

@@ -222,8 +222,12 @@ struct KindOf {
 template <typename T, int K, int LOGN, int B = 2>
 struct Single {
   static constexpr int NT = KindOf<T, K, B>::template nt<LOGN>();
-  // the smallest multiple of NT of at least WS_MIN_BLOCK threads
-  static constexpr int BLOCK = NT >= WS_MIN_BLOCK ? NT : NT * ((WS_MIN_BLOCK + NT - 1) / NT);
+  // the smallest multiple of NT of at least WS_MIN_BLOCK threads; with
+  // WS_DUAL_PAIR, dual column tiles take both columns of a block-column
+  static constexpr int BLOCK = KindOf<T, K, B>::template dual<LOGN>() && WS_DUAL_PAIR
+                                   ? (Cfg<T, LOGN, B>::CB / Cfg<T, LOGN, B>::CPB) * NT
+                               : NT >= WS_MIN_BLOCK ? NT
+                                                    : NT * ((WS_MIN_BLOCK + NT - 1) / NT);
   static constexpr int TPB = BLOCK / NT;
   static constexpr int LDS = TPB * KindOf<T, K, B>::template lds_tile<LOGN>();
   // Waves per SIMD the registers are sized for.  Row kernels: as many blocks

@@ -642,11 +642,11 @@ __device__ __forceinline__ void cols_dual_tile(const Seg<T>& sg, int t, bool val
   cx<T>* col = g.col(sg.work);
   const int k2 = cb * CB + c;
 
-  // twiddle loads first: the step w_nb^{P}, the seeds w_nb^{p} of the
-  // pre-twiddle and the combine, the forward stage bases
+  // twiddle loads first: the step w_nb^{P} and seed w_nb^{p} of the
+  // pre-twiddle, the forward stage bases (the combine's run is loaded again
+  // at the end rather than held through the transforms: holding it spilled)
   const cx<W> wstep = tw.template get<-1>(P);
   const cx<W> wpre = tw.template get<-1>(p);
-  const cx<W> wcomb = tw.template get<+1>(p);
   cx<W> wb[NB > 0 ? NB : 1];
   load_bases<L, E, -1, 1>(wb, p, tw, B);
   cx<T> v[2][E];
@@ -769,8 +769,8 @@ __device__ __forceinline__ void cols_dual_tile(const Seg<T>& sg, int t, bool val
   run_stages<L, E, 2, +1, 1>(v, line, p, tw, B, static_cast<const cx<W>*>(wb));
   if (GUARD && !valid) return;
   // out_i = line_0(i) + w_nb^{-i} line_1(i), i = p + P s
-  const cx<W> wcstep = cconj(wstep);
-  cx<W> w = wcomb;
+  const cx<W> wcstep = tw.template get<+1>(P);
+  cx<W> w = tw.template get<+1>(p);
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int reg = slot_of<E, RL>(s);

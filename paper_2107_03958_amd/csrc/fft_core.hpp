@@ -12,10 +12,9 @@
 // A thread may drive NL lines at once (all exchanged with one barrier pair).
 //
 // Twiddles come from a table of exp(-2 pi i m / TWN) in FP64.  The FP32 path
-// forms them in FP64 as the FP64 path does and takes each product x w in FP64,
-// rounded once to FP32, so the twiddle itself carries FP64 accuracy (a table
-// of (hi, lo) float pairs rounded from FP64, applied as x hi + x lo, remains
-// as the -DWS_TW32_POWERS=0 build).
+// forms them in FP64 as the FP64 path does and rounds each one once to FP32
+// for an FP32 product (WS_TW32_POWERS; products taken in FP64, and a table of
+// (hi, lo) float pairs applied as x hi + x lo, remain as other builds).
 #pragma once
 #include <type_traits>
 #include <hip/hip_runtime.h>
@@ -95,17 +94,26 @@ __device__ __forceinline__ void tw_run(const TwD& tw, int b, int d, cx<double> (
   run_from<K>(tw.template get<SGN>(b), K > 1 ? tw.template get<SGN>(d) : cx<double>{1, 0}, w);
 }
 
-// 1 (default): FP32 passes use TwDF, each product x w taken in FP64 and
-// rounded once; 2: the FP64 twiddle is split in registers into the FP32 pair
-// (hi, lo) = (fl(w), fl(w - hi)) and applied as x lo + x hi with FP32 FMAs;
-// 0: the (hi, lo) pair table, TwF.
+// FP32 passes (TwDF: FP64 table, bases and powers formed in FP64):
+// 3 (default): each FP64 twiddle rounded once to FP32, x fl(w) in FP32 (a
+// power serves both lines of a dual column tile, so it is rounded once for
+// two products); 1: each product x w taken in FP64 and rounded once; 2: the
+// twiddle split in registers into the FP32 pair (hi, lo) = (fl(w), fl(w - hi))
+// and applied as x lo + x hi with FP32 FMAs; 0: the (hi, lo) pair table, TwF.
+// At 2048^2 the FP32 step went from 62.6-63.6 to 56.5-57.2 us per density
+// with 3 against 1 (columns 34.4-35.0 -> 30.2-30.6), and its error against
+// FP64 over 96 applies from rel Linf 3.46e-7 / rel L2 1.56e-7 to 3.82e-7 /
+// 1.67e-7.
 #ifndef WS_TW32_POWERS
-#define WS_TW32_POWERS 1
+#define WS_TW32_POWERS 3
 #endif
 
 // FP32 data times an FP64 twiddle (see WS_TW32_POWERS).
 __device__ __forceinline__ cx<float> cmul(cx<float> a, cx<double> b) {
-#if WS_TW32_POWERS == 2
+#if WS_TW32_POWERS == 3
+  const float bx = (float)b.x, by = (float)b.y;
+  return {a.x * bx - a.y * by, a.x * by + a.y * bx};
+#elif WS_TW32_POWERS == 2
   const float hx = (float)b.x, hy = (float)b.y;
   const float lx = (float)(b.x - (double)hx), ly = (float)(b.y - (double)hy);
   float rx = a.x * lx, ry = a.x * ly;
@@ -123,9 +131,8 @@ __device__ __forceinline__ cx<float> cmul(cx<float> a, cx<double> b) {
 }
 
 // FP32 data with the FP64 table: bases loaded and powers formed in FP64 as
-// for TwD, each product x w taken in FP64 and rounded once to FP32 (at least
-// as accurate as x hi + x lo with the pair rounded from FP64), with no table
-// load inside a transform.
+// for TwD, each product x w taken as WS_TW32_POWERS sets (by default FP32
+// with the twiddle rounded once), with no table load inside a transform.
 struct TwDF {
   const cx<double>* t;
   static constexpr bool kPowers = true;

@@ -66,6 +66,17 @@ namespace ws {
 #ifndef WS_DUAL_COLS
 #define WS_DUAL_COLS 1
 #endif
+// 1: a block of dual column tiles holds both columns of a block-column, so
+// the two halves of every 32-byte row segment are written together.  Alone,
+// a dual FP64 tile's 16-byte stores leave half lines that the L2 at times
+// writes back before the partner column's tile fills them: 245.6 MB written
+// per 3-density launch at 2048^2 against 201.3 MB algorithmic.  Paired, the
+// writes are 201.8 MB, but the two tiles' barriers run in lockstep: columns
+// 51.7-52.5 us per density against 49.6-50.8, rows 1.8 us faster, the total
+// the same (98.1 against 98.0, three runs each).  Off.
+#ifndef WS_DUAL_PAIR
+#define WS_DUAL_PAIR 0
+#endif
 // Elements per thread of the forward real row pass (default: that of the inverse, ER).
 #ifndef WS_ERF64
 #define WS_ERF64 WS_ER64
