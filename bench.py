@@ -198,6 +198,40 @@ def run_eval_bench(api, torch, n, count, repeats=10):
                               note="whole call (spectrum pass + series sum), series flops only"))
 
 
+def run_paper_timing(api, torch, n=512, b=3, repeats=20):
+    """Context for the paper's one timing result (Section 3.1, Example 1, Figure complexity): a single
+    FP64 apply of log|x| to the Gaussian density (sigma = 0.05) at period b = 3, timed with HIP events,
+    beside the paper's fitted C N log N, C = 1.2e-7 (seconds presumably; N = (b n)^2; the log base and
+    the paper's hardware are unstated, so every base is given).  n = 512 (N = 1536^2) is the
+    power-of-two size nearest the paper's largest, n = 504 (N = 1512^2)."""
+    import math
+
+    import synth
+    plan = api.ConvPlan("log", n=n, b=b)
+    u = torch.as_tensor(synth.gaussian_density(n)).cuda().unsqueeze(0)
+    out = torch.empty_like(u)
+    work = plan.workspace(1)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        plan.apply(u, out=out, work=work)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(repeats):
+        plan.apply(u, out=out, work=work)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / repeats
+    N = (b * n) ** 2
+    fit = {name: 1.2e-7 * N * math.log(N, base) for name, base in (("log10", 10.0), ("ln", math.e), ("log2", 2.0))}
+    return dict(workload=f"one FP64 apply, log|x|, Gaussian density sigma=0.05 about the centre, {n}x{n} grid, "
+                         f"period b={b} (N=({b}*{n})^2={N})",
+                n=n, b=b, N=N, ms_per_apply=ms,
+                paper_fit_s_per_apply=fit,
+                note="the paper fits T = C N log N with C = 1.2e-7 over n = 24l, l = 1..21, on unstated "
+                     "hardware and precision; context only")
+
+
 def ls_step_bytes(n: int, s: int, j: int) -> float:
     """Algorithmic HBM bytes of Arnoldi step j (j + 1 basis vectors before it) at period 2, s bytes per real.
 
@@ -784,6 +818,11 @@ def main(argv=None):
                                         "pass_avg_ms", "pass_gbps", "densities_per_launch", "roofline")})
         log(f"period3: {r3['applies_per_s']:.1f} applies/s, pass model {r3['pass_model_gbps']:.0f} GB/s, "
             f"passes {r3['pass_avg_ms']}")
+    ctx = None
+    if not args.no_period3:
+        log("paper timing context (one period-3 apply, n=512) ...")
+        ctx = run_paper_timing(api, torch)
+        log(f"paper context: {ctx['ms_per_apply']:.3f} ms per apply; paper fit {ctx['paper_fit_s_per_apply']}")
     ev = None
     if not args.no_eval:
         log("off-grid evaluation bench (n=512, 4096 targets) ...")
@@ -840,6 +879,8 @@ def main(argv=None):
                                             "error_vs_fp64", "roofline")}
     if p3 is not None:
         line["period3"] = p3
+    if ctx is not None:
+        line["paper_timing_context"] = ctx
     if ev is not None:
         line["offgrid_eval"] = ev
     if ls is not None:

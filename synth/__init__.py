@@ -56,6 +56,13 @@ def bump_density(n: int) -> np.ndarray:
     return cutoff(n)
 
 
+def gaussian_density(n: int, sigma: float = 0.05) -> np.ndarray:
+    """(1/(2 pi sigma^2)) exp(-|y - c|^2 / (2 sigma^2)) about the centre c of D: the
+    density of the paper's first convergence example (Section 3.1), sigma = 0.05."""
+    r = radius(n)
+    return np.exp(-r * r / (2.0 * sigma * sigma)) / (2.0 * np.pi * sigma * sigma)
+
+
 def smooth_density(n: int, seed: int) -> np.ndarray:
     """Sum of 1..8 Gaussian bumps times the cutoff.
 

@@ -23,3 +23,14 @@ def test_more_than_one_gpu_is_refused(capsys):
     assert bench.main(["--gpus", "2"]) == 2
     out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     assert "one GPU" in out["error"] and out["n_gpus"] == 2
+
+
+def test_paper_timing_density():
+    # the density of the paper's timing example (Section 3.1): a normalised Gaussian, sigma = 0.05,
+    # about the centre of D; its grid sum times h^2 is its mass, 1
+    import synth
+    n = 256
+    u = synth.gaussian_density(n)
+    assert abs(u.sum() / n ** 2 - 1.0) < 1e-12
+    assert u[n // 2, n // 2] == u.max()
+    assert abs(u.max() - 1.0 / (2 * 3.141592653589793 * 0.05 ** 2)) < 1e-9
