@@ -82,9 +82,8 @@ typedef struct {
     int    n;               /* grid points per side on D; power of two, 16 <= n <= 2048 */
     int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1): 2, or 3 for
                                densities supported on all of D (b >= 1 + sqrt 2, Section 2.1).
-                               b = 3 needs WS_FP64 and n <= 1024, and is not taken by
-                               conv_apply_multi, Fourier smoothing or mixed-precision ls_solve
-                               (WS_EUNSUPPORTED) */
+                               b = 3 needs n <= 1024, and is not taken by
+                               conv_apply_multi or Fourier smoothing (WS_EUNSUPPORTED) */
     double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
                                the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the disc window
                                below.  The scheme computes the convolution only when a is at least

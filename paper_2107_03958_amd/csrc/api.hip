@@ -166,7 +166,6 @@ int conv_plan_query(const ws_kernel* kernel, const ws_grid* grid, int precision,
   int logn;
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
-  if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
   if ((rc = check_beta(kernel, grid->n, a))) return rc;
   const Sizes s = sizes_for(grid->n, grid->b, kernel->family == WS_HELMHOLTZ, precision, kernel->beta);
   if (plan_bytes) *plan_bytes = s.total;
@@ -185,7 +184,6 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   int logn;
   if ((rc = check_grid(grid, &a, &logn))) return rc;
   if (precision != WS_FP64 && precision != WS_FP32) return fail(WS_EINVAL, "unknown precision");
-  if (grid->b == 3 && precision != WS_FP64) return fail(WS_EUNSUPPORTED, "period b = 3 needs WS_FP64");
   if ((rc = check_beta(kernel, grid->n, a))) return rc;
   if (!plan_buf) return fail(WS_EINVAL, "plan buffer is NULL");
   if (reinterpret_cast<uintptr_t>(plan_buf) % 256) return fail(WS_EINVAL, "plan buffer must be 256-byte aligned");

@@ -56,9 +56,9 @@ struct Cfg {
                                   B * CPB * SF * 8 * 3 <= 163840;
   static constexpr int LDS_C = SPLIT_C ? (B * CPB * SF + 1) / 2 : B * CPB * SF;   // cx<T> elements
   // Column tiles compiled for three blocks per CU (168 VGPRs), which load
-  // their moments after the forward transform to fit: split tiles, and FP64
+  // their moments after the forward transform to fit: split tiles, and
   // period-3 tiles, whose three lines already fit three blocks' LDS.
-  static constexpr bool THREE_C = SPLIT_C || (sizeof(T) == 8 && B == 3 && LDS_C * 16 * 3 <= 163840);
+  static constexpr bool THREE_C = SPLIT_C || (B == 3 && LDS_C * (int)sizeof(cx<T>) * 3 <= 163840);
   // Real-path period-2 column tiles whose threads hold both lines (NT_CD
   // threads, the same LDS), where the LDS still admits at least two waves per
   // SIMD of them (n = 2048): the data is loaded once per thread, the stage
@@ -85,7 +85,7 @@ struct Cfg {
 };
 
 constexpr int kMinLogn = 4, kMaxLogn = 11;
-// Period b = 3 (nb = 3n): FP64 plans up to n = 1024, single-plan launches.
+// Period b = 3 (nb = 3n): plans up to n = 1024, single-plan launches.
 constexpr int kMaxLognB3 = 10;
 constexpr int kMaxSegs = 8;
 

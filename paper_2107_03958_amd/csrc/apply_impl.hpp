@@ -331,7 +331,7 @@ __device__ __forceinline__ void combine_lines(const cx<T>* base, int S, int p, i
       else emit(i, l0[LL::pad(i)] + tw.template mul<+1>(l1[LL::pad(i)], U * i));
     }
   } else {
-    static_assert(B == 3 && TW::kPowers, "period 3: FP64 only");
+    static_assert(B == 3 && TW::kPowers, "period 3: twiddle runs formed by products");
     const cx<T>* l2 = l1 + S;
     constexpr int TMAX = (E + B - 1) / B;
     cx<W> w[TMAX];                                           // w_nb^{-u i}, i = p + P (l + 3 t)
@@ -1249,11 +1249,11 @@ Geo geo_of() {
   using KO = KindOf<T, K, B>;
   return Geo{KO::template tiles_per_density<LOGN>(), KO::template nt<LOGN>(), Single<T, K, LOGN, B>::BLOCK};
 }
-// Period-3 kernels exist for FP64 plans of n <= 2^kMaxLognB3, without the
-// smoothing pre-pass.
+// Period-3 kernels exist for FP64 and FP32 plans of n <= 2^kMaxLognB3,
+// without the smoothing pre-pass.
 template <typename T, int K>
 constexpr bool has_b3() {
-  return std::is_same_v<T, double> && K != kRowsInvFs && K != kColsGen;
+  return K != kRowsInvFs && K != kColsGen;
 }
 #define WS_FOR_EACH_LOGN_B3(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
 static_assert(kMaxLognB3 == 10, "WS_FOR_EACH_LOGN_B3 lists 4..kMaxLognB3");

@@ -172,7 +172,7 @@ void check_all() {
 // (line, position) map, and the combine's slot split over the B line groups.
 template <typename T, int LOGN, int K>
 void check_single_b3(int batch) {
-  const char* tname = "double/b3";
+  const char* tname = sizeof(T) == 8 ? "double/b3" : "float/b3";
   constexpr int KIND = -100 - K;
   constexpr int B = 3;
   using C = Cfg<T, LOGN, B>;
@@ -241,22 +241,23 @@ void check_single_b3(int batch) {
   }
 }
 
-template <int LOGN>
+template <typename T, int LOGN>
 void check_b3() {
   for (int batch : {1, 2, 3, 7}) {
-    check_single_b3<double, LOGN, ws::kRowsFwdReal>(batch);
-    check_single_b3<double, LOGN, ws::kColsReal>(batch);
-    check_single_b3<double, LOGN, ws::kRowsInvReal>(batch);
-    check_single_b3<double, LOGN, ws::kRowsFwdCplx>(batch);
-    check_single_b3<double, LOGN, ws::kRowsFwdCplxMul>(batch);
-    check_single_b3<double, LOGN, ws::kColsCplx>(batch);
-    check_single_b3<double, LOGN, ws::kRowsInvCplx>(batch);
+    check_single_b3<T, LOGN, ws::kRowsFwdReal>(batch);
+    check_single_b3<T, LOGN, ws::kColsReal>(batch);
+    check_single_b3<T, LOGN, ws::kRowsInvReal>(batch);
+    check_single_b3<T, LOGN, ws::kRowsFwdCplx>(batch);
+    check_single_b3<T, LOGN, ws::kRowsFwdCplxMul>(batch);
+    check_single_b3<T, LOGN, ws::kColsCplx>(batch);
+    check_single_b3<T, LOGN, ws::kRowsInvCplx>(batch);
   }
-  if constexpr (LOGN < kMaxLognB3) check_b3<LOGN + 1>();
+  if constexpr (LOGN < kMaxLognB3) check_b3<T, LOGN + 1>();
 }
 
 int main() {
-  check_b3<kMinLogn>();
+  check_b3<double, kMinLogn>();
+  check_b3<float, kMinLogn>();
   check_all<double, kMinLogn>();
   check_all<float, kMinLogn>();
   std::printf("apply geometry checks passed (block sizes: double %d/%d/%d, float %d/%d/%d)\n", Blk<double>::RH,

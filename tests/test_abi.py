@@ -74,7 +74,6 @@ def test_plan_query_sizes_period3(lib):
     (dict(n=4096), L.WS_EUNSUPPORTED),
     (dict(b=4), L.WS_EUNSUPPORTED),
     (dict(b=3, n=2048), L.WS_EUNSUPPORTED),
-    (dict(b=3, prec=L.WS_FP32), L.WS_EUNSUPPORTED),
     (dict(b=0), L.WS_EINVAL),
     (dict(a=2.5), L.WS_EINVAL),
     (dict(family=L.WS_POWER, gamma=0.5), L.WS_EINVAL),
