@@ -810,7 +810,7 @@ def main(argv=None):
         u3 = torch.as_tensor(np.stack([synth.full_support_density(n3, synth.SEED_FULL_SUPPORT + i)
                                        for i in range(b3)]))
         r3 = run_apply_bench(api, torch, n3, b3, "fp64", args.steps, args.warmup, u3, b=3, kernels=KERNELS[:2])
-        r3.pop("_outs")
+        outs3 = r3.pop("_outs")
         r3["hbm_frac_pass_model"] = r3["pass_model_gbps"] / PEAK_HBM_GBPS
         p3 = dict(workload=f"A_n apply, {n3}x{n3} grid on D, period b=3 ({3 * n3}^2 FFT), {b3} densities "
                            f"supported on all of D x {len(KERNELS[:2])} kernels per step, FP64",
@@ -818,6 +818,15 @@ def main(argv=None):
                                         "pass_avg_ms", "pass_gbps", "densities_per_launch", "roofline")})
         log(f"period3: {r3['applies_per_s']:.1f} applies/s, pass model {r3['pass_model_gbps']:.0f} GB/s, "
             f"passes {r3['pass_avg_ms']}")
+        if not args.no_fp32:
+            r3f = run_apply_bench(api, torch, n3, b3, "fp32", args.steps, args.warmup, u3, b=3,
+                                  kernels=KERNELS[:2])
+            tab3 = error_table(torch, r3f.pop("_outs"), outs3, KERNELS[:2])
+            p3["fp32"] = dict(applies_per_s=r3f["applies_per_s"], ms_per_step=r3f["ms_per_step"],
+                              pass_model_gbps=r3f["pass_model_gbps"], pass_avg_ms=r3f["pass_avg_ms"],
+                              error_vs_fp64=tab3, bound=dict(rel_linf=2e-6, rel_l2=5e-7))
+            log(f"period3 fp32: {r3f['applies_per_s']:.1f} applies/s; errors vs FP64 {tab3}")
+        del outs3
     ctx = None
     if not args.no_period3:
         log("paper timing context (one period-3 apply, n=512) ...")
