@@ -172,6 +172,36 @@ def test_b3_ls_solve_mixed_vs_dense(api, n):
     assert np.linalg.norm(res) / np.linalg.norm(ui) <= 1e-11
 
 
+@functools.lru_cache(maxsize=4)
+def _b3_ls_oracle(n, kappa):
+    x1, x2 = synth.grid(n)
+    m = 0.5 * (16.0 * x1 * (1.0 - x1) * x2 * (1.0 - x2)) ** 3
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + int(kappa)))
+    g = table3(f"helm{int(kappa)}", n)
+    x, info = ols.gmres(m, ui, g, B3, kappa, tol=1e-13, restart=50)
+    assert info["converged"], info
+    return m, ui, g, x
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mixed", [False, True])
+def test_b3_ls_solve_n128(api, mixed):
+    # period 3 at n = 128, kappa = 40, FP64 and FP32 + FP64 refinement: the GPU solution's residual
+    # under the oracle's operator meets the requested 1e-12, and it agrees with the oracle's GMRES
+    # solution (to 1e-13) within 2 cond_2(K) (r_gpu + r_oracle); cond_2(K) of this operator, from the
+    # oracle's dense matrix, is 25.0 / 24.3 at n = 16 / 32, bounded here by 30
+    n, kappa = 128, 40.0
+    m, ui, g, xo = _b3_ls_oracle(n, kappa)
+    plan = api.ConvPlan(n=n, b=B3, precision="fp32" if mixed else "fp64", **plan_kwargs("helm40"))
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-12, restart=50,
+                            mixed=mixed)
+    assert info.status == 0, info
+    got = u.cpu().numpy()
+    res = np.linalg.norm(ui - ols.matvec(got, m, g, B3, kappa)) / np.linalg.norm(ui)
+    assert res <= 1.2e-12, (res, info)
+    assert metrics.rel_linf(got, xo) <= 2 * 30.0 * (res + 1e-13)
+
+
 def test_b3_unsupported_uses(api):
     from paper_2107_03958_amd import _lib as L
     with pytest.raises(L.WsError) as e:
