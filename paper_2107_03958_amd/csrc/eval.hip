@@ -21,8 +21,8 @@ namespace ws {
 namespace {
 
 constexpr int kEvalThreads = 256;
-constexpr int kEvalTargets = 8;          // targets per block: every spectrum read serves this many
-constexpr int kReseed = 32;              // exact exponentials every 32 bins, products in between
+constexpr int kEvalTargets = 16;         // targets per block: every spectrum read serves this many
+constexpr int kE1Rows = 64;              // rows k1 whose exponentials the block shares through LDS at a time
 
 __global__ void k_real_to_cplx(const double* __restrict__ u, cx<double>* __restrict__ v, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -37,49 +37,58 @@ __device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
   return {c, s};
 }
 
-// Block (x, y): kEvalTargets targets x, and the slice y of the columns k2
-// (k2 = y * 256 + t + j * 256 * gridDim.y for thread t): per column, the sum
-// over k1 of c(k1, k2) exp(2 pi i k1 x1/b) (exponentials by products,
-// re-seeded exactly every kReseed bins and at the jump to negative k1), times
+// Block (x, y): kEvalTargets targets, and the slice y of the columns k2
+// (k2 = y * 256 + t + j * 256 * gridDim.y for thread t; every thread runs the
+// same number of column rounds, those past nb with a zero column).  Per
+// column, the sum over k1 of c(k1, k2) exp(2 pi i k1 x1/b), with the row
+// exponentials of every target computed once per block, kE1Rows rows at a
+// time, into LDS (every thread reads the same entries), times
 // exp(2 pi i k2 x2/b); then a block reduction per target into
 // part[y * count + target] (with one slice, straight into the result).
-__global__ __launch_bounds__(kEvalThreads) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
+__global__ __launch_bounds__(kEvalThreads, 2) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
                                                        const double* __restrict__ targets, int count,
                                                        cx<double>* __restrict__ part) {
+  __shared__ cx<double> e1s[kE1Rows][kEvalTargets];
+  __shared__ double xs[2][kEvalTargets];
   __shared__ cx<double> red[kEvalTargets][kEvalThreads / 64];
   const int t0 = blockIdx.x * kEvalTargets;
-  double x1[kEvalTargets], x2[kEvalTargets];
-  cx<double> step[kEvalTargets];
-#pragma unroll
-  for (int g = 0; g < kEvalTargets; ++g) {
-    const int ti = t0 + g < count ? t0 + g : count - 1;
-    x1[g] = targets[2 * (size_t)ti] * inv_b;
-    x2[g] = targets[2 * (size_t)ti + 1] * inv_b;
-    double s, c;
-    sincospi(2.0 * x1[g], &s, &c);
-    step[g] = {c, s};                                 // exp(2 pi i x1 / b): one bin further
+  if (threadIdx.x < kEvalTargets) {
+    const int ti = t0 + (int)threadIdx.x < count ? t0 + (int)threadIdx.x : count - 1;
+    xs[0][threadIdx.x] = targets[2 * (size_t)ti] * inv_b;
+    xs[1][threadIdx.x] = targets[2 * (size_t)ti + 1] * inv_b;
   }
+  __syncthreads();
   cx<double> tot[kEvalTargets];
 #pragma unroll
   for (int g = 0; g < kEvalTargets; ++g) tot[g] = {0.0, 0.0};
-  for (int k2 = blockIdx.y * kEvalThreads + threadIdx.x; k2 < nb; k2 += kEvalThreads * gridDim.y) {
-    cx<double> acc[kEvalTargets], e1[kEvalTargets];
+  const int stride = kEvalThreads * gridDim.y;
+  const int rounds = (nb + stride - 1) / stride;
+  for (int jc = 0; jc < rounds; ++jc) {
+    const int k2 = blockIdx.y * kEvalThreads + threadIdx.x + jc * stride;
+    const bool ok = k2 < nb;
+    cx<double> acc[kEvalTargets];
 #pragma unroll
     for (int g = 0; g < kEvalTargets; ++g) acc[g] = {0.0, 0.0};
-    for (int k1 = 0; k1 < nb; ++k1) {
-      if (k1 % kReseed == 0 || k1 == nb / 2) {
-#pragma unroll
-        for (int g = 0; g < kEvalTargets; ++g) e1[g] = expo(k1, nb, x1[g]);
+    for (int c0 = 0; c0 < nb; c0 += kE1Rows) {
+      const int rows = nb - c0 < kE1Rows ? nb - c0 : kE1Rows;
+      __syncthreads();                                  // the previous rows' reads are done
+      for (int idx = threadIdx.x; idx < rows * kEvalTargets; idx += kEvalThreads) {
+        const int r = idx / kEvalTargets, g = idx % kEvalTargets;
+        e1s[r][g] = expo(c0 + r, nb, xs[0][g]);
       }
-      const cx<double> c = spec[(size_t)k1 * nb + k2];
+      __syncthreads();
+      const cx<double>* col = spec + (size_t)c0 * nb + (ok ? k2 : 0);
+#pragma unroll 2
+      for (int r = 0; r < rows; ++r) {
+        const cx<double> c = ok ? col[(size_t)r * nb] : cx<double>{0.0, 0.0};
 #pragma unroll
-      for (int g = 0; g < kEvalTargets; ++g) {
-        acc[g] = acc[g] + cmul(c, e1[g]);
-        e1[g] = cmul(e1[g], step[g]);
+        for (int g = 0; g < kEvalTargets; ++g) acc[g] = acc[g] + cmul(c, e1s[r][g]);
       }
     }
+    if (ok) {
 #pragma unroll
-    for (int g = 0; g < kEvalTargets; ++g) tot[g] = tot[g] + cmul(acc[g], expo(k2, nb, x2[g]));
+      for (int g = 0; g < kEvalTargets; ++g) tot[g] = tot[g] + cmul(acc[g], expo(k2, nb, xs[1][g]));
+    }
   }
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
