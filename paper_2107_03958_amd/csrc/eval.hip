@@ -23,6 +23,7 @@ namespace {
 constexpr int kEvalThreads = 256;
 constexpr int kEvalTargets = 16;         // targets per block: every spectrum read serves this many
 constexpr int kE1Rows = 64;              // rows k1 whose exponentials the block shares through LDS at a time
+constexpr int kEvalCols = 2;             // columns per thread: every LDS read serves this many
 
 __global__ void k_real_to_cplx(const double* __restrict__ u, cx<double>* __restrict__ v, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -37,17 +38,18 @@ __device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
   return {c, s};
 }
 
-// Block (x, y): kEvalTargets targets, and the slice y of the columns k2
-// (k2 = y * 256 + t + j * 256 * gridDim.y for thread t; every thread runs the
-// same number of column rounds, those past nb with a zero column).  Per
-// column, the sum over k1 of c(k1, k2) exp(2 pi i k1 x1/b), with the row
-// exponentials of every target computed once per block, kE1Rows rows at a
-// time, into LDS (every thread reads the same entries), times
+// Block (x, y): kEvalTargets targets, and the slice y of the columns k2:
+// thread t takes the kEvalCols columns k2 = (y + j gridDim.y) kEvalCols 256 +
+// c 256 + t, c < kEvalCols, in rounds j (every thread runs the same rounds;
+// columns past nb count as zero).  Per column, the sum over k1 of
+// c(k1, k2) exp(2 pi i k1 x1/b), with the row exponentials of every target
+// computed once per block, kE1Rows rows at a time, into LDS (every thread
+// reads the same entries, each read serving kEvalCols columns), times
 // exp(2 pi i k2 x2/b); then a block reduction per target into
 // part[y * count + target] (with one slice, straight into the result).
 __global__ __launch_bounds__(kEvalThreads, 2) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
-                                                       const double* __restrict__ targets, int count,
-                                                       cx<double>* __restrict__ part) {
+                                                          const double* __restrict__ targets, int count,
+                                                          cx<double>* __restrict__ part) {
   __shared__ cx<double> e1s[kE1Rows][kEvalTargets];
   __shared__ double xs[2][kEvalTargets];
   __shared__ cx<double> red[kEvalTargets][kEvalThreads / 64];
@@ -57,18 +59,22 @@ __global__ __launch_bounds__(kEvalThreads, 2) void k_eval(const cx<double>* __re
     xs[0][threadIdx.x] = targets[2 * (size_t)ti] * inv_b;
     xs[1][threadIdx.x] = targets[2 * (size_t)ti + 1] * inv_b;
   }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  constexpr int nwaves = kEvalThreads / 64;
+  if (threadIdx.x < kEvalTargets * nwaves) red[threadIdx.x / nwaves][threadIdx.x % nwaves] = {0.0, 0.0};
   __syncthreads();
-  cx<double> tot[kEvalTargets];
-#pragma unroll
-  for (int g = 0; g < kEvalTargets; ++g) tot[g] = {0.0, 0.0};
-  const int stride = kEvalThreads * gridDim.y;
-  const int rounds = (nb + stride - 1) / stride;
+  constexpr int span = kEvalCols * kEvalThreads;       // columns of one block round
+  const int rounds = (nb + span * gridDim.y - 1) / (span * gridDim.y);
   for (int jc = 0; jc < rounds; ++jc) {
-    const int k2 = blockIdx.y * kEvalThreads + threadIdx.x + jc * stride;
-    const bool ok = k2 < nb;
-    cx<double> acc[kEvalTargets];
+    const int base = (blockIdx.y + jc * gridDim.y) * span + threadIdx.x;
+    bool ok[kEvalCols];
 #pragma unroll
-    for (int g = 0; g < kEvalTargets; ++g) acc[g] = {0.0, 0.0};
+    for (int c = 0; c < kEvalCols; ++c) ok[c] = base + c * kEvalThreads < nb;
+    cx<double> acc[kEvalCols][kEvalTargets];
+#pragma unroll
+    for (int c = 0; c < kEvalCols; ++c)
+#pragma unroll
+      for (int g = 0; g < kEvalTargets; ++g) acc[c][g] = {0.0, 0.0};
     for (int c0 = 0; c0 < nb; c0 += kE1Rows) {
       const int rows = nb - c0 < kE1Rows ? nb - c0 : kE1Rows;
       __syncthreads();                                  // the previous rows' reads are done
@@ -77,28 +83,34 @@ __global__ __launch_bounds__(kEvalThreads, 2) void k_eval(const cx<double>* __re
         e1s[r][g] = expo(c0 + r, nb, xs[0][g]);
       }
       __syncthreads();
-      const cx<double>* col = spec + (size_t)c0 * nb + (ok ? k2 : 0);
-#pragma unroll 2
       for (int r = 0; r < rows; ++r) {
-        const cx<double> c = ok ? col[(size_t)r * nb] : cx<double>{0.0, 0.0};
+        cx<double> cv[kEvalCols];
 #pragma unroll
-        for (int g = 0; g < kEvalTargets; ++g) acc[g] = acc[g] + cmul(c, e1s[r][g]);
+        for (int c = 0; c < kEvalCols; ++c)
+          cv[c] = ok[c] ? spec[(size_t)(c0 + r) * nb + base + c * kEvalThreads] : cx<double>{0.0, 0.0};
+#pragma unroll
+        for (int g = 0; g < kEvalTargets; ++g) {
+          const cx<double> e = e1s[r][g];
+#pragma unroll
+          for (int c = 0; c < kEvalCols; ++c) acc[c][g] = acc[c][g] + cmul(cv[c], e);
+        }
       }
     }
-    if (ok) {
+    // this round's columns times exp(2 pi i k2 x2/b), summed over the block's
+    // threads into red (one wave sum per target, added by lane 0)
 #pragma unroll
-      for (int g = 0; g < kEvalTargets; ++g) tot[g] = tot[g] + cmul(acc[g], expo(k2, nb, xs[1][g]));
-    }
-  }
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    for (int g = 0; g < kEvalTargets; ++g) {
+      cx<double> v{0.0, 0.0};
 #pragma unroll
-  for (int g = 0; g < kEvalTargets; ++g) {
-    double re = tot[g].x, im = tot[g].y;
-    for (int off = 32; off > 0; off >>= 1) {
-      re += __shfl_down(re, off, 64);
-      im += __shfl_down(im, off, 64);
+      for (int c = 0; c < kEvalCols; ++c)
+        if (ok[c]) v = v + cmul(acc[c][g], expo(base + c * kEvalThreads, nb, xs[1][g]));
+      double re = v.x, im = v.y;
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+      }
+      if (lane == 0) red[g][wave] = red[g][wave] + cx<double>{re, im};
     }
-    if (lane == 0) red[g][wave] = {re, im};
   }
   __syncthreads();
   if (threadIdx.x < kEvalTargets && t0 + (int)threadIdx.x < count) {
@@ -118,11 +130,11 @@ __global__ void k_eval_sum(const cx<double>* __restrict__ part, int slices, int 
 }
 
 // Column slices per target group: enough blocks for about 1024 in all, at most
-// one slice per 256 columns, and partial sums that fit in `room` elements.
+// one slice per block round of columns, and partial sums that fit in `room` elements.
 int eval_slices(int count, int nb, size_t room) {
   const int groups = (count + kEvalTargets - 1) / kEvalTargets;
   int s = (1024 + groups - 1) / groups;
-  s = std::min(s, std::max(1, nb / kEvalThreads));
+  s = std::min(s, std::max(1, nb / (kEvalCols * kEvalThreads)));
   while (s > 1 && (size_t)s * count > room) --s;
   return std::max(1, s);
 }
