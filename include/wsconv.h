@@ -82,8 +82,8 @@ typedef struct {
     int    n;               /* grid points per side on D; power of two, 16 <= n <= 2048 */
     int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1): 2, or 3 for
                                densities supported on all of D (b >= 1 + sqrt 2, Section 2.1).
-                               b = 3 needs n <= 1024, and is not taken by
-                               conv_apply_multi or Fourier smoothing (WS_EUNSUPPORTED) */
+                               b = 3 is not taken by conv_apply_multi or Fourier smoothing
+                               (WS_EUNSUPPORTED) */
     double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
                                the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the disc window
                                below.  The scheme computes the convolution only when a is at least
@@ -178,8 +178,9 @@ int conv_apply(ws_plan_t plan, int batch, const void* density, void* out, void* 
  * `work` argument: the intermediate lives in a fixed 64 MiB device array of
  * the library (one per device, held from the first call on that device until
  * the process ends), so a plan qualifies when its work_bytes_per_density is
- * at most 64 MiB (every real-kernel plan up to n = 2048 in FP64; Helmholtz
- * plans up to n = 1024 in FP64, 2048 in FP32); larger ones return
+ * at most 64 MiB (at period 2 every real-kernel plan up to n = 2048 in FP64,
+ * Helmholtz plans up to n = 1024 in FP64, 2048 in FP32; at period 3 every plan
+ * up to n = 1024, and FP32 real-kernel plans at 2048); larger ones return
  * WS_EUNSUPPORTED.  Densities go through the passes
  * min(conv_apply_chunk(plan), 64 MiB / work_bytes_per_density) at a time, with
  * results bitwise equal to conv_apply's.  The call allocates nothing; its

@@ -71,7 +71,6 @@ int check_grid(const ws_grid* g, double* a_out, int* logn) {
   if (g->n < 16 || g->n > 2048) return fail(WS_EUNSUPPORTED, "n must lie in [16, 2048]");
   if (g->b < 1) return fail(WS_EINVAL, "period b must be a positive integer");
   if (g->b != 2 && g->b != 3) return fail(WS_EUNSUPPORTED, "period b must be 2 or 3 (FFT length 2n or 3n)");
-  if (g->b == 3 && g->n > 1024) return fail(WS_EUNSUPPORTED, "period b = 3 supports n <= 1024");
   if (!std::isfinite(g->support_radius) || g->support_radius >= std::sqrt(2.0) / 2.0)
     return fail(WS_EINVAL, "support_radius must be finite and below sqrt(2)/2 (<= 0: all of D)");
   double a = g->a;

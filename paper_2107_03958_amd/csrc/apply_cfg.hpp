@@ -20,11 +20,20 @@ struct Cfg {
   static constexpr int n = 1 << LOGN;
   static constexpr int nb = B * n;
   static constexpr int CB = Layout<T>::CB;
-  static constexpr int RPB = Layout<T>::RPB;
   static constexpr int cap(int e, int lines, int L) {         // keep lines * L / e <= 1024 threads
     while (lines * (L / e) > 1024) e *= 2;
     return e < L ? e : L;
   }
+  // Rows per real row tile: Layout<T>::RPB, or one where that many rows' B
+  // half-length lines would take more than half the LDS of a CU (FP64,
+  // period 3, n = 2048), so that at least two blocks fit.
+  template <int ROWS>
+  static constexpr bool fits_half() {
+    constexpr int e = cap(Layout<T>::ER, B * ROWS, n / 2), ef = cap(Layout<T>::ERF, B * ROWS, n / 2);
+    return ROWS * B * std::max(LineLayout<n / 2, e>::STRIDE, LineLayout<n / 2, ef>::STRIDE) *
+               (int)sizeof(cx<T>) <= 81920;
+  }
+  static constexpr int RPB = fits_half<Layout<T>::RPB>() ? Layout<T>::RPB : 1;
   // Columns of the intermediate: real path nb/2 (half spectrum, column 0
   // packing the DC and Nyquist columns), complex path nb.
   static constexpr int NCOLS_R = nb / 2, NCOLS_C = nb;
@@ -49,11 +58,13 @@ struct Cfg {
   static constexpr int PF = LF / EF;
   static constexpr int NT_C = B * CPB * PF;
   static constexpr int SF = LineLayout<LF, EF>::STRIDE;
-  // FP64 period-2 column tiles whose cx<T> line buffers would leave room for
-  // only two blocks per CU exchange one real component at a time, through
-  // line buffers of T (half the LDS), so three blocks fit.
-  static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && B == 2 && B * CPB * SF * 16 * 3 > 163840 &&
-                                  B * CPB * SF * 8 * 3 <= 163840;
+  // FP64 column tiles whose cx<T> line buffers would leave room for fewer
+  // than three blocks per CU exchange one real component at a time, through
+  // line buffers of T (half the LDS), so three blocks fit (n = 2048: two
+  // blocks per CU instead of one at period 3, whose 384-thread tiles the
+  // registers then limit to two).
+  static constexpr bool SPLIT_C = WS_SPLIT64 && sizeof(T) == 8 && (B == 2 || B == 3) &&
+                                  B * CPB * SF * 16 * 3 > 163840 && B * CPB * SF * 8 * 3 <= 163840;
   static constexpr int LDS_C = SPLIT_C ? (B * CPB * SF + 1) / 2 : B * CPB * SF;   // cx<T> elements
   // Column tiles compiled for three blocks per CU (168 VGPRs), which load
   // their moments after the forward transform to fit: split tiles, and
@@ -85,8 +96,8 @@ struct Cfg {
 };
 
 constexpr int kMinLogn = 4, kMaxLogn = 11;
-// Period b = 3 (nb = 3n): plans up to n = 1024, single-plan launches.
-constexpr int kMaxLognB3 = 10;
+// Period b = 3 (nb = 3n): plans of every size, single-plan launches.
+constexpr int kMaxLognB3 = 11;
 constexpr int kMaxSegs = 8;
 
 // Block size and LDS of each kind of pass: the largest over all sizes.
@@ -123,9 +134,10 @@ struct Blk {
                 LDS_RC * sizeof(cx<T>) <= 163840 && LDS_CR * sizeof(cx<T>) <= 163840, "block LDS above 160 KiB");
   // Waves per SIMD the column kernel reserves registers for: as many blocks
   // per CU as its LDS allows, up to two, or three for split tiles (which
-  // load their moments late to fit the registers of three).
+  // load their moments late to fit the registers of three) when three blocks
+  // are at most three waves per SIMD (168 VGPRs; below that the butterflies spill).
   static constexpr int waves(int threads, int lds_bytes, bool three) {
-    const int blocks = three && lds_bytes * 3 <= 163840 ? 3 : lds_bytes * 2 <= 163840 ? 2 : 1;
+    const int blocks = three && lds_bytes * 3 <= 163840 && threads * 3 <= 768 ? 3 : lds_bytes * 2 <= 163840 ? 2 : 1;
     const int w = (blocks * threads + 255) / 256;
     return w < 1 ? 1 : w;
   }

@@ -432,7 +432,6 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
   const TW tw = sg.tw;
   cx<T>* col = g.col(sg.work);
   constexpr bool SPLIT = C::SPLIT_C;                   // line buffers of T: one component at a time
-  static_assert(!SPLIT || B == 2, "split column exchange: period 2");
   using LT = std::conditional_t<SPLIT, T, cx<T>>;
   LT* const lbase = reinterpret_cast<LT*>(lds);
   LT* mine = lbase + (B * cc + l) * S;
@@ -576,7 +575,7 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     if (GUARD && !valid) return;
     combine_lines<B, L, E, 1>(lds + (B * cc) * S, S, p, l, tw, wcomb, B == 2 ? cconj(wstep) : wcstep,
                               [&](int i, cx<T> y) { col[(size_t)i * CB + c] = y; });
-  } else {
+  } else if constexpr (B == 2) {
     // combine_lines (B = 2) one component at a time: out_i = line_0[i] +
     // w_i line_1[i], w_i = w_nb^{-i}, accumulated over the two rounds.
     const T* l0 = lbase + (B * cc) * S;
@@ -601,6 +600,43 @@ __device__ __forceinline__ void cols_compute(const Seg<T>& sg, int t, bool valid
     if (GUARD && !valid) return;
 #pragma unroll
     for (int tt = 0; tt < E / 2; ++tt) col[(size_t)(p + P * (l * (E / 2) + tt)) * CB + c] = acc[tt];
+  } else {
+    // combine_lines (B = 3) one component at a time: out_i = line_0[i] +
+    // w_i line_1[i] + w_i^2 line_2[i], w_i = w_nb^{-i}, i = p + P (l + 3 t),
+    // accumulated over the two rounds (a real part a adds a w, an imaginary
+    // part b adds i b w).
+    const T* l0 = lbase + (B * cc) * S;
+    const T* l1 = l0 + S;
+    const T* l2 = l1 + S;
+    constexpr int TMAX = (E + B - 1) / B;
+    cx<W> w[TMAX];
+    cx<T> acc[TMAX];
+    run_from<TMAX>(wcomb, wcstep, w);
+    split_parts([&](auto part) {
+      constexpr int PART = decltype(part)::value;
+#pragma unroll
+      for (int reg = 0; reg < E; ++reg) mine[LL::pad_ps(p, slot_elem<E, RL>(reg))] = part_of<PART>(v[0][reg]);
+      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < TMAX; ++tt) {
+        const int s = l + B * tt;
+        if (s < E) {
+          const int i = p + P * s;
+          const cx<W> w2 = cmul(w[tt], w[tt]);
+          const T a0 = l0[LL::pad(i)], a1 = l1[LL::pad(i)], a2 = l2[LL::pad(i)];
+          const T re = (T)w[tt].x * a1 + (T)w2.x * a2, im = (T)w[tt].y * a1 + (T)w2.y * a2;
+          if constexpr (PART == 0) acc[tt] = {a0 + re, im};
+          else acc[tt] = {acc[tt].x - im, acc[tt].y + (a0 + re)};
+        }
+      }
+      __syncthreads();
+    });
+    if (GUARD && !valid) return;
+#pragma unroll
+    for (int tt = 0; tt < TMAX; ++tt) {
+      const int s = l + B * tt;
+      if (s < E) col[(size_t)(p + P * s) * CB + c] = acc[tt];
+    }
   }
 }
 
@@ -1255,8 +1291,8 @@ template <typename T, int K>
 constexpr bool has_b3() {
   return K != kRowsInvFs && K != kColsGen;
 }
-#define WS_FOR_EACH_LOGN_B3(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10)
-static_assert(kMaxLognB3 == 10, "WS_FOR_EACH_LOGN_B3 lists 4..kMaxLognB3");
+#define WS_FOR_EACH_LOGN_B3(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
+static_assert(kMaxLognB3 == 11, "WS_FOR_EACH_LOGN_B3 lists 4..kMaxLognB3");
 template <typename T, int K>
 Geo geo(int logn, int b) {
   if (b == 3) {

@@ -106,7 +106,7 @@ template <> struct Layout<float> {
 
 struct Plan {
   ws_kernel kern;
-  int n = 0, b = 2, nb = 0, logn = 0;   // nb = b n; b = 2, or 3 (FP64, n <= 1024, single-plan launches)
+  int n = 0, b = 2, nb = 0, logn = 0;   // nb = b n; b = 2, or 3 (single-plan launches)
   double a = 0;
   double support_radius = 0;  // rho of the grid descriptor (<= 0: all of D)
   bool force_a = false;       // the a-window check was skipped at plan time

@@ -180,7 +180,7 @@ void check_single_b3(int batch) {
   using KO = KindOf<T, K, B>;
   CHECK(S::BLOCK % S::NT == 0 && S::TPB * S::NT == S::BLOCK && S::BLOCK <= 1024 && S::BLOCK >= WS_MIN_BLOCK);
   CHECK(S::LDS * (int)sizeof(cx<T>) <= 163840);
-  CHECK(!C::SPLIT_C);                                  // the split exchange is period 2 only
+  CHECK(!C::SPLIT_C || (sizeof(T) == 8 && LOGN == 11));   // split exchange: FP64 at n = 2048 only
   const int ntiles = batch * KO::template tiles_per_density<LOGN>();
   const int nblocks = (ntiles + S::TPB - 1) / S::TPB;
   constexpr int G = KO::template line_group<LOGN>();

@@ -66,6 +66,8 @@ def test_plan_query_sizes_period3(lib):
     rc, pbh, wbh = _query(lib, family=L.WS_HELMHOLTZ, kappa=20.0, n=512, b=3)
     assert rc == L.WS_OK and wbh == 512 * 1536 * 16
     assert pbh >= 769 * 1536 * 16
+    rc, pb, wb = _query(lib, n=2048, b=3)
+    assert rc == L.WS_OK and wb == 2048 * 3072 * 16
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -73,7 +75,6 @@ def test_plan_query_sizes_period3(lib):
     (dict(n=8), L.WS_EUNSUPPORTED),
     (dict(n=4096), L.WS_EUNSUPPORTED),
     (dict(b=4), L.WS_EUNSUPPORTED),
-    (dict(b=3, n=2048), L.WS_EUNSUPPORTED),
     (dict(b=0), L.WS_EINVAL),
     (dict(a=2.5), L.WS_EINVAL),
     (dict(family=L.WS_POWER, gamma=0.5), L.WS_EINVAL),

@@ -58,9 +58,9 @@ def test_b3_real_apply(api, kname, n):
         assert metrics.rel_linf(got[i], ref) <= FP64_TOL, (kname, n, i)
 
 
-@pytest.mark.parametrize("n", [512, 1024])
+@pytest.mark.parametrize("n", [512, 1024, 2048])
 def test_b3_real_apply_large(api, n):
-    # n = 1024 is the largest period-3 size; batch 2 at n = 512 and 1024
+    # batch 2 up to the largest size, n = 2048 (FFT length 6144)
     us = _densities(n, 2)
     plan = api.ConvPlan(n=n, b=B3, **plan_kwargs("log"))
     got = plan.apply(_gpu(us, torch.float64)).cpu().numpy()
@@ -82,7 +82,7 @@ def test_b3_passes_match_apply(api):
     assert torch.equal(out, ref)
 
 
-@pytest.mark.parametrize("n", [16, 64, 256])
+@pytest.mark.parametrize("n", [16, 64, 256, 2048])
 def test_b3_complex_apply(api, n):
     rng = np.random.default_rng(synth.SEED_FULL_SUPPORT + n)
     base = synth.full_support_density(n, synth.SEED_FULL_SUPPORT)
@@ -128,7 +128,7 @@ def test_b3_ls_solve_vs_dense(api, n):
 
 
 @pytest.mark.parametrize("kname,n", [("log", 16), ("pow-1/2", 16), ("log", 64), ("pow-1/2", 64), ("log", 256),
-                                     ("pow-1/2", 256), ("log", 1024)])
+                                     ("pow-1/2", 256), ("log", 1024), ("log", 2048)])
 def test_b3_fp32_real_apply(api, kname, n):
     # FP32 passes at period 3 against the FP64 oracle, to the FP32 bounds (|x|^-1/2 up to
     # n = 256: the oracle's power-kernel table at n = 1024, b = 3 takes minutes)
@@ -141,7 +141,7 @@ def test_b3_fp32_real_apply(api, kname, n):
         assert metrics.rel_l2(got[i], ref) <= 5e-7, (kname, n, i)
 
 
-@pytest.mark.parametrize("n", [16, 64, 256])
+@pytest.mark.parametrize("n", [16, 64, 256, 2048])
 def test_b3_fp32_complex_apply(api, n):
     rng = np.random.default_rng(synth.SEED_FULL_SUPPORT + n)
     base = synth.full_support_density(n, synth.SEED_FULL_SUPPORT)
@@ -204,9 +204,6 @@ def test_b3_ls_solve_n128(api, mixed):
 
 def test_b3_unsupported_uses(api):
     from paper_2107_03958_amd import _lib as L
-    with pytest.raises(L.WsError) as e:
-        api.ConvPlan(n=2048, b=B3, **plan_kwargs("log"))
-    assert e.value.code == L.WS_EUNSUPPORTED
     p3 = api.ConvPlan(n=64, b=B3, **plan_kwargs("log"))
     p2 = api.ConvPlan(n=64, **plan_kwargs("log"))
     u = _gpu(_densities(64, 1), torch.float64)
@@ -216,3 +213,21 @@ def test_b3_unsupported_uses(api):
     with pytest.raises(L.WsError) as e:
         p3.apply(u, fs=[api.FsDesc("disc", 0.5, 0.5, 0.2, 0.2, 0.39)])
     assert e.value.code == L.WS_EUNSUPPORTED
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mixed", [False, True])
+def test_b3_ls_solve_n2048(api, mixed):
+    # period 3 at the largest size (FFT length 6144), kappa = 20, FP64 and FP32 + FP64 refinement:
+    # the GPU solution's residual under the oracle's operator meets the requested 1e-10
+    n, kappa = 2048, 20.0
+    x1, x2 = synth.grid(n)
+    m = 0.5 * (16.0 * x1 * (1.0 - x1) * x2 * (1.0 - x2)) ** 3
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + 20))
+    plan = api.ConvPlan(n=n, b=B3, precision="fp32" if mixed else "fp64", **plan_kwargs("helm20"))
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-10, restart=50,
+                            mixed=mixed)
+    assert info.status == 0, info
+    got = u.cpu().numpy()
+    res = np.linalg.norm(ui - ols.matvec(got, m, table3("helm20", n), B3, kappa)) / np.linalg.norm(ui)
+    assert res <= 1.2e-10, (res, info)
