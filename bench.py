@@ -58,6 +58,12 @@ def pass_bytes(n: int, s: int, b: int = 2) -> list[float]:
     return [n * n * s + inter, 2.0 * inter + (half + 1) * (half + 1) * s, inter + n * n * s]
 
 
+def table_bytes(n: int, s: int, b: int = 2) -> float:
+    """Bytes of the moment table the column pass reads (included in pass_bytes once per density)."""
+    half = b * n // 2
+    return float((half + 1) * (half + 1) * s)
+
+
 def measured_traffic(kernel: str, precision: str, n: int, chunk: int, b: int = 2):
     """HBM bytes per launch of `kernel` from the committed PMC summary of this workload
     (profiles/apply_<precision>_<n>[_period3]_traffic.json: FETCH_SIZE + WRITE_SIZE, calibrated by a
@@ -129,6 +135,9 @@ def run_apply_bench(api, torch, n, batch, precision, steps, warmup, u_host, b=2,
         applies_per_s=applies / elapsed,
         ms_per_step=elapsed / steps * 1e3,
         pass_model_gbps=applies * sum(pb) / elapsed / 1e9,
+        # the same with the moment table, which a launch's densities share, counted once per launch
+        pass_model_gbps_table_per_launch=(applies * (sum(pb) - table_bytes(n, s, b)) + launches * table_bytes(n, s, b))
+        / elapsed / 1e9,
         pass_avg_ms={PASS_NAMES[i]: float(avg_pass_ms[i]) for i in range(3)},
         pass_gbps={PASS_NAMES[i]: float(pb[i] * batch * steps * nk / (pass_ms[i] * 1e-3) / 1e9) for i in range(3)},
         densities_per_launch=chunk,
@@ -873,6 +882,7 @@ def main(argv=None):
         "grid_points_per_s": r64["applies_per_s"] * n * n,
         "hbm_gbps_pass_model": r64["pass_model_gbps"],
         "hbm_frac_pass_model": r64["pass_model_gbps"] / PEAK_HBM_GBPS,
+        "hbm_frac_pass_model_table_per_launch": r64["pass_model_gbps_table_per_launch"] / PEAK_HBM_GBPS,
         "pass_avg_ms": r64["pass_avg_ms"],
         "pass_gbps": r64["pass_gbps"],
         "plan_build_s": r64["plan_build_s"],

@@ -115,7 +115,8 @@ Sizes sizes_for(int n, int b, bool cplx, int precision, double beta = 0.0) {
   const size_t nb = (size_t)b * n;
   const size_t te = ws::table_elems(n, b, cplx);
   s.tw64 = align_up(nb * 16);
-  s.tw32 = precision == WS_FP32 ? align_up(nb * 16) : 0;  // (hi, lo) float pairs
+  // (hi, lo) float pairs: read only by FP32 passes built to use the pair table
+  s.tw32 = precision == WS_FP32 && WS_TW32_POWERS == 0 ? align_up(nb * 16) : 0;
   s.g64 = align_up(te * (cplx ? 16 : 8));
   s.nyq64 = cplx ? 0 : align_up((nb / 2 + 1) * 8);
   s.g32 = precision == WS_FP32 ? align_up(te * (cplx ? 8 : 4)) : 0;
@@ -204,7 +205,7 @@ int conv_plan(const ws_kernel* kernel, const ws_grid* grid, int precision, void*
   size_t off = 0;
   p->tw64 = reinterpret_cast<ws::cx<double>*>(base + off);
   off += s.tw64;
-  if (precision == WS_FP32) {
+  if (s.tw32) {
     p->tw32 = reinterpret_cast<ws::TwPair*>(base + off);
     off += s.tw32;
   }

@@ -19,6 +19,12 @@ def test_period3_pass_model():
     assert pb == [n * n * s + inter, 2 * inter + (3 * n // 2 + 1) ** 2 * s, inter + n * n * s]
 
 
+def test_table_bytes_is_the_column_pass_extra():
+    # the moment table is what the column pass reads beyond the intermediate it reads and writes
+    for n, s, b in ((64, 8, 2), (2048, 8, 2), (2048, 4, 2), (1024, 8, 3)):
+        assert bench.pass_bytes(n, s, b)[1] - 2 * b * n * n * s == bench.table_bytes(n, s, b)
+
+
 def test_more_than_one_gpu_is_refused(capsys):
     assert bench.main(["--gpus", "2"]) == 2
     out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
