@@ -241,37 +241,40 @@ def run_paper_timing(api, torch, n=512, b=3, repeats=20):
                      "hardware and precision; context only")
 
 
-def ls_step_bytes(n: int, s: int, j: int) -> float:
-    """Algorithmic HBM bytes of Arnoldi step j (j + 1 basis vectors before it) at period 2, s bytes per real.
+def ls_op_bytes(n: int, s: int) -> float:
+    """Algorithmic HBM bytes of one LS operator application at period 2, s bytes per real.
 
     The operator v -> v + kappa^2 A_n(m v) reads v (2 n^2 s) and m (n^2 s) and writes the n x 2n
     complex intermediate (4 n^2 s); the column pass reads and writes it and reads the complex
     moment table ((n + 1) 2n complex, ~4 n^2 s); the inverse rows read it and v and write the
-    result (2 n^2 s): 27 n^2 s.  Each of the two Gram-Schmidt passes reads the j + 1 basis
-    vectors and w for the dot products, then the j + 1 vectors and w again and writes w for the
-    update ((4 j + 10) 2 n^2 s for both); the normalisation reads and writes w (4 n^2 s).
+    result (2 n^2 s): 27 n^2 s.
     """
-    vec = 2 * n * n * s
-    return 27 * n * n * s + (4 * j + 10) * vec + 2 * vec
+    return 27 * n * n * s
+
+
+def ls_step_bytes(n: int, s: int, j: int) -> float:
+    """Algorithmic HBM bytes of the Gram-Schmidt work of Arnoldi step j (delayed reorthogonalisation,
+    j final basis vectors before it): the reduction reads the j vectors, u_j and w; the update reads
+    them again and writes v_j and u_{j+1}: (2 j + 6) vectors of 2 n^2 s."""
+    return (2 * j + 6) * 2 * n * n * s
 
 
 def ls_solve_bytes(n: int, info, mixed: bool, restart: int = 50) -> float:
-    """Bytes of a whole solve from its counters: cycles of `restart` steps (the last one shorter),
-    each ending with a true-residual operator application (and a residual vector pass); the
+    """Bytes of a whole solve from its counters.  A cycle of k columns takes k + 1 steps (the last
+    finalises column k - 1); its operator applications, the cycle's true-residual one included,
+    are the solver's matvec count, and each cycle ends with a residual vector pass.  The
     mixed-precision solve runs its Arnoldi steps with FP32 vectors and one FP64 operator per
     refinement."""
     s_in = 4 if mixed else 8
     it = info.iterations
     extra_fp64 = info.refinements if mixed else 0
-    cycles_mv = max(0, info.matvecs - it - extra_fp64)     # true-residual applications of the inner solver
-    total = 0.0
+    total = max(0, info.matvecs - extra_fp64) * ls_op_bytes(n, s_in)
     left = it
     while left > 0:
         k = min(restart, left)
-        total += sum(ls_step_bytes(n, s_in, j) for j in range(k))
+        total += sum(ls_step_bytes(n, s_in, j) for j in range(k + 1)) + 3 * 2 * n * n * s_in
         left -= k
-    total += cycles_mv * (27 * n * n * s_in + 3 * 2 * n * n * s_in)
-    total += extra_fp64 * (27 * n * n * 8 + 3 * 2 * n * n * 8)
+    total += extra_fp64 * (ls_op_bytes(n, 8) + 3 * 2 * n * n * 8)
     return total
 
 

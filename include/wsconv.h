@@ -122,7 +122,7 @@ typedef struct {
 
 typedef struct {
     int    status;        /* WS_LS_CONVERGED, WS_LS_MAXIT or WS_LS_BREAKDOWN */
-    int    iterations;    /* Arnoldi steps taken (all cycles, all refinements) */
+    int    iterations;    /* Arnoldi columns built (all cycles, all refinements) */
     int    matvecs;       /* operator applications, including true-residual checks */
     int    refinements;   /* outer refinement steps (mixed precision), else 0 */
     double rel_residual;  /* final true relative residual ||u_inc - K u|| / ||u_inc||, in FP64 */
@@ -226,8 +226,9 @@ int ls_solve_query(ws_plan_t plan, int restart, int mixed_precision, size_t* wor
 
 /* Solve the Nystrom discretisation of the Lippmann-Schwinger equation
  * (Section 3.3, eq. descretls):  u_j + kappa^2 (A_n(m u))_j = u_inc_j,  j in G_n,
- * by restarted GMRES(restart) from u = 0 with classical Gram-Schmidt applied
- * twice and Givens rotations, all in FP64 on the device; the stop test is the
+ * by restarted GMRES(restart) from u = 0 with Gram-Schmidt and one
+ * reorthogonalisation (delayed into the next Arnoldi step's single reduction)
+ * and Givens rotations, all in FP64 on the device; the stop test is the
  * true relative residual ||u_inc - K u||_2 / ||u_inc||_2 <= tol (K = I + kappa^2 A_n M).
  *  plan:      a WS_HELMHOLTZ plan (kappa from the kernel).
  *  contrast:  [n][n] float64, m = 1 - mu (device).

@@ -2,11 +2,15 @@
 // (Section 3.3, eq. descretls):  K u = u_inc,  K v = v + kappa^2 A_n(m v).
 //
 // The paper solves it with a matrix-free GMRES; restart length, tolerance and
-// orthogonalisation are not stated.  Here: x0 = 0, classical Gram-Schmidt
-// applied twice (CGS2) with FP64 accumulation, Givens rotations on the
-// Hessenberg matrix, all on the device.  An Arnoldi step is eight launches:
-// the three passes of the operator, two (dot products, update) pairs in which
-// the update blocks finish the dot products, and the normalisation, whose
+// orthogonalisation are not stated.  Here: x0 = 0, Gram-Schmidt with one
+// reorthogonalisation and FP64 accumulation, Givens rotations on the
+// Hessenberg matrix, all on the device.  By default the reorthogonalisation
+// of each direction is delayed into the next step's single reduction (see
+// k_dots_d / k_update_d): a step is five launches, the three passes of the
+// operator, the dot products and the update, whose blocks finish the dot
+// products and whose first block finalises a Hessenberg column.  With
+// WS_LS_DCGS2 = 0 a step is classical Gram-Schmidt twice, eight launches: the
+// operator, two (dot products, update) pairs, and the normalisation, whose
 // blocks finish the norm and whose first block applies the Givens rotation.
 // The host enqueues a cycle's steps in chunks (replayed as captured graphs),
 // watches the device's stop flag one chunk behind through page-locked memory
@@ -36,6 +40,12 @@
 
 #include "ls.hpp"
 
+// 1: Arnoldi with delayed reorthogonalisation (one reduction per step, the
+// basis read twice per step); 0: classical Gram-Schmidt twice per step.
+#ifndef WS_LS_DCGS2
+#define WS_LS_DCGS2 1
+#endif
+
 namespace ws {
 
 namespace {
@@ -52,6 +62,8 @@ struct GState {
   double beta;     // norm of the cycle's start residual
   double tol_abs;  // stop when est <= tol_abs
   double norm;     // scratch: last computed norm
+  int nop;         // delayed reorthogonalisation: the next step applies no operator (stopped, or budget reached)
+  int mv;          // delayed reorthogonalisation: operator applications of this cycle
 };
 
 // Per-cycle parameters of a batch's instances, passed by value.
@@ -232,12 +244,174 @@ __global__ __launch_bounds__(kThreads) void k_normalise_givens(cx<T>* V, size_t 
   }
 }
 
-// flag = every instance of the batch has stopped (the operator's skip flag).
-__global__ void k_all_done(const GState* st, int count, int* flag) {
+// ---------------------------------------------------------------------------
+// Arnoldi step with delayed reorthogonalisation: the second Gram-Schmidt pass
+// of direction j - 1 is folded into step j's single reduction.  On entry to
+// step j, slot j holds u_j, the once-orthogonalised (unnormalised) direction
+// left by step j - 1 (at j = 0 the normalised v_0), and the operator has
+// written w = Op u_j into slot j + 1.  With V_j = (v_0 .. v_{j-1}) orthonormal:
+//   a = V_j^H u_j, b = V_j^H w, alpha = |u_j|^2, beta = u_j^H w   (one sweep),
+//   nu = sqrt(alpha - |a|^2)                 (norm of u_j - V_j a; nu = 1 at j = 0),
+//   v_j = (u_j - V_j a) / nu,
+//   column j - 1 of the Hessenberg matrix gains a and its subdiagonal nu, and
+//   is final (Givens rotation, residual estimate, stop test),
+//   d = v_j^H w = (beta - a^H b) / nu,
+//   u_{j+1} = (w - V_j b - v_j d) / nu       (= Op v_j minus its projection on v_0 .. v_j),
+//   provisional column j = ((b, d) - Hraw[:, 0:j] a) / nu,
+// which follows from Op u_j = w and Op V_j = V_{j+1} Hraw[:, 0:j] (the
+// Arnoldi relation with the final columns 0 .. j - 1).  A column is final one
+// step after its direction's operator, so the stop test lags one step, and a
+// cycle of m columns ends with an operator-free step j = m.
+
+// Partials of (a_i, b_i) for rows i < j, and of (alpha, beta) for row j (grid
+// nbd x (j + 1) x count).  last: step j = restart, no w.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dots_d(const cx<T>* V, size_t N, int count, int j, int last,
+                                                     cx<double>* pa, cx<double>* pb, size_t pstride,
+                                                     const GState* st) {
+  const int s = blockIdx.z;
+  if (st[s].done) return;
+  __shared__ double sh[kThreads];
+  const int i = blockIdx.y;
+  const cx<T>* vi = V + ((size_t)i * count + s) * N;      // row j: u_j itself
+  const cx<T>* u = V + ((size_t)j * count + s) * N;
+  const cx<T>* w = last ? nullptr : V + ((size_t)(j + 1) * count + s) * N;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
+    const cx<double> a = up(vi[e]), x = up(u[e]);
+    ar += a.x * x.x + a.y * x.y;
+    ai += a.x * x.y - a.y * x.x;
+    if (w) {
+      const cx<double> y = up(w[e]);
+      br += a.x * y.x + a.y * y.y;
+      bi += a.x * y.y - a.y * y.x;
+    }
+  }
+  ar = block_sum(ar, sh);
+  ai = block_sum(ai, sh);
+  if (w) {
+    br = block_sum(br, sh);
+    bi = block_sum(bi, sh);
+  }
+  if (threadIdx.x == 0) {
+    const size_t k = s * pstride + (size_t)i * gridDim.x + blockIdx.x;
+    pa[k] = {ar, ai};
+    pb[k] = {br, bi};
+  }
+}
+
+// The rest of step j (every block finishes the sums itself, in a fixed
+// order); block 0 finalises column j - 1 and stores the provisional column j;
+// every block writes its part of v_j and u_{j+1}.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_d(cx<T>* V, size_t N, int count, int j, int last,
+                                                       const cx<double>* pa, const cx<double>* pb, size_t pstride,
+                                                       int nbd, cx<double>* H, cx<double>* Hraw, size_t hstride,
+                                                       int ldh, cx<double>* cs, cx<double>* sn, int rs,
+                                                       cx<double>* g, GState* st) {
+  const int s = blockIdx.z;
+  if (st[s].done) return;
+  __shared__ cx<double> as[256], bs[256];
+  __shared__ double nu_s;
+  __shared__ cx<double> d_s;
+  const cx<double>* qa = pa + s * pstride;
+  const cx<double>* qb = pb + s * pstride;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+  for (int i = wave; i <= j; i += nw) {
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    for (int b = lane; b < nbd; b += 64) {
+      const cx<double> x = qa[(size_t)i * nbd + b], y = qb[(size_t)i * nbd + b];
+      r0 += x.x;
+      r1 += x.y;
+      r2 += y.x;
+      r3 += y.y;
+    }
+    r0 = wave_sum(r0);
+    r1 = wave_sum(r1);
+    r2 = wave_sum(r2);
+    r3 = wave_sum(r3);
+    if (lane == 0) {
+      as[i] = {r0, r1};
+      bs[i] = {r2, r3};
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double na = 0.0;
+    cx<double> ab{0.0, 0.0};
+    for (int i = 0; i < j; ++i) {
+      na += as[i].x * as[i].x + as[i].y * as[i].y;
+      ab = {ab.x + as[i].x * bs[i].x + as[i].y * bs[i].y, ab.y + as[i].x * bs[i].y - as[i].y * bs[i].x};
+    }
+    const double nu = j == 0 ? 1.0 : sqrt(fmax(as[j].x - na, 0.0));
+    nu_s = nu;
+    d_s = {(bs[j].x - ab.x) / nu, (bs[j].y - ab.y) / nu};
+  }
+  __syncthreads();
+  const double nu = nu_s;
+  const cx<double> d = d_s;
+  if (blockIdx.x == 0) {
+    GState& S = st[s];
+    cx<double>* Hr = Hraw + s * hstride;
+    cx<double>* Hs = H + s * hstride;
+    if (j >= 1) {
+      cx<double>* col = Hr + (size_t)(j - 1) * ldh;
+      for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        col[i] = i < j ? cx<double>{col[i].x + as[i].x, col[i].y + as[i].y} : cx<double>{nu, 0.0};
+        Hs[(size_t)(j - 1) * ldh + i] = col[i];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (!S.nop) S.mv += 1;             // this step's operator ran for this instance
+      if (j >= 1)
+        givens_step(Hs, ldh, cs + (size_t)s * rs, sn + (size_t)s * rs, g + (size_t)s * (rs + 1), j - 1, nu, &S);
+      S.nop = S.done || j + 1 >= S.maxk;
+    }
+    if (!last) {
+      for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        cx<double> acc = i < j ? bs[i] : d;
+        for (int k = 0; k < j; ++k) {
+          const cx<double> h = Hr[(size_t)k * ldh + i];
+          acc = {acc.x - (h.x * as[k].x - h.y * as[k].y), acc.y - (h.x * as[k].y + h.y * as[k].x)};
+        }
+        Hr[(size_t)j * ldh + i] = {acc.x / nu, acc.y / nu};
+      }
+    }
+  }
+  if (last) return;
+  const double inv = 1.0 / nu;
+  cx<T>* u = V + ((size_t)j * count + s) * N;
+  cx<T>* w = V + ((size_t)(j + 1) * count + s) * N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
+    cx<double> x = up(u[e]), y = up(w[e]);
+    for (int i = 0; i < j; ++i) {
+      const cx<double> v = up(V[((size_t)i * count + s) * N + e]);
+      x.x -= v.x * as[i].x - v.y * as[i].y;
+      x.y -= v.x * as[i].y + v.y * as[i].x;
+      y.x -= v.x * bs[i].x - v.y * bs[i].y;
+      y.y -= v.x * bs[i].y + v.y * bs[i].x;
+    }
+    const cx<T> xr = down<T>({x.x * inv, x.y * inv});
+    const cx<double> xd = up(xr);                   // v_j as stored
+    y.x -= xd.x * d.x - xd.y * d.y;
+    y.y -= xd.x * d.y + xd.y * d.x;
+    u[e] = xr;
+    w[e] = down<T>({y.x * inv, y.y * inv});
+  }
+}
+
+// flag = every instance of the batch has stopped; flag_nop (when given) = no
+// instance needs the next step's operator.
+__global__ void k_all_done(const GState* st, int count, int* flag, int* flag_nop) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int all = 1;
-  for (int s = 0; s < count; ++s) all &= st[s].done ? 1 : 0;
+  int all = 1, alln = 1;
+  for (int s = 0; s < count; ++s) {
+    all &= st[s].done ? 1 : 0;
+    alln &= st[s].nop ? 1 : 0;
+  }
   *flag = all;
+  if (flag_nop) *flag_nop = alln;
 }
 
 // y = R^-1 g over the kused x kused upper triangle (instance s = blockIdx.x, in mask).
@@ -328,17 +502,19 @@ __global__ void k_norm_finish(const double* npart, int nb, GState* st) {
 }
 
 // Start of a cycle for the instances in ctl.active: V_s(0) = r_s / ||r_s||
-// (norm in st[s].norm), H_s and g_s cleared, g_s(0) = ||r_s||, stop state
-// reset; every other instance is marked stopped.
+// (norm in st[s].norm), H_s (and Hraw_s, when given) and g_s cleared,
+// g_s(0) = ||r_s||, stop state reset; every other instance is marked stopped.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cycle_start(const cx<T>* r, cx<T>* V, size_t N, int count,
-                                                          cx<double>* H, size_t hstride, cx<double>* g, int gstride,
-                                                          GState* st, CycleCtl ctl) {
+                                                          cx<double>* H, cx<double>* Hraw, size_t hstride,
+                                                          cx<double>* g, int gstride, GState* st, CycleCtl ctl) {
   const int s = blockIdx.z;
   if (!in_mask(ctl.active, s)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st[s].done = 1;
+      st[s].nop = 1;
       st[s].kused = 0;
+      st[s].mv = 0;
     }
     return;
   }
@@ -354,11 +530,15 @@ __global__ __launch_bounds__(kThreads) void k_cycle_start(const cx<T>* r, cx<T>*
     cx<double>* Hs = H + s * hstride;
     cx<double>* gs = g + (size_t)s * gstride;
     for (size_t i = threadIdx.x; i < hstride; i += blockDim.x) Hs[i] = {0.0, 0.0};
+    if (Hraw)
+      for (size_t i = threadIdx.x; i < hstride; i += blockDim.x) Hraw[s * hstride + i] = {0.0, 0.0};
     for (int i = threadIdx.x; i < gstride; i += blockDim.x) gs[i] = {0.0, 0.0};
     __syncthreads();
     if (threadIdx.x == 0) {
       gs[0] = {nrm, 0.0};
       st[s].done = 0;
+      st[s].nop = 0;
+      st[s].mv = 0;
       st[s].kused = 0;
       st[s].bad = 0;
       st[s].maxk = ctl.maxk[s];
@@ -422,13 +602,16 @@ struct Krylov {
   size_t N = 0;
   GState* st = nullptr;      // [count]
   int* alldone = nullptr;    // every instance stopped (batches of more than one)
-  cx<double>* H = nullptr;   // [count][(restart + 1) restart]
+  int* allnop = nullptr;     // every instance's next step applies no operator (delayed reorthogonalisation)
+  cx<double>* H = nullptr;   // [count][(restart + 1) restart], Givens-rotated
+  cx<double>* Hraw = nullptr;   // [count][(restart + 1) restart], unrotated (delayed reorthogonalisation)
   cx<double>* cs = nullptr;  // [count][restart]
   cx<double>* sn = nullptr;
   cx<double>* g = nullptr;   // [count][restart + 1]
   cx<double>* y = nullptr;
   cx<double>* h = nullptr;
   cx<double>* partial = nullptr;   // [count][(restart + 1) kBlocks]
+  cx<double>* partial2 = nullptr;  // [count][(restart + 1) kBlocks] (delayed reorthogonalisation)
   double* npart = nullptr;         // [count][kBlocks]
   cx<T>* V = nullptr;        // [restart + 1][count][N]
   cx<T>* r = nullptr;        // [count][N]
@@ -440,10 +623,10 @@ struct Krylov {
 
   static size_t bytes(int restart, size_t N, int n, int nb, int count, int inters) {
     const size_t c = (size_t)count;
-    size_t b = align_up(sizeof(GState) * c + sizeof(int));
-    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * restart * c);
+    size_t b = align_up(sizeof(GState) * c + 2 * sizeof(int));
+    b += 2 * align_up(sizeof(cx<double>) * (size_t)(restart + 1) * restart * c);
     b += 3 * align_up(sizeof(cx<double>) * (size_t)(restart + 1) * c) + 2 * align_up(sizeof(cx<double>) * restart * c);
-    b += align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks * c) + align_up(sizeof(double) * kBlocks * c);
+    b += 2 * align_up(sizeof(cx<double>) * (size_t)(restart + 1) * kBlocks * c) + align_up(sizeof(double) * kBlocks * c);
     b += align_up(sizeof(cx<T>) * (size_t)(restart + 1) * N * c) + 2 * align_up(sizeof(cx<T>) * N * c);
     b += align_up(sizeof(cx<T>) * inter_elems<T>(n, nb) * (size_t)inters);
     return b;
@@ -458,16 +641,19 @@ struct Krylov {
       base += align_up(sz);
       return p;
     };
-    char* stb = take(sizeof(GState) * c + sizeof(int));
+    char* stb = take(sizeof(GState) * c + 2 * sizeof(int));
     st = (GState*)stb;
     alldone = (int*)(stb + sizeof(GState) * c);
+    allnop = alldone + 1;
     H = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * rs * c);
+    Hraw = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * rs * c);
     g = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
     h = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
     y = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * c);
     cs = (cx<double>*)take(sizeof(cx<double>) * rs * c);
     sn = (cx<double>*)take(sizeof(cx<double>) * rs * c);
     partial = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * kBlocks * c);
+    partial2 = (cx<double>*)take(sizeof(cx<double>) * (size_t)(rs + 1) * kBlocks * c);
     npart = (double*)take(sizeof(double) * kBlocks * c);
     V = (cx<T>*)take(sizeof(cx<T>) * (size_t)(rs + 1) * N * c);
     r = (cx<T>*)take(sizeof(cx<T>) * N * c);
@@ -475,8 +661,17 @@ struct Krylov {
     awork = (cx<T>*)take(sizeof(cx<T>) * inter_elems<T>(n, nb) * (size_t)inters);
     return base;
   }
-  // The operator's skip flag: the instance's own stop flag, or "all stopped".
-  const int* skip() const { return count == 1 ? &st[0].done : alldone; }
+  // The operator's skip flag: the instance's own stop flag, or "all stopped"
+  // (with delayed reorthogonalisation: no instance needs the next operator).
+  const int* skip() const {
+#if WS_LS_DCGS2
+    return count == 1 ? &st[0].nop : allnop;
+#else
+    return count == 1 ? &st[0].done : alldone;
+#endif
+  }
+  // Every instance has stopped (the host's poll).
+  const int* stopped() const { return count == 1 ? &st[0].done : alldone; }
 };
 
 struct Counters {
@@ -546,6 +741,19 @@ hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
   for (int j = j0; j < j0 + c; ++j) {
     cx<T>* vj = K.V + (size_t)j * cnt * N;
     cx<T>* w = K.V + (size_t)(j + 1) * cnt * N;
+#if WS_LS_DCGS2
+    const int last = j == K.restart ? 1 : 0;         // the operator-free step that ends a full cycle
+    if (!last) {
+      hipError_t e = op(vj, w, K.skip());
+      if (e != hipSuccess) return e;
+    }
+    k_dots_d<T><<<dim3(nbd, j + 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, last, K.partial, K.partial2, K.pstride(),
+                                                           K.st);
+    k_update_d<T><<<dim3(nbu, 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, last, K.partial, K.partial2, K.pstride(),
+                                                         nbd, K.H, K.Hraw, K.hstride(), ldh, K.cs, K.sn, K.restart,
+                                                         K.g, K.st);
+    if (cnt > 1) k_all_done<<<1, 64, 0, s>>>(K.st, cnt, K.alldone, K.allnop);
+#else
     hipError_t e = op(vj, w, K.skip());
     if (e != hipSuccess) return e;
     for (int pass = 0; pass < 2; ++pass) {   // classical Gram-Schmidt, twice
@@ -555,7 +763,8 @@ hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
     }
     k_normalise_givens<T><<<dim3(nbu, 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, K.npart, nbu, K.H, K.hstride(), ldh,
                                                                   K.cs, K.sn, K.restart, K.g, K.st);
-    if (cnt > 1) k_all_done<<<1, 64, 0, s>>>(K.st, cnt, K.alldone);
+    if (cnt > 1) k_all_done<<<1, 64, 0, s>>>(K.st, cnt, K.alldone, nullptr);
+#endif
   }
   return hipGetLastError();
 }
@@ -684,21 +893,24 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
     }
     if (!active) return 0;
     ctl.active = active;
-    k_cycle_start<T><<<dim3(grid_for(N), 1, C), kThreads, 0, s>>>(rcur, K.V, N, C, K.H, K.hstride(), K.g,
-                                                                    K.restart + 1, K.st, ctl);
-    if (C > 1) k_all_done<<<1, 64, 0, s>>>(K.st, C, K.alldone);
+    k_cycle_start<T><<<dim3(grid_for(N), 1, C), kThreads, 0, s>>>(rcur, K.V, N, C, K.H, WS_LS_DCGS2 ? K.Hraw : nullptr,
+                                                                    K.hstride(), K.g, K.restart + 1, K.st, ctl);
+    if (C > 1) k_all_done<<<1, 64, 0, s>>>(K.st, C, K.alldone, K.allnop);
+    // With delayed reorthogonalisation a cycle of `steps` columns takes one
+    // more step, which finalises the last column.
+    const int nsteps = steps + (WS_LS_DCGS2 ? 1 : 0);
     int nsnap = 0;
-    for (int j0 = 0; j0 < steps; j0 += kChunk) {
-      const int c = std::min(kChunk, steps - j0);
+    for (int j0 = 0; j0 < nsteps; j0 += kChunk) {
+      const int c = std::min(kChunk, nsteps - j0);
       if ((*herr = run_chunk(p, K, op, op_id, j0, c, s, graphs)) != hipSuccess) return -1;
       if (nsnap < kMaxSnap) {
-        if ((*herr = hipMemcpyAsync(&snap.pinned[nsnap], K.skip(), sizeof(int), hipMemcpyDeviceToHost, s)) !=
+        if ((*herr = hipMemcpyAsync(&snap.pinned[nsnap], K.stopped(), sizeof(int), hipMemcpyDeviceToHost, s)) !=
                 hipSuccess ||
             (*herr = hipEventRecord(snap.ev[nsnap], s)) != hipSuccess)
           return -1;
         ++nsnap;
       }
-      if (nsnap > kLag && j0 + c < steps) {
+      if (nsnap > kLag && j0 + c < nsteps) {
         const int k = nsnap - 1 - kLag;
         if ((*herr = hipEventSynchronize(snap.ev[k])) != hipSuccess) return -1;
         if (snap.pinned[k]) break;
@@ -709,7 +921,7 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
     unsigned long long upd = 0;
     for (int i = 0; i < C; ++i) {
       if (!in_mask_host(active, i)) continue;
-      cnt[i].matvecs += hs[i].kused;
+      cnt[i].matvecs += WS_LS_DCGS2 ? hs[i].mv : hs[i].kused;
       cnt[i].iterations += hs[i].kused;
       if (hs[i].bad) {
         out[i].status = WS_LS_BREAKDOWN;

@@ -19,6 +19,17 @@ def test_period3_pass_model():
     assert pb == [n * n * s + inter, 2 * inter + (3 * n // 2 + 1) ** 2 * s, inter + n * n * s]
 
 
+def test_ls_bytes_model():
+    # delayed reorthogonalisation: step j reads j basis vectors, u_j and w twice and writes v_j, u_{j+1}
+    n, s = 256, 8
+    vec = 2 * n * n * s
+    assert bench.ls_step_bytes(n, s, 0) == 6 * vec and bench.ls_step_bytes(n, s, 10) == 26 * vec
+    info = type("I", (), dict(iterations=3, matvecs=5, refinements=0))()
+    # one cycle of 3 columns: 4 steps, 5 operator applications (4 in the cycle, 1 true residual)
+    expect = 5 * 27 * n * n * s + sum(bench.ls_step_bytes(n, s, j) for j in range(4)) + 3 * vec
+    assert bench.ls_solve_bytes(n, info, False) == expect
+
+
 def test_table_bytes_is_the_column_pass_extra():
     # the moment table is what the column pass reads beyond the intermediate it reads and writes
     for n, s, b in ((64, 8, 2), (2048, 8, 2), (2048, 4, 2), (1024, 8, 3)):
