@@ -278,7 +278,7 @@ def ls_solve_bytes(n: int, info, mixed: bool, restart: int = 50) -> float:
     return total
 
 
-def run_ls_bench(api, torch, ns, kappas, repeats):
+def run_ls_bench(api, torch, ns, kappas, repeats, fs_leg=True):
     import synth
     lat = {"fp64": [], "fp32+ir": []}
     detail = []
@@ -309,8 +309,9 @@ def run_ls_bench(api, torch, ns, kappas, repeats):
                     f"rel_res={info.rel_residual:.2e}, status={info.status}, {gb / dt:.0f} GB/s model")
     # Fourier-smoothed solves (Example 9): m = -1 in the disc of radius 0.25 about the centre, 0 outside,
     # through ls_solve_fs with m_tilde = -1 and psi ramping from the disc to r = 0.39.
-    lat["fp64+fs"] = []
-    for n in ns:
+    if fs_leg:
+        lat["fp64+fs"] = []
+    for n in (ns if fs_leg else []):
         for kappa in kappas:
             mt = torch.full((n, n), -1.0, dtype=torch.float64, device="cuda")
             ui = torch.as_tensor(synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + int(kappa)))).cuda()
@@ -334,7 +335,7 @@ def run_ls_bench(api, torch, ns, kappas, repeats):
     # The smoothed disc at the largest kappa stalls GMRES(50) restarts (a strongly resonant scatterer);
     # the same solve with a longer restart, for comparison (not part of the p50/p99 above).
     restart_cmp = []
-    if 80.0 in kappas and 512 in ns:
+    if fs_leg and 80.0 in kappas and 512 in ns:
         n, kappa = 512, 80.0
         mt = torch.full((n, n), -1.0, dtype=torch.float64, device="cuda")
         ui = torch.as_tensor(synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + int(kappa)))).cuda()
@@ -744,6 +745,7 @@ def main(argv=None):
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="processes of the pooled CPU baseline (at most the host's cores)")
     ap.add_argument("--no-ls", action="store_true")
+    ap.add_argument("--no-ls-fs", action="store_true", help="skip the Fourier-smoothed LS solves")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--ls-n", type=int, nargs="*", default=[256, 512, 1024])
     ap.add_argument("--ls-kappa", type=float, nargs="*", default=[20.0, 40.0, 80.0])
@@ -852,7 +854,7 @@ def main(argv=None):
     ls = None
     if not args.no_ls:
         log("LS latency bench ...")
-        ls = run_ls_bench(api, torch, args.ls_n, args.ls_kappa, args.ls_repeats)
+        ls = run_ls_bench(api, torch, args.ls_n, args.ls_kappa, args.ls_repeats, not args.no_ls_fs)
         if args.ls_batch > 1:
             log("batched LS bench ...")
             ls["batched"] = run_ls_batch_bench(api, torch, [256, 512], 40.0, args.ls_batch, args.ls_repeats)
