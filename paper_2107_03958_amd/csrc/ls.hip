@@ -415,24 +415,36 @@ __global__ void k_all_done(const GState* st, int count, int* flag, int* flag_nop
 }
 
 // y = R^-1 g over the kused x kused upper triangle (instance s = blockIdx.x, in mask).
+// Back substitution by columns: once y_i is known, the threads subtract
+// column i's contribution from the rows above it in parallel (one block of
+// one wave per instance; kused <= restart <= 200).
 __global__ void k_trisolve(const cx<double>* H, size_t hstride, int ldh, const cx<double>* g, int gstride,
                            cx<double>* y, const GState* st, unsigned long long mask) {
   const int s = blockIdx.x;
-  if (threadIdx.x != 0 || !in_mask(mask, s)) return;
+  if (!in_mask(mask, s)) return;
+  __shared__ cx<double> acc[256];
+  __shared__ cx<double> yk;
   const cx<double>* Hs = H + s * hstride;
   const cx<double>* gs = g + (size_t)s * gstride;
   cx<double>* ys = y + (size_t)s * gstride;
   const int k = st[s].kused;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) acc[i] = gs[i];
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    cx<double> acc = gs[i];
-    for (int l = i + 1; l < k; ++l) {
-      const cx<double> h = Hs[(size_t)l * ldh + i];
-      acc.x -= h.x * ys[l].x - h.y * ys[l].y;
-      acc.y -= h.x * ys[l].y + h.y * ys[l].x;
+    if (threadIdx.x == 0) {
+      const cx<double> d = Hs[(size_t)i * ldh + i], a = acc[i];
+      const double dd = d.x * d.x + d.y * d.y;
+      const cx<double> yi = {(a.x * d.x + a.y * d.y) / dd, (a.y * d.x - a.x * d.y) / dd};
+      ys[i] = yi;
+      yk = yi;
     }
-    const cx<double> d = Hs[(size_t)i * ldh + i];
-    const double dd = d.x * d.x + d.y * d.y;
-    ys[i] = {(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+    __syncthreads();
+    const cx<double> yi = yk;
+    for (int r = threadIdx.x; r < i; r += blockDim.x) {
+      const cx<double> h = Hs[(size_t)i * ldh + r];
+      acc[r] = {acc[r].x - (h.x * yi.x - h.y * yi.y), acc[r].y - (h.x * yi.y + h.y * yi.x)};
+    }
+    __syncthreads();
   }
 }
 
@@ -931,7 +943,7 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
       }
     }
     if (upd) {
-      k_trisolve<<<C, 1, 0, s>>>(K.H, K.hstride(), K.restart + 1, K.g, K.restart + 1, K.y, K.st, upd);
+      k_trisolve<<<C, 64, 0, s>>>(K.H, K.hstride(), K.restart + 1, K.g, K.restart + 1, K.y, K.st, upd);
       k_xupdate<T, T><<<dim3(kBlocks, 1, C), kThreads, 0, s>>>(x, K.V, N, C, K.y, K.restart + 1, K.st, 1.0, upd);
     }
     if (!active) return 0;
