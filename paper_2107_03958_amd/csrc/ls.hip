@@ -45,6 +45,16 @@
 #ifndef WS_LS_DCGS2
 #define WS_LS_DCGS2 1
 #endif
+// Dot-product blocks per basis vector: min(WS_LS_NBD_MAX, max(8, N /
+// WS_LS_NBD_DIV)).  Over the LS bench cases (n = 256-1024, kappa = 20-80,
+// FP64 and FP32 + refinement) the sum of solve times was 58.3 ms with
+// (64, 4096), 64.8 with (32, 8192), 55.4 with (128, 2048), 56.3 with (256, 1024).
+#ifndef WS_LS_NBD_MAX
+#define WS_LS_NBD_MAX 128
+#endif
+#ifndef WS_LS_NBD_DIV
+#define WS_LS_NBD_DIV 2048
+#endif
 
 namespace ws {
 
@@ -749,7 +759,7 @@ hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
   const int ldh = K.restart + 1;
   const int nbu = grid_for(N);
   // dot-product blocks per vector: few, so every update block can finish the sums cheaply
-  const int nbd = (int)std::min<size_t>(64, std::max<size_t>(8, N / 4096));
+  const int nbd = (int)std::min<size_t>(WS_LS_NBD_MAX, std::max<size_t>(8, N / WS_LS_NBD_DIV));
   for (int j = j0; j < j0 + c; ++j) {
     cx<T>* vj = K.V + (size_t)j * cnt * N;
     cx<T>* w = K.V + (size_t)(j + 1) * cnt * N;
