@@ -749,9 +749,10 @@ HostSnapshots& snapshots() {
   return h;
 }
 
-// Steps [j0, j0 + c) of an Arnoldi cycle of every instance: the operator,
-// classical Gram-Schmidt twice (FP64 coefficients), Givens rotation,
-// normalisation.
+// Steps [j0, j0 + c) of an Arnoldi cycle of every instance: the operator and
+// Gram-Schmidt with one reorthogonalisation (FP64 coefficients; delayed into
+// the next step's reduction, or, with WS_LS_DCGS2 = 0, classical Gram-Schmidt
+// twice with normalisation), and the Givens rotation of a final column.
 template <typename T, typename OpF>
 hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
   const size_t N = K.N;
