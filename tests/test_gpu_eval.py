@@ -105,6 +105,27 @@ def test_eval_n2048_sampled(api):
     assert np.max(np.abs(got - ref)) <= TOL * np.max(np.abs(ref))
 
 
+@pytest.mark.slow
+def test_eval_period3_n2048(api):
+    # period 3 at the largest grid (6144^2 spectrum, split-exchange column tiles): off-grid targets
+    # against the oracle, on-grid targets against conv_apply (itself checked against the oracle there)
+    n, b = 2048, 3
+    a3 = (b + math.sqrt(2) / 2 - 0.5) / 2
+    u = synth.full_support_density(n, synth.SEED_FULL_SUPPORT + 5)
+    ut = torch.as_tensor(u).cuda()
+    plan = api.ConvPlan(n=n, b=b, **plan_kwargs("log"))
+    pts = _targets(4, 17)
+    got = plan.eval(ut, torch.as_tensor(pts).cuda()).cpu().numpy()
+    ref = scheme.apply_at(u, moments.ghat_table(oracle_kernel("log"), n, b, a3), b, pts)
+    assert np.max(np.abs(got - ref)) <= TOL * np.max(np.abs(ref))
+    full = plan.apply(ut[None].clone())[0].cpu().numpy()
+    idx = np.random.default_rng(6).integers(0, n, size=(32, 2))
+    on = plan.eval(ut, torch.as_tensor(idx.astype(np.float64) / n).cuda()).cpu().numpy()
+    scale = np.max(np.abs(full))
+    assert np.max(np.abs(on.real - full[idx[:, 0], idx[:, 1]])) <= TOL * scale
+    assert np.max(np.abs(on.imag)) <= TOL * scale
+
+
 def test_eval_edge_cases(api):
     from paper_2107_03958_amd import _lib as L
     n = 32
