@@ -84,6 +84,10 @@ class Engine:
                           contrast.data_ptr(), out.data_ptr(), float(tol), int(restart), int(max_matvecs))
         return req, (u_inc, contrast, out)
 
+    def submit_request(self, req: L.WsRequest, held) -> int:
+        """Submit a request built by request_apply or request_ls (its buffers held until it completes)."""
+        return self._submit(req, held)
+
     def submit_apply(self, kernel: dict, density: torch.Tensor, out: torch.Tensor | None = None) -> int:
         req, held = self.request_apply(kernel, density, out)
         return self._submit(req, held)

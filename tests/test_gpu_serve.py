@@ -51,19 +51,27 @@ def _mix_requests():
     return reqs
 
 
-def _submit(eng, r):
+def _request(eng, r):
+    """The engine request of r, its page-locked inputs and output allocated."""
     if r[0] == "apply":
         kind, kname, n, u = r
         dt = torch.complex128 if np.iscomplexobj(u) else torch.float64
-        return eng.submit_apply(plan_kwargs(kname), _pinned(u, dt))
+        return eng.request_apply(plan_kwargs(kname), _pinned(u, dt))
     kind, kname, n, m, ui, kappa = r
-    return eng.submit_ls(kappa, _pinned(m, torch.float64), _pinned(ui, torch.complex128), tol=1e-10, restart=30)
+    return eng.request_ls(kappa, _pinned(m, torch.float64), _pinned(ui, torch.complex128), tol=1e-10, restart=30)
+
+
+def _submit(eng, r):
+    return eng.submit_request(*_request(eng, r))
 
 
 def _run(eng, reqs, together):
     outs = []
     if together:
-        tickets = [_submit(eng, r) for r in reqs]
+        # every request prepared first (page-locked buffers take time to allocate),
+        # then submitted back to back, so the engine finds them pending together
+        prepared = [_request(eng, r) for r in reqs]
+        tickets = [eng.submit_request(req, held) for req, held in prepared]
         outs = [eng.wait(t, timeout=120) for t in tickets]
     else:
         for r in reqs:
