@@ -862,12 +862,12 @@ struct Outcome {
 
 // GMRES(restart) for Op x_s = rhs_s, s < count, from x_s = 0 (x zeroed by the
 // caller), for the instances in `run` (the others are left alone).  Instance s
-// stops when its true residual ||rhs_s - Op x_s|| <= tol_rel ||rhs_s||, at
+// stops when its true residual ||rhs_s - Op x_s|| <= tol_rel[s] ||rhs_s||, at
 // max_mv[s] operator applications (counted in cnt[s]), or on a non-finite
 // value.  Returns 0, or -1 with *herr set.
 template <typename T, typename OpF>
-int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* rhs, cx<T>* x, double tol_rel,
-          const std::vector<int>& max_mv, unsigned long long run, std::vector<Counters>& cnt,
+int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* rhs, cx<T>* x,
+          const std::vector<double>& tol_rel, const std::vector<int>& max_mv, unsigned long long run, std::vector<Counters>& cnt,
           std::vector<Outcome>& out, hipStream_t s, bool graphs, hipError_t* herr) {
   const size_t N = K.N;
   const int C = K.count;
@@ -888,7 +888,7 @@ int gmres(const Plan& p, Krylov<T>& K, OpF op, const void* op_id, const cx<T>* r
       out[i] = {WS_LS_CONVERGED, 0.0};
     } else {
       active |= 1ull << i;
-      tol_abs[i] = tol_rel * rhsn[i];
+      tol_abs[i] = tol_rel[i] * rhsn[i];
     }
   }
   rn = rhsn;
@@ -1036,7 +1036,8 @@ int ls_run_on(const Plan& p, int count, const double* contrast, const cx<double>
     };
     k_zero<double><<<grid_for(NC), kThreads, 0, s>>>(u_out, NC);
     const std::vector<int> budget(count, max_matvecs);
-    if (gmres<double>(p, K, op, contrast, u_inc, u_out, tol, budget, all, cnt, out, s, graphs, &he) < 0)
+    if (gmres<double>(p, K, op, contrast, u_inc, u_out, std::vector<double>(count, tol), budget, all, cnt, out, s,
+                      graphs, &he) < 0)
       goto device_error;
   } else {
     Krylov<float> K32;
@@ -1067,7 +1068,11 @@ int ls_run_on(const Plan& p, int count, const double* contrast, const cx<double>
       const cx<double>* r64 = u_inc;
       rn = fn;
       std::vector<double> prev(count, HUGE_VAL);
-      const double inner_tol = 1e-5;
+      // Inner tolerance of instance s: 1e-5, or the reduction its refinement
+      // still needs (with a margin) when that is less, so that the last
+      // refinement stops early.  Per instance, so a batched solve takes the
+      // steps it takes alone.
+      const double kInnerTol = 1e-5, kMargin = 0.3;
       std::vector<GState> hs(count);
       while (true) {
         std::vector<int> budget(count, 0);
@@ -1087,6 +1092,9 @@ int ls_run_on(const Plan& p, int count, const double* contrast, const cx<double>
           budget[i] = max_matvecs - cnt[i].matvecs;
         }
         if (!active) break;
+        std::vector<double> inner_tol(count, kInnerTol);
+        for (int i = 0; i < count; ++i)
+          if (in_mask_host(active, i)) inner_tol[i] = std::max(kInnerTol, kMargin * tol * fn[i] / rn[i]);
         k_convert_unit<double, float><<<dim3(grid_for(N), 1, count), kThreads, 0, s>>>(r64, rhs32, N, K64.st);
         k_zero<float><<<grid_for(NC), kThreads, 0, s>>>(delta, NC);
         std::vector<Outcome> inner(count);
