@@ -3,12 +3,18 @@
 // sum).  The coefficients c(k) = ghat(k) uhat_{e,n}(k) on F_n come from the
 // spectrum pass (apply_f64.hip); this file sums the series
 //     (A_n u)(x) = sum_{k in F_n} c(k) exp(2 pi i k.x / b)
-// directly at each target: O(|F_n|) per target, for callers with modest
-// numbers of scattered points.  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
+// at each target: O(|F_n|) per target, for callers with modest numbers of
+// scattered points.  The sum over k2 is a dense complex matrix product,
+//     P(k1, t) = sum_{k2} c(k1, k2) exp(2 pi i k2 x2_t / b),
+// taken by rocBLAS (ZGEMM, FP64 matrix cores) over tiles of targets; a kernel
+// forms the exponential matrix, another the final sum over k1 with
+// exp(2 pi i k1 x1_t / b).  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
 // value is complex even for real u and a real kernel, except on the grid.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include <cmath>
 #include <cstdint>
@@ -21,9 +27,7 @@ namespace ws {
 namespace {
 
 constexpr int kEvalThreads = 256;
-constexpr int kEvalTargets = 16;         // targets per block: every spectrum read serves this many
-constexpr int kE1Rows = 64;              // rows k1 whose exponentials the block shares through LDS at a time
-constexpr int kEvalCols = 2;             // columns per thread: every LDS read serves this many
+constexpr size_t kTileBytes = 64u << 20;   // each of the two target-tile buffers
 
 __global__ void k_real_to_cplx(const double* __restrict__ u, cx<double>* __restrict__ v, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -38,111 +42,74 @@ __device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
   return {c, s};
 }
 
-// Block (x, y): kEvalTargets targets, and the slice y of the columns k2:
-// thread t takes the kEvalCols columns k2 = (y + j gridDim.y) kEvalCols 256 +
-// c 256 + t, c < kEvalCols, in rounds j (every thread runs the same rounds;
-// columns past nb count as zero).  Per column, the sum over k1 of
-// c(k1, k2) exp(2 pi i k1 x1/b), with the row exponentials of every target
-// computed once per block, kE1Rows rows at a time, into LDS (every thread
-// reads the same entries, each read serving kEvalCols columns), times
-// exp(2 pi i k2 x2/b); then a block reduction per target into
-// part[y * count + target] (with one slice, straight into the result).
-__global__ __launch_bounds__(kEvalThreads, 2) void k_eval(const cx<double>* __restrict__ spec, int nb, double inv_b,
-                                                          const double* __restrict__ targets, int count,
-                                                          cx<double>* __restrict__ part) {
-  __shared__ cx<double> e1s[kE1Rows][kEvalTargets];
-  __shared__ double xs[2][kEvalTargets];
-  __shared__ cx<double> red[kEvalTargets][kEvalThreads / 64];
-  const int t0 = blockIdx.x * kEvalTargets;
-  if (threadIdx.x < kEvalTargets) {
-    const int ti = t0 + (int)threadIdx.x < count ? t0 + (int)threadIdx.x : count - 1;
-    xs[0][threadIdx.x] = targets[2 * (size_t)ti] * inv_b;
-    xs[1][threadIdx.x] = targets[2 * (size_t)ti + 1] * inv_b;
-  }
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  constexpr int nwaves = kEvalThreads / 64;
-  if (threadIdx.x < kEvalTargets * nwaves) red[threadIdx.x / nwaves][threadIdx.x % nwaves] = {0.0, 0.0};
-  __syncthreads();
-  constexpr int span = kEvalCols * kEvalThreads;       // columns of one block round
-  const int rounds = (nb + span * gridDim.y - 1) / (span * gridDim.y);
-  for (int jc = 0; jc < rounds; ++jc) {
-    const int base = (blockIdx.y + jc * gridDim.y) * span + threadIdx.x;
-    bool ok[kEvalCols];
-#pragma unroll
-    for (int c = 0; c < kEvalCols; ++c) ok[c] = base + c * kEvalThreads < nb;
-    cx<double> acc[kEvalCols][kEvalTargets];
-#pragma unroll
-    for (int c = 0; c < kEvalCols; ++c)
-#pragma unroll
-      for (int g = 0; g < kEvalTargets; ++g) acc[c][g] = {0.0, 0.0};
-    for (int c0 = 0; c0 < nb; c0 += kE1Rows) {
-      const int rows = nb - c0 < kE1Rows ? nb - c0 : kE1Rows;
-      __syncthreads();                                  // the previous rows' reads are done
-      for (int idx = threadIdx.x; idx < rows * kEvalTargets; idx += kEvalThreads) {
-        const int r = idx / kEvalTargets, g = idx % kEvalTargets;
-        e1s[r][g] = expo(c0 + r, nb, xs[0][g]);
-      }
-      __syncthreads();
-      for (int r = 0; r < rows; ++r) {
-        cx<double> cv[kEvalCols];
-#pragma unroll
-        for (int c = 0; c < kEvalCols; ++c)
-          cv[c] = ok[c] ? spec[(size_t)(c0 + r) * nb + base + c * kEvalThreads] : cx<double>{0.0, 0.0};
-#pragma unroll
-        for (int g = 0; g < kEvalTargets; ++g) {
-          const cx<double> e = e1s[r][g];
-#pragma unroll
-          for (int c = 0; c < kEvalCols; ++c) acc[c][g] = acc[c][g] + cmul(cv[c], e);
-        }
-      }
-    }
-    // this round's columns times exp(2 pi i k2 x2/b), summed over the block's
-    // threads into red (one wave sum per target, added by lane 0)
-#pragma unroll
-    for (int g = 0; g < kEvalTargets; ++g) {
-      cx<double> v{0.0, 0.0};
-#pragma unroll
-      for (int c = 0; c < kEvalCols; ++c)
-        if (ok[c]) v = v + cmul(acc[c][g], expo(base + c * kEvalThreads, nb, xs[1][g]));
-      double re = v.x, im = v.y;
-      for (int off = 32; off > 0; off >>= 1) {
-        re += __shfl_down(re, off, 64);
-        im += __shfl_down(im, off, 64);
-      }
-      if (lane == 0) red[g][wave] = red[g][wave] + cx<double>{re, im};
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < kEvalTargets && t0 + (int)threadIdx.x < count) {
-    cx<double> s{0.0, 0.0};
-    for (int w = 0; w < kEvalThreads / 64; ++w) s = s + red[threadIdx.x][w];
-    part[(size_t)blockIdx.y * count + t0 + threadIdx.x] = s;
+// E[t nb + q] = exp(2 pi i k(q) x2_t / b) for the tc targets from t0 (column t
+// of a column-major nb x tc matrix).
+__global__ __launch_bounds__(kEvalThreads) void k_eval_e2(const double* __restrict__ targets, int t0, int tc, int nb,
+                                                          double inv_b, cx<double>* __restrict__ E) {
+  const size_t total = (size_t)tc * nb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(i / nb), q = (int)(i % nb);
+    E[i] = expo(q, nb, targets[2 * (size_t)(t0 + t) + 1] * inv_b);
   }
 }
 
-// out[t] = sum over the slices of part[s * count + t], in slice order.
-__global__ void k_eval_sum(const cx<double>* __restrict__ part, int slices, int count, cx<double>* __restrict__ out) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-    cx<double> s = part[t];
-    for (int y = 1; y < slices; ++y) s = s + part[(size_t)y * count + t];
-    out[t] = s;
+// out[t0 + t] = sum_q exp(2 pi i k(q) x1_t / b) P[t nb + q]: one block per
+// target, the block's partial sums added in a fixed order.
+__global__ __launch_bounds__(kEvalThreads) void k_eval_dot(const cx<double>* __restrict__ P, int nb, double inv_b,
+                                                           const double* __restrict__ targets, int t0,
+                                                           cx<double>* __restrict__ out) {
+  __shared__ cx<double> red[kEvalThreads / 64];
+  const int t = blockIdx.x;
+  const double x1 = targets[2 * (size_t)(t0 + t)] * inv_b;
+  const cx<double>* col = P + (size_t)t * nb;
+  double re = 0.0, im = 0.0;
+  for (int q = threadIdx.x; q < nb; q += kEvalThreads) {
+    const cx<double> v = cmul(expo(q, nb, x1), col[q]);
+    re += v.x;
+    im += v.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_down(re, off, 64);
+    im += __shfl_down(im, off, 64);
+  }
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = {re, im};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    cx<double> s = red[0];
+    for (int w = 1; w < kEvalThreads / 64; ++w) s = s + red[w];
+    out[t0 + t] = s;
   }
 }
 
-// Column slices per target group: enough blocks for about 1024 in all, at most
-// one slice per block round of columns, and partial sums that fit in `room` elements.
-int eval_slices(int count, int nb, size_t room) {
-  const int groups = (count + kEvalTargets - 1) / kEvalTargets;
-  int s = (1024 + groups - 1) / groups;
-  s = std::min(s, std::max(1, nb / (kEvalCols * kEvalThreads)));
-  while (s > 1 && (size_t)s * count > room) --s;
-  return std::max(1, s);
+// Targets per tile: as many as fit kTileBytes in an nb x tile complex matrix
+// (at most 4096, a multiple of 64, at least 64).
+int eval_tile(int nb) {
+  int t = (int)std::min<size_t>(4096, kTileBytes / (sizeof(cx<double>) * (size_t)nb));
+  t -= t % 64;
+  return std::max(t, 64);
+}
+
+// One rocBLAS handle per device, made on first use with that device current;
+// calls that share it hold the lock while they bind their stream and enqueue.
+std::mutex& blas_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+rocblas_handle blas_handle(int dev, rocblas_status* st) {
+  static rocblas_handle h[64] = {};
+  *st = rocblas_status_success;
+  if (dev < 0 || dev >= 64) {
+    *st = rocblas_status_invalid_value;
+    return nullptr;
+  }
+  if (!h[dev]) *st = rocblas_create_handle(&h[dev]);
+  return *st == rocblas_status_success ? h[dev] : nullptr;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct EvalWork {
-  size_t widen, inter, spec, total;
+  size_t widen, inter, spec, tile, total;   // tile: bytes of each of the two target-tile matrices
 };
 
 EvalWork eval_work(const Plan& p) {
@@ -151,7 +118,8 @@ EvalWork eval_work(const Plan& p) {
   w.widen = p.cplx ? 0 : align256(n * n * sizeof(cx<double>));
   w.inter = align256(inter_elems<double>((int)n, (int)nb) * sizeof(cx<double>));
   w.spec = align256(nb * nb * sizeof(cx<double>));
-  w.total = w.widen + w.inter + w.spec;
+  w.tile = align256(nb * (size_t)eval_tile((int)nb) * sizeof(cx<double>));
+  w.total = w.widen + w.inter + w.spec + 2 * w.tile;
   return w;
 }
 
@@ -202,16 +170,39 @@ int conv_eval(ws_plan_t plan, const void* density, int count, const double* targ
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = ws::launch_spectrum(p, v, inter, spec, s);
   if (e == hipSuccess) {
-    // the row-pass intermediate is free once the spectrum exists: it holds the partial sums
-    const int slices = ws::eval_slices(count, p.nb, w.inter / sizeof(ws::cx<double>));
-    const dim3 grid((count + ws::kEvalTargets - 1) / ws::kEvalTargets, slices);
+    // P(:, t) = C E(:, t) over tiles of targets: C is the row-major spectrum,
+    // i.e. the transpose of the column-major matrix rocBLAS sees
+    ws::cx<double>* E = reinterpret_cast<ws::cx<double>*>(base + w.widen + w.inter + w.spec);
+    ws::cx<double>* P = reinterpret_cast<ws::cx<double>*>(base + w.widen + w.inter + w.spec + w.tile);
     ws::cx<double>* res = static_cast<ws::cx<double>*>(out);
-    ws::k_eval<<<grid, ws::kEvalThreads, 0, s>>>(spec, p.nb, 1.0 / p.b, targets, count, slices > 1 ? inter : res);
-    if (slices > 1) {
-      const int blocks = std::min((count + 255) / 256, 1024);
-      ws::k_eval_sum<<<blocks, 256, 0, s>>>(inter, slices, count, res);
+    const int nb = p.nb, tile = ws::eval_tile(nb);
+    const double inv_b = 1.0 / p.b;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    for (int t0 = 0; e == hipSuccess && t0 < count; t0 += tile) {
+      const int tc = std::min(tile, count - t0);
+      const size_t elems = (size_t)tc * nb;
+      ws::k_eval_e2<<<(unsigned)std::min<size_t>((elems + 255) / 256, 8192), ws::kEvalThreads, 0, s>>>(
+          targets, t0, tc, nb, inv_b, E);
+      e = hipGetLastError();
+      if (e != hipSuccess) break;
+      {
+        std::lock_guard<std::mutex> lk(ws::blas_mutex());
+        rocblas_status bs;
+        rocblas_handle h = ws::blas_handle(dev, &bs);
+        if (bs == rocblas_status_success) bs = rocblas_set_stream(h, s);
+        const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+        if (bs == rocblas_status_success)
+          bs = rocblas_zgemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, tc, nb, &one,
+                             reinterpret_cast<const rocblas_double_complex*>(spec), nb,
+                             reinterpret_cast<const rocblas_double_complex*>(E), nb, &zero,
+                             reinterpret_cast<rocblas_double_complex*>(P), nb);
+        if (bs != rocblas_status_success)
+          return ws::set_last_error(WS_EDEVICE, std::string("conv_eval: rocBLAS: ") + rocblas_status_to_string(bs));
+      }
+      ws::k_eval_dot<<<tc, ws::kEvalThreads, 0, s>>>(P, nb, inv_b, targets, t0, res);
+      e = hipGetLastError();
     }
-    e = hipGetLastError();
   }
   if (e != hipSuccess) return ws::set_last_error(WS_EDEVICE, std::string("conv_eval: ") + hipGetErrorString(e));
   return WS_OK;
