@@ -273,8 +273,16 @@ __global__ __launch_bounds__(kThreads) void k_normalise_givens(cx<T>* V, size_t 
 // step after its direction's operator, so the stop test lags one step, and a
 // cycle of m columns ends with an operator-free step j = m.
 
-// Partials of (a_i, b_i) for rows i < j, and of (alpha, beta) for row j (grid
-// nbd x (j + 1) x count).  last: step j = restart, no w.
+// Partials of (a_i, b_i) for rows i < j, and of (alpha, beta) for row j: a
+// block takes WS_LS_DOT_ROWS consecutive rows of one slice of the elements,
+// reading u_j and w once for them (grid nbd x ceil((j + 1) / WS_LS_DOT_ROWS)
+// x count).  last: step j = restart, no w.  One row per block measured best:
+// the LS bench cases summed to 51.8 ms with 1, 53.8 with 2, 60.4 with 4 (fewer
+// blocks along y leave the chip short of work).
+#ifndef WS_LS_DOT_ROWS
+#define WS_LS_DOT_ROWS 1
+#endif
+constexpr int kDotRows = WS_LS_DOT_ROWS;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dots_d(const cx<T>* V, size_t N, int count, int j, int last,
                                                      cx<double>* pa, cx<double>* pb, size_t pstride,
@@ -282,31 +290,34 @@ __global__ __launch_bounds__(kThreads) void k_dots_d(const cx<T>* V, size_t N, i
   const int s = blockIdx.z;
   if (st[s].done) return;
   __shared__ double sh[kThreads];
-  const int i = blockIdx.y;
-  const cx<T>* vi = V + ((size_t)i * count + s) * N;      // row j: u_j itself
+  const int i0 = blockIdx.y * kDotRows;
+  const int rows = min(kDotRows, j + 1 - i0);
   const cx<T>* u = V + ((size_t)j * count + s) * N;
   const cx<T>* w = last ? nullptr : V + ((size_t)(j + 1) * count + s) * N;
-  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  double acc[4 * kDotRows];
+#pragma unroll
+  for (int q = 0; q < 4 * kDotRows; ++q) acc[q] = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N; e += (size_t)gridDim.x * blockDim.x) {
-    const cx<double> a = up(vi[e]), x = up(u[e]);
-    ar += a.x * x.x + a.y * x.y;
-    ai += a.x * x.y - a.y * x.x;
-    if (w) {
-      const cx<double> y = up(w[e]);
-      br += a.x * y.x + a.y * y.y;
-      bi += a.x * y.y - a.y * y.x;
+    const cx<double> x = up(u[e]);
+    const cx<double> y = w ? up(w[e]) : cx<double>{0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kDotRows; ++r) {
+      if (r < rows) {
+        const cx<double> a = up(V[((size_t)(i0 + r) * count + s) * N + e]);   // row j: u_j itself
+        acc[4 * r] += a.x * x.x + a.y * x.y;
+        acc[4 * r + 1] += a.x * x.y - a.y * x.x;
+        acc[4 * r + 2] += a.x * y.x + a.y * y.y;
+        acc[4 * r + 3] += a.x * y.y - a.y * y.x;
+      }
     }
   }
-  ar = block_sum(ar, sh);
-  ai = block_sum(ai, sh);
-  if (w) {
-    br = block_sum(br, sh);
-    bi = block_sum(bi, sh);
-  }
-  if (threadIdx.x == 0) {
-    const size_t k = s * pstride + (size_t)i * gridDim.x + blockIdx.x;
-    pa[k] = {ar, ai};
-    pb[k] = {br, bi};
+#pragma unroll
+  for (int q = 0; q < 4 * kDotRows; ++q) acc[q] = block_sum(acc[q], sh);
+  if (threadIdx.x < rows) {
+    const int r = threadIdx.x;
+    const size_t k = s * pstride + (size_t)(i0 + r) * gridDim.x + blockIdx.x;
+    pa[k] = {acc[4 * r], acc[4 * r + 1]};
+    pb[k] = {acc[4 * r + 2], acc[4 * r + 3]};
   }
 }
 
@@ -770,8 +781,8 @@ hipError_t arnoldi_steps(Krylov<T>& K, OpF& op, int j0, int c, hipStream_t s) {
       hipError_t e = op(vj, w, K.skip());
       if (e != hipSuccess) return e;
     }
-    k_dots_d<T><<<dim3(nbd, j + 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, last, K.partial, K.partial2, K.pstride(),
-                                                           K.st);
+    k_dots_d<T><<<dim3(nbd, (j + kDotRows) / kDotRows, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, last, K.partial,
+                                                                                K.partial2, K.pstride(), K.st);
     k_update_d<T><<<dim3(nbu, 1, cnt), kThreads, 0, s>>>(K.V, N, cnt, j, last, K.partial, K.partial2, K.pstride(),
                                                          nbd, K.H, K.Hraw, K.hstride(), ldh, K.cs, K.sn, K.restart,
                                                          K.g, K.st);
