@@ -126,6 +126,18 @@ def test_eval_period3_n2048(api):
     assert np.max(np.abs(on.imag)) <= TOL * scale
 
 
+def test_eval_target_tiles(api):
+    # more targets than one tile of the matrix product (4096 at this size): a full tile and a
+    # ragged one of 4, against the oracle
+    n = 64
+    u = synth.smooth_density(n, 41)
+    pts = _targets(4100, 23)
+    plan = api.ConvPlan(n=n, **plan_kwargs("log"))
+    got = plan.eval(torch.as_tensor(u).cuda(), torch.as_tensor(pts).cuda()).cpu().numpy()
+    ref = scheme.apply_at(u, oracle_table("log", n), B, pts)
+    assert np.max(np.abs(got - ref)) <= TOL * np.max(np.abs(ref))
+
+
 def test_eval_edge_cases(api):
     from paper_2107_03958_amd import _lib as L
     n = 32
