@@ -82,8 +82,7 @@ typedef struct {
     int    n;               /* grid points per side on D; power of two, 16 <= n <= 2048 */
     int    b;               /* period of the extension D_e = [0,b]^2 (Section 2.1): 2, or 3 for
                                densities supported on all of D (b >= 1 + sqrt 2, Section 2.1).
-                               b = 3 is not taken by conv_apply_multi or Fourier smoothing
-                               (WS_EUNSUPPORTED) */
+                               b = 3 is not taken by Fourier smoothing (WS_EUNSUPPORTED) */
     double a;               /* truncation radius of the kernel ball B_a(0) (eq. io); <= 0 selects
                                the default (b + sqrt(2)/2 - 1/2)/2, the midpoint of the disc window
                                below.  The scheme computes the convolution only when a is at least
@@ -205,10 +204,11 @@ int conv_apply_pass(ws_plan_t plan, int pass, int batch, const void* density, vo
  * densities at density[i] (layout and element type as conv_apply) into out[i]
  * (may equal density[i]), with work[i] holding
  * min(batch[i], conv_apply_chunk(plans[i])) * work_bytes_per_density of plan i.
- * Every pass of the apply is one launch shared by all items (up to 8 items per
- * launch), so densities of different grid sizes and kernels run together;
- * each result equals what conv_apply gives for that item alone.  All plans
- * must have the same precision, period b = 2, and be all real-kernel (WS_LOG /
+ * Every pass of the apply is one launch shared by all items of one period (up
+ * to 8 items per launch; plans of period 2 and of period 3 take separate
+ * launches), so densities of different grid sizes and kernels run together;
+ * each result equals what conv_apply gives for that item alone, to rounding.
+ * All plans must have the same precision and be all real-kernel (WS_LOG /
  * WS_POWER) or all WS_HELMHOLTZ (else WS_EUNSUPPORTED); no Fourier smoothing.  Items must
  * not share work buffers.  count = 0 is a no-op. */
 int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const void* const* density,

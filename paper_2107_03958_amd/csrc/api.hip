@@ -435,7 +435,6 @@ int conv_apply_multi(int count, const ws_plan_t* plans, const int* batch, const 
       return fail(WS_EINVAL, "device buffers must be 16-byte aligned");
     if (precision < 0) precision = p->precision;
     if (cplx < 0) cplx = p->cplx ? 1 : 0;
-    if (p->b != 2) return fail(WS_EUNSUPPORTED, "conv_apply_multi takes plans of period b = 2");
     if (p->precision != precision) return fail(WS_EUNSUPPORTED, "all plans must have the same precision");
     if ((p->cplx ? 1 : 0) != cplx)
       return fail(WS_EUNSUPPORTED, "real-kernel and Helmholtz plans cannot share one call");

@@ -100,14 +100,15 @@ constexpr int kMinLogn = 4, kMaxLogn = 11;
 constexpr int kMaxLognB3 = 11;
 constexpr int kMaxSegs = 8;
 
-// Block size and LDS of each kind of pass: the largest over all sizes.
-template <typename T>
+// Block size and LDS of each kind of pass: the largest over all sizes (at
+// period B, for the several-size launches of that period).
+template <typename T, int B = 2>
 struct Blk {
   template <int... L>
   static constexpr int max_nt(int which, std::integer_sequence<int, L...>) {
     int m = 64;
-    ((m = std::max(m, which == 0 ? std::max(Cfg<T, L + kMinLogn>::NT_RH, Cfg<T, L + kMinLogn>::NT_RHF)
-                      : which == 1 ? Cfg<T, L + kMinLogn>::NT_C : Cfg<T, L + kMinLogn>::NT_RC)), ...);
+    ((m = std::max(m, which == 0 ? std::max(Cfg<T, L + kMinLogn, B>::NT_RH, Cfg<T, L + kMinLogn, B>::NT_RHF)
+                      : which == 1 ? Cfg<T, L + kMinLogn, B>::NT_C : Cfg<T, L + kMinLogn, B>::NT_RC)), ...);
     return m;
   }
   using Seq = std::make_integer_sequence<int, kMaxLogn - kMinLogn + 1>;
@@ -117,13 +118,13 @@ struct Blk {
   template <int... L>
   static constexpr int max_lds(int which, std::integer_sequence<int, L...>) {
     int m = 0;
-    ((m = std::max(m, which == 0 ? std::max((RH / Cfg<T, L + kMinLogn>::NT_RH) * Cfg<T, L + kMinLogn>::LDS_RH,
-                                            (RH / Cfg<T, L + kMinLogn>::NT_RHF) * Cfg<T, L + kMinLogn>::LDS_RHF)
-                      : which == 1 ? (C / Cfg<T, L + kMinLogn>::NT_C) * Cfg<T, L + kMinLogn>::LDS_C
-                      : which == 3 ? (C / (Cfg<T, L + kMinLogn>::DUAL_C ? Cfg<T, L + kMinLogn>::NT_CD
-                                                                        : Cfg<T, L + kMinLogn>::NT_C)) *
-                                         Cfg<T, L + kMinLogn>::LDS_C
-                                   : (RC / Cfg<T, L + kMinLogn>::NT_RC) * Cfg<T, L + kMinLogn>::LDS_RC)), ...);
+    ((m = std::max(m, which == 0 ? std::max((RH / Cfg<T, L + kMinLogn, B>::NT_RH) * Cfg<T, L + kMinLogn, B>::LDS_RH,
+                                            (RH / Cfg<T, L + kMinLogn, B>::NT_RHF) * Cfg<T, L + kMinLogn, B>::LDS_RHF)
+                      : which == 1 ? (C / Cfg<T, L + kMinLogn, B>::NT_C) * Cfg<T, L + kMinLogn, B>::LDS_C
+                      : which == 3 ? (C / (Cfg<T, L + kMinLogn, B>::DUAL_C ? Cfg<T, L + kMinLogn, B>::NT_CD
+                                                                        : Cfg<T, L + kMinLogn, B>::NT_C)) *
+                                         Cfg<T, L + kMinLogn, B>::LDS_C
+                                   : (RC / Cfg<T, L + kMinLogn, B>::NT_RC) * Cfg<T, L + kMinLogn, B>::LDS_RC)), ...);
     return m;
   }
   static constexpr int LDS_RH = max_lds(0, Seq{});
@@ -195,9 +196,11 @@ struct KindOf {
   static constexpr bool CPLX_COLS = K == kColsCplx;
   static constexpr bool REAL_COLS = K == kColsReal || K == kColsGen;
   // block size, LDS elements and waves of the several-size kernel
-  static constexpr int BLK = ROWS_R ? Blk<T>::RH : ROWS_C ? Blk<T>::RC : Blk<T>::C;
-  static constexpr int LDS = ROWS_R ? Blk<T>::LDS_RH : ROWS_C ? Blk<T>::LDS_RC : REAL_COLS ? Blk<T>::LDS_CR : Blk<T>::LDS_C;
-  static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : REAL_COLS ? Blk<T>::WAVES_CR : Blk<T>::WAVES_C;
+  static constexpr int BLK = ROWS_R ? Blk<T, B>::RH : ROWS_C ? Blk<T, B>::RC : Blk<T, B>::C;
+  static constexpr int LDS = ROWS_R ? Blk<T, B>::LDS_RH
+                             : ROWS_C ? Blk<T, B>::LDS_RC
+                             : REAL_COLS ? Blk<T, B>::LDS_CR : Blk<T, B>::LDS_C;
+  static constexpr int WAVES = (ROWS_R || ROWS_C) ? 1 : REAL_COLS ? Blk<T, B>::WAVES_CR : Blk<T, B>::WAVES_C;
   // tiles of this kind hold both lines in every thread (Cfg::DUAL_C)
   template <int LOGN>
   static constexpr bool dual() {

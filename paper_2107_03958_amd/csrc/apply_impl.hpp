@@ -1237,18 +1237,18 @@ __global__ __launch_bounds__((Single<T, K, LOGN>::BLOCK), (Single<T, K, LOGN>::W
 // Launches over several segments of any sizes: one block size for all.  (A
 // persistent form, each block looping over logical blocks, made the compiler
 // keep values across iterations: 700-1100 spilled registers in the column and
-// complex-row kernels.)
-template <typename T, int K>
-__global__ __launch_bounds__((KindOf<T, K>::BLK), (KindOf<T, K>::WAVES)) void k_pass(Segs<T> tab) {
+// complex-row kernels.)  B: the period every segment of the launch has.
+template <typename T, int K, int B = 2>
+__global__ __launch_bounds__((KindOf<T, K, B>::BLK), (KindOf<T, K, B>::WAVES)) void k_pass(Segs<T> tab) {
   if (tab.skip && *tab.skip) return;
-  __shared__ cx<T> lds[KindOf<T, K>::LDS];
+  __shared__ cx<T> lds[KindOf<T, K, B>::LDS];
   const int si = find_seg(tab, blockIdx.x);
   const Seg<T>& sg = tab.s[si];
   const int blk = blockIdx.x - sg.block0;
   switch (sg.logn) {
-#define WS_CASE(L)                                         \
-  case L:                                                  \
-    run_group<T, L, K, KindOf<T, K>::BLK>(sg, blk, lds);   \
+#define WS_CASE(L)                                               \
+  case L:                                                        \
+    run_group<T, L, K, KindOf<T, K, B>::BLK, B>(sg, blk, lds);   \
     break;
     WS_FOR_EACH_LOGN(WS_CASE)
 #undef WS_CASE
@@ -1331,13 +1331,13 @@ Seg<T> make_seg(const Plan& p, int batch, const void* src, void* dst, cx<T>* wor
   s.alpha = (T)1;
   const Geo g = geo<T, K>(p.logn, p.b);
   s.ntiles = batch * g.tiles_per_density;
-  const int tpb = (multi ? KindOf<T, K>::BLK : g.block_single) / g.nt;
+  const int tpb = (multi ? (p.b == 3 ? KindOf<T, K, 3>::BLK : KindOf<T, K>::BLK) : g.block_single) / g.nt;
   s.nblocks = (s.ntiles + tpb - 1) / tpb;
   return s;
 }
 
-// Launch pass kind K over tab.count segments (block offsets filled in here).
-template <typename T, int K>
+// Launch pass kind K over tab.count segments of period B (block offsets filled in here).
+template <typename T, int K, int B = 2>
 hipError_t launch_segs(Segs<T>& tab, hipStream_t st) {
   long total = 0;
   for (int i = 0; i < tab.count; ++i) {
@@ -1346,7 +1346,7 @@ hipError_t launch_segs(Segs<T>& tab, hipStream_t st) {
   }
   if (total == 0) return hipSuccess;
   if (total > 0x7fffffffL) return hipErrorInvalidValue;
-  k_pass<T, K><<<(unsigned)total, KindOf<T, K>::BLK, 0, st>>>(tab);
+  k_pass<T, K, B><<<(unsigned)total, KindOf<T, K, B>::BLK, 0, st>>>(tab);
   return hipGetLastError();
 }
 
@@ -1470,10 +1470,10 @@ template <typename T>
 hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipStream_t s) {
   std::vector<int> done(count, 0);
   for (;;) {
-    std::vector<Seg<T>> seg[3];
+    std::vector<Seg<T>> seg[2][3];    // [period 2 or 3][pass]
     for (int i = 0; i < count; ++i) {
       const Plan& p = *items[i].plan;
-      if (p.logn < kMinLogn || p.logn > kMaxLogn || p.b != 2) return hipErrorInvalidValue;
+      if (p.logn < kMinLogn || p.logn > kMaxLogn || (p.b != 2 && p.b != 3)) return hipErrorInvalidValue;
       const int left = items[i].batch - done[i];
       if (left <= 0) continue;
       const int nb = std::min(left, apply_chunk(p));
@@ -1481,31 +1481,44 @@ hipError_t launch_apply_multi(const ApplyItem* items, int count, bool cplx, hipS
       const auto* in = static_cast<const char*>(items[i].in) + off;
       auto* out = static_cast<char*>(items[i].out) + off;
       auto* w = static_cast<cx<T>*>(items[i].work);
+      auto& sp = seg[p.b == 3 ? 1 : 0];
       if (cplx) {
-        seg[0].push_back(make_seg<T, kRowsFwdCplx>(p, nb, in, nullptr, w, true));
-        seg[1].push_back(make_seg<T, kColsCplx>(p, nb, nullptr, nullptr, w, true));
-        seg[2].push_back(make_seg<T, kRowsInvCplx>(p, nb, in, out, w, true));
+        sp[0].push_back(make_seg<T, kRowsFwdCplx>(p, nb, in, nullptr, w, true));
+        sp[1].push_back(make_seg<T, kColsCplx>(p, nb, nullptr, nullptr, w, true));
+        sp[2].push_back(make_seg<T, kRowsInvCplx>(p, nb, in, out, w, true));
       } else {
-        seg[0].push_back(make_seg<T, kRowsFwdReal>(p, nb, in, nullptr, w, true));
-        seg[1].push_back(make_seg<T, kColsReal>(p, nb, nullptr, nullptr, w, true));
-        seg[2].push_back(make_seg<T, kRowsInvReal>(p, nb, nullptr, out, w, true));
+        sp[0].push_back(make_seg<T, kRowsFwdReal>(p, nb, in, nullptr, w, true));
+        sp[1].push_back(make_seg<T, kColsReal>(p, nb, nullptr, nullptr, w, true));
+        sp[2].push_back(make_seg<T, kRowsInvReal>(p, nb, nullptr, out, w, true));
       }
       done[i] += nb;
     }
-    if (seg[0].empty()) return hipSuccess;
+    if (seg[0][0].empty() && seg[1][0].empty()) return hipSuccess;
+    // each period's segments share launches among themselves
     for (int pass = 0; pass < 3; ++pass) {
-      for (size_t g0 = 0; g0 < seg[pass].size(); g0 += kMaxSegs) {
-        Segs<T> tab{};
-        tab.count = (int)std::min<size_t>(kMaxSegs, seg[pass].size() - g0);
-        for (int k = 0; k < tab.count; ++k) tab.s[k] = seg[pass][g0 + k];
-        hipError_t e;
-        if (cplx)
-          e = pass == 0 ? launch_segs<T, kRowsFwdCplx>(tab, s)
-              : pass == 1 ? launch_segs<T, kColsCplx>(tab, s) : launch_segs<T, kRowsInvCplx>(tab, s);
-        else
-          e = pass == 0 ? launch_segs<T, kRowsFwdReal>(tab, s)
-              : pass == 1 ? launch_segs<T, kColsReal>(tab, s) : launch_segs<T, kRowsInvReal>(tab, s);
-        if (e != hipSuccess) return e;
+      for (int pi = 0; pi < 2; ++pi) {
+        for (size_t g0 = 0; g0 < seg[pi][pass].size(); g0 += kMaxSegs) {
+          Segs<T> tab{};
+          tab.count = (int)std::min<size_t>(kMaxSegs, seg[pi][pass].size() - g0);
+          for (int k = 0; k < tab.count; ++k) tab.s[k] = seg[pi][pass][g0 + k];
+          hipError_t e;
+          if (pi == 0) {
+            if (cplx)
+              e = pass == 0 ? launch_segs<T, kRowsFwdCplx>(tab, s)
+                  : pass == 1 ? launch_segs<T, kColsCplx>(tab, s) : launch_segs<T, kRowsInvCplx>(tab, s);
+            else
+              e = pass == 0 ? launch_segs<T, kRowsFwdReal>(tab, s)
+                  : pass == 1 ? launch_segs<T, kColsReal>(tab, s) : launch_segs<T, kRowsInvReal>(tab, s);
+          } else {
+            if (cplx)
+              e = pass == 0 ? launch_segs<T, kRowsFwdCplx, 3>(tab, s)
+                  : pass == 1 ? launch_segs<T, kColsCplx, 3>(tab, s) : launch_segs<T, kRowsInvCplx, 3>(tab, s);
+            else
+              e = pass == 0 ? launch_segs<T, kRowsFwdReal, 3>(tab, s)
+                  : pass == 1 ? launch_segs<T, kColsReal, 3>(tab, s) : launch_segs<T, kRowsInvReal, 3>(tab, s);
+          }
+          if (e != hipSuccess) return e;
+        }
       }
     }
   }

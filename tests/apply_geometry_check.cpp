@@ -181,6 +181,10 @@ void check_single_b3(int batch) {
   CHECK(S::BLOCK % S::NT == 0 && S::TPB * S::NT == S::BLOCK && S::BLOCK <= 1024 && S::BLOCK >= WS_MIN_BLOCK);
   CHECK(S::LDS * (int)sizeof(cx<T>) <= 163840);
   CHECK(!C::SPLIT_C || (sizeof(T) == 8 && LOGN == 11));   // split exchange: FP64 at n = 2048 only
+  // the several-size kernel of period 3: whole tiles per block, their LDS within the block's
+  CHECK(KO::BLK % S::NT == 0 && KO::BLK <= 1024);
+  CHECK((KO::BLK / S::NT) * KO::template lds_tile<LOGN>() <= KO::LDS);
+  CHECK(KO::LDS * (int)sizeof(cx<T>) <= 163840);
   const int ntiles = batch * KO::template tiles_per_density<LOGN>();
   const int nblocks = (ntiles + S::TPB - 1) / S::TPB;
   constexpr int G = KO::template line_group<LOGN>();

@@ -15,7 +15,7 @@ import pytest
 import synth
 from oracle import ls as ols
 from oracle import metrics, moments, scheme
-from tests.gpu_common import oracle_kernel, plan_kwargs
+from tests.gpu_common import oracle_kernel, oracle_table, plan_kwargs
 
 pytestmark = pytest.mark.gpu
 
@@ -172,6 +172,44 @@ def test_b3_ls_solve_mixed_vs_dense(api, n):
     assert np.linalg.norm(res) / np.linalg.norm(ui) <= 1e-11
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_b3_apply_multi(api, precision):
+    # plans of periods 2 and 3 and several sizes in one call: each period's items share launches;
+    # every result agrees with its own single-plan apply to rounding and with the oracle
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    specs = [(3, "log", 64, 2), (2, "log", 64, 1), (3, "pow-1/2", 16, 3), (3, "log", 256, 1), (2, "pow-1/2", 32, 2),
+             (3, "log", 32, 2)]
+    plans = [api.ConvPlan(n=n, b=b, precision=precision, **plan_kwargs(k)) for b, k, n, _ in specs]
+    hosts = [_densities(n, c) for _, _, n, c in specs]
+    dens = [_gpu(h, dt) for h in hosts]
+    outs = api.apply_multi(plans, dens)
+    same = 1e-14 if precision == "fp64" else 2e-6
+    for (b, k, n, c), p, d, o, h in zip(specs, plans, dens, outs, hosts):
+        got = o.cpu().numpy().astype(np.float64)
+        assert metrics.rel_linf(got, p.apply(d).cpu().numpy().astype(np.float64)) <= same, (b, k, n)
+        table = table3(k, n) if b == 3 else oracle_table(k, n)
+        for j in range(c):
+            ref = np.real(scheme.apply(h[j], table, b))
+            if precision == "fp64":
+                assert metrics.rel_linf(got[j], ref) <= FP64_TOL, (b, k, n, j)
+            else:
+                assert metrics.rel_linf(got[j], ref) <= 2e-6 and metrics.rel_l2(got[j], ref) <= 5e-7, (b, k, n, j)
+
+
+def test_b3_apply_multi_complex(api):
+    specs = [(3, 64, 1), (2, 64, 1), (3, 16, 2), (3, 128, 1)]
+    plans = [api.ConvPlan(n=n, b=b, **plan_kwargs("helm20")) for b, n, _ in specs]
+    rng = np.random.default_rng(78)
+    hosts = [_densities(n, c) * (1.0 + 0.5j + 0.1 * rng.normal(size=(c, n, n))) for _, n, c in specs]
+    dens = [_gpu(h, torch.complex128) for h in hosts]
+    outs = api.apply_multi(plans, dens)
+    for (b, n, c), p, d, o, h in zip(specs, plans, dens, outs, hosts):
+        assert metrics.rel_linf(o.cpu().numpy(), p.apply(d).cpu().numpy()) <= 1e-14, (b, n)
+        table = table3("helm20", n) if b == 3 else oracle_table("helm20", n)
+        for j in range(c):
+            assert metrics.rel_linf(o[j].cpu().numpy(), scheme.apply(h[j], table, b)) <= FP64_TOL, (b, n, j)
+
+
 @functools.lru_cache(maxsize=4)
 def _b3_ls_oracle(n, kappa):
     x1, x2 = synth.grid(n)
@@ -205,11 +243,7 @@ def test_b3_ls_solve_n128(api, mixed):
 def test_b3_unsupported_uses(api):
     from paper_2107_03958_amd import _lib as L
     p3 = api.ConvPlan(n=64, b=B3, **plan_kwargs("log"))
-    p2 = api.ConvPlan(n=64, **plan_kwargs("log"))
     u = _gpu(_densities(64, 1), torch.float64)
-    with pytest.raises(L.WsError) as e:
-        api.apply_multi([p2, p3], [u, u.clone()])
-    assert e.value.code == L.WS_EUNSUPPORTED
     with pytest.raises(L.WsError) as e:
         p3.apply(u, fs=[api.FsDesc("disc", 0.5, 0.5, 0.2, 0.2, 0.39)])
     assert e.value.code == L.WS_EUNSUPPORTED
