@@ -186,8 +186,8 @@ def run_eval_bench(api, torch, n, count, repeats=10):
     """conv_eval: (A_n u)(x) at `count` scattered targets, one density, log|x| kernel, FP64.
 
     The series sum costs (nb)^2 complex multiply-adds (8 flops) per target, most of them in a
-    complex matrix product on the FP64 matrix cores; the roofline puts that rate against the FP64
-    dense matrix peak."""
+    complex matrix product on the FP64 matrix cores (taken as three real products, 6 of those 8
+    flops); the roofline puts the 8-flop rate against the FP64 dense matrix peak."""
     import synth
     plan = api.ConvPlan("log", n=n)
     u = torch.as_tensor(synth.smooth_density(n, synth.SEED_PRECISION)).cuda()

@@ -295,10 +295,11 @@ int ls_solve_fs(ws_plan_t plan, const void* contrast_tilde, const ws_fs_desc* fs
                 ws_ls_info* info, void* stream);
 
 /* Device scratch for conv_eval: the spectrum of one density (nb x nb
- * complex128), the row-pass intermediate (n x nb complex128), two nb x T
- * complex128 matrices for a tile of T targets (T = 64 .. 4096, 64 MiB each at
- * most) and, for real-kernel plans, the density widened to complex.
- * WS_EUNSUPPORTED for WS_FP32 plans. */
+ * complex128) and its three real planes (3 nb x nb float64), the row-pass
+ * intermediate (n x nb complex128), two groups of three nb x T float64 planes
+ * for a tile of T targets (T = 64 .. 4096, 96 MiB per group at most) and, for
+ * real-kernel plans, the density widened to complex.  WS_EUNSUPPORTED for
+ * WS_FP32 plans. */
 int conv_eval_query(ws_plan_t plan, size_t* work_bytes);
 
 /* (A_n u)(x) at `count` arbitrary points x of the plane (Section 2.1: the
@@ -313,7 +314,8 @@ int conv_eval_query(ws_plan_t plan, size_t* work_bytes);
  *  work:    conv_eval_query bytes, 256-byte aligned.
  * Cost: one forward transform of the density, then |F_n| = (nb)^2 complex
  * multiply-adds per target (for modest target counts), the sum over k2 as a
- * complex matrix product per tile of targets (rocBLAS ZGEMM; the library
+ * complex matrix product per tile of targets (three real products, rocBLAS
+ * DGEMM, in the three-multiplication form; the library
  * keeps one rocBLAS handle per device, made on the first call there, which
  * may allocate rocBLAS's own device workspace). */
 int conv_eval(ws_plan_t plan, const void* density, int count, const double* targets, void* out,

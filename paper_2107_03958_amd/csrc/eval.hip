@@ -6,9 +6,12 @@
 // at each target: O(|F_n|) per target, for callers with modest numbers of
 // scattered points.  The sum over k2 is a dense complex matrix product,
 //     P(k1, t) = sum_{k2} c(k1, k2) exp(2 pi i k2 x2_t / b),
-// taken by rocBLAS (ZGEMM, FP64 matrix cores) over tiles of targets; a kernel
-// forms the exponential matrix, another the final sum over k1 with
-// exp(2 pi i k1 x1_t / b).  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
+// over tiles of targets, taken as three real products on the FP64 matrix
+// cores (rocBLAS DGEMM; the three-multiplication form of a complex product:
+// with C = Cr + i Ci and E = Er + i Ei, P = Cr Er - Ci Ei + i ((Cr + Ci)(Er +
+// Ei) - Cr Er - Ci Ei), 6 instead of 8 real flops per complex multiply-add);
+// kernels split the spectrum into those planes, form the exponential planes,
+// and take the final sum over k1 with exp(2 pi i k1 x1_t / b).  F_n = [-nb/2, nb/2)^2 is not symmetric, so the
 // value is complex even for real u and a real kernel, except on the grid.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
@@ -27,7 +30,7 @@ namespace ws {
 namespace {
 
 constexpr int kEvalThreads = 256;
-constexpr size_t kTileBytes = 64u << 20;   // each of the two target-tile buffers
+constexpr size_t kTileBytes = 96u << 20;   // each of the two target-tile buffers (three planes each)
 
 __global__ void k_real_to_cplx(const double* __restrict__ u, cx<double>* __restrict__ v, size_t count) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
@@ -42,29 +45,50 @@ __device__ __forceinline__ cx<double> expo(int q, int nb, double x_over_b) {
   return {c, s};
 }
 
-// E[t nb + q] = exp(2 pi i k(q) x2_t / b) for the tc targets from t0 (column t
-// of a column-major nb x tc matrix).
-__global__ __launch_bounds__(kEvalThreads) void k_eval_e2(const double* __restrict__ targets, int t0, int tc, int nb,
-                                                          double inv_b, cx<double>* __restrict__ E) {
-  const size_t total = (size_t)tc * nb;
+// The spectrum's real planes: Cr, Ci and Cr + Ci (row-major, as the spectrum).
+__global__ __launch_bounds__(kEvalThreads) void k_eval_split(const cx<double>* __restrict__ spec, size_t total,
+                                                             double* __restrict__ cr, double* __restrict__ ci,
+                                                             double* __restrict__ cs) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int t = (int)(i / nb), q = (int)(i % nb);
-    E[i] = expo(q, nb, targets[2 * (size_t)(t0 + t) + 1] * inv_b);
+    const cx<double> v = spec[i];
+    cr[i] = v.x;
+    ci[i] = v.y;
+    cs[i] = v.x + v.y;
   }
 }
 
-// out[t0 + t] = sum_q exp(2 pi i k(q) x1_t / b) P[t nb + q]: one block per
-// target, the block's partial sums added in a fixed order.
-__global__ __launch_bounds__(kEvalThreads) void k_eval_dot(const cx<double>* __restrict__ P, int nb, double inv_b,
-                                                           const double* __restrict__ targets, int t0,
+// The exponential planes for the tc targets from t0: E = exp(2 pi i k(q)
+// x2_t / b) at [t nb + q] (column t of a column-major nb x tc matrix), as Er,
+// Ei and Er + Ei, plane after plane (stride plane).
+__global__ __launch_bounds__(kEvalThreads) void k_eval_e2(const double* __restrict__ targets, int t0, int tc, int nb,
+                                                          double inv_b, double* __restrict__ E, size_t plane) {
+  const size_t total = (size_t)tc * nb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(i / nb), q = (int)(i % nb);
+    const cx<double> e = expo(q, nb, targets[2 * (size_t)(t0 + t) + 1] * inv_b);
+    E[i] = e.x;
+    E[plane + i] = e.y;
+    E[2 * plane + i] = e.x + e.y;
+  }
+}
+
+// out[t0 + t] = sum_q exp(2 pi i k(q) x1_t / b) P(q, t), with P rebuilt from
+// the three real products P1 = Cr Er, P2 = Ci Ei, P3 = (Cr + Ci)(Er + Ei):
+// P = (P1 - P2) + i (P3 - P1 - P2).  One block per target, the block's
+// partial sums added in a fixed order.
+__global__ __launch_bounds__(kEvalThreads) void k_eval_dot(const double* __restrict__ P, size_t plane, int nb,
+                                                           double inv_b, const double* __restrict__ targets, int t0,
                                                            cx<double>* __restrict__ out) {
   __shared__ cx<double> red[kEvalThreads / 64];
   const int t = blockIdx.x;
   const double x1 = targets[2 * (size_t)(t0 + t)] * inv_b;
-  const cx<double>* col = P + (size_t)t * nb;
+  const double* p1 = P + (size_t)t * nb;
+  const double* p2 = p1 + plane;
+  const double* p3 = p2 + plane;
   double re = 0.0, im = 0.0;
   for (int q = threadIdx.x; q < nb; q += kEvalThreads) {
-    const cx<double> v = cmul(expo(q, nb, x1), col[q]);
+    const double a = p1[q], bb = p2[q];
+    const cx<double> v = cmul(expo(q, nb, x1), cx<double>{a - bb, p3[q] - a - bb});
     re += v.x;
     im += v.y;
   }
@@ -75,16 +99,16 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dot(const cx<double>* __r
   if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = {re, im};
   __syncthreads();
   if (threadIdx.x == 0) {
-    cx<double> s = red[0];
-    for (int w = 1; w < kEvalThreads / 64; ++w) s = s + red[w];
-    out[t0 + t] = s;
+    cx<double> sum = red[0];
+    for (int w = 1; w < kEvalThreads / 64; ++w) sum = sum + red[w];
+    out[t0 + t] = sum;
   }
 }
 
-// Targets per tile: as many as fit kTileBytes in an nb x tile complex matrix
+// Targets per tile: as many as fit kTileBytes in three nb x tile real planes
 // (at most 4096, a multiple of 64, at least 64).
 int eval_tile(int nb) {
-  int t = (int)std::min<size_t>(4096, kTileBytes / (sizeof(cx<double>) * (size_t)nb));
+  int t = (int)std::min<size_t>(4096, kTileBytes / (3 * sizeof(double) * (size_t)nb));
   t -= t % 64;
   return std::max(t, 64);
 }
@@ -109,7 +133,7 @@ rocblas_handle blas_handle(int dev, rocblas_status* st) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct EvalWork {
-  size_t widen, inter, spec, tile, total;   // tile: bytes of each of the two target-tile matrices
+  size_t widen, inter, spec, planes, tile, total;   // planes: Cr, Ci, Cr + Ci; tile: three nb x T planes
 };
 
 EvalWork eval_work(const Plan& p) {
@@ -118,8 +142,9 @@ EvalWork eval_work(const Plan& p) {
   w.widen = p.cplx ? 0 : align256(n * n * sizeof(cx<double>));
   w.inter = align256(inter_elems<double>((int)n, (int)nb) * sizeof(cx<double>));
   w.spec = align256(nb * nb * sizeof(cx<double>));
-  w.tile = align256(nb * (size_t)eval_tile((int)nb) * sizeof(cx<double>));
-  w.total = w.widen + w.inter + w.spec + 2 * w.tile;
+  w.planes = align256(nb * nb * sizeof(double));
+  w.tile = align256(3 * nb * (size_t)eval_tile((int)nb) * sizeof(double));
+  w.total = w.widen + w.inter + w.spec + 3 * w.planes + 2 * w.tile;
   return w;
 }
 
@@ -170,20 +195,30 @@ int conv_eval(ws_plan_t plan, const void* density, int count, const double* targ
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = ws::launch_spectrum(p, v, inter, spec, s);
   if (e == hipSuccess) {
-    // P(:, t) = C E(:, t) over tiles of targets: C is the row-major spectrum,
-    // i.e. the transpose of the column-major matrix rocBLAS sees
-    ws::cx<double>* E = reinterpret_cast<ws::cx<double>*>(base + w.widen + w.inter + w.spec);
-    ws::cx<double>* P = reinterpret_cast<ws::cx<double>*>(base + w.widen + w.inter + w.spec + w.tile);
+    // the spectrum's planes, then per tile of targets the exponential planes,
+    // three real products (the row-major planes are, to rocBLAS's
+    // column-major view, transposed: hence transA) and the final sum
+    char* pl = base + w.widen + w.inter + w.spec;
+    double* cr = reinterpret_cast<double*>(pl);
+    double* ci = reinterpret_cast<double*>(pl + w.planes);
+    double* cs = reinterpret_cast<double*>(pl + 2 * w.planes);
+    double* E = reinterpret_cast<double*>(pl + 3 * w.planes);
+    double* P = reinterpret_cast<double*>(pl + 3 * w.planes + w.tile);
     ws::cx<double>* res = static_cast<ws::cx<double>*>(out);
     const int nb = p.nb, tile = ws::eval_tile(nb);
+    const size_t plane = (size_t)nb * tile;                   // elements per tile plane
     const double inv_b = 1.0 / p.b;
+    const size_t nn = (size_t)nb * nb;
+    ws::k_eval_split<<<(unsigned)std::min<size_t>((nn + 255) / 256, 8192), ws::kEvalThreads, 0, s>>>(spec, nn, cr,
+                                                                                                     ci, cs);
+    e = hipGetLastError();
     int dev = 0;
-    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
     for (int t0 = 0; e == hipSuccess && t0 < count; t0 += tile) {
       const int tc = std::min(tile, count - t0);
       const size_t elems = (size_t)tc * nb;
       ws::k_eval_e2<<<(unsigned)std::min<size_t>((elems + 255) / 256, 8192), ws::kEvalThreads, 0, s>>>(
-          targets, t0, tc, nb, inv_b, E);
+          targets, t0, tc, nb, inv_b, E, plane);
       e = hipGetLastError();
       if (e != hipSuccess) break;
       {
@@ -191,16 +226,15 @@ int conv_eval(ws_plan_t plan, const void* density, int count, const double* targ
         rocblas_status bs;
         rocblas_handle h = ws::blas_handle(dev, &bs);
         if (bs == rocblas_status_success) bs = rocblas_set_stream(h, s);
-        const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
-        if (bs == rocblas_status_success)
-          bs = rocblas_zgemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, tc, nb, &one,
-                             reinterpret_cast<const rocblas_double_complex*>(spec), nb,
-                             reinterpret_cast<const rocblas_double_complex*>(E), nb, &zero,
-                             reinterpret_cast<rocblas_double_complex*>(P), nb);
+        const double one = 1.0, zero = 0.0;
+        const double* cpl[3] = {cr, ci, cs};
+        for (int k = 0; k < 3 && bs == rocblas_status_success; ++k)
+          bs = rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, tc, nb, &one, cpl[k], nb,
+                             E + k * plane, nb, &zero, P + k * plane, nb);
         if (bs != rocblas_status_success)
           return ws::set_last_error(WS_EDEVICE, std::string("conv_eval: rocBLAS: ") + rocblas_status_to_string(bs));
       }
-      ws::k_eval_dot<<<tc, ws::kEvalThreads, 0, s>>>(P, nb, inv_b, targets, t0, res);
+      ws::k_eval_dot<<<tc, ws::kEvalThreads, 0, s>>>(P, plane, nb, inv_b, targets, t0, res);
       e = hipGetLastError();
     }
   }
