@@ -86,6 +86,28 @@ def test_ls_solve_n512_kappa80(api, mode):
     _check_solve(api, 512, 80.0, mode)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("mode", ["fp64", "fp32+ir"])
+def test_ls_solve_n1024_kappa80_residual(api, mode):
+    # the largest LS case of the benchmark: the GPU solution's residual recomputed with the
+    # oracle's operator (one oracle matvec) meets the requested tolerance, so the solution is
+    # within cond_2(K) times it of the discrete system's exact solution
+    n, kappa = 1024, 80.0
+    mixed = mode == "fp32+ir"
+    print(f"ls case n={n} kappa={kappa} {mode}", flush=True)
+    g = moments.ghat_table(moments.Kernel("helmholtz", 1.0, 0.0, kappa), n, B, A_DEFAULT)
+    m = synth.contrast(n)
+    ui = synth.plane_wave(n, kappa, synth.plane_wave_angle(synth.SEED_LS_ANGLE + int(kappa)))
+    plan = api.ConvPlan("helmholtz", n=n, kappa=kappa, precision="fp32" if mixed else "fp64")
+    u, info = plan.ls_solve(_gpu(m, torch.float64), _gpu(ui, torch.complex128), tol=1e-10, restart=50,
+                            mixed=mixed)
+    assert info.status == 0, info
+    got = u.cpu().numpy()
+    res = np.linalg.norm(ui - ols.matvec(got, m, g, B, kappa)) / np.linalg.norm(ui)
+    assert res <= 1.2e-10, (res, info)
+    assert abs(res - info.rel_residual) <= 1e-14 + 0.05 * res, (res, info.rel_residual)
+
+
 @pytest.mark.parametrize("n", [16, 32])
 @pytest.mark.parametrize("kappa", [20.0, 40.0])
 def test_ls_solve_fp64_vs_dense_tight(api, n, kappa):
